@@ -1,0 +1,288 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle.
+
+Each test checks the oracle against mathematics that fixes the result:
+the DFT special case when omega lies on the Cartesian frequency grid,
+Parseval, the adjoint identity, single-pixel plane waves, central finite
+differences of the loss, and an independent automatic-differentiation route
+through a dense matrix built with torch.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ndft, nufft_ref, points_ref
+from paper_2111_02912_amd import workloads as W
+
+
+def _rand_c(shape, seed):
+    return W.complex_normal(shape, seed).astype(np.complex128)
+
+
+def _inner(a, b):
+    return np.vdot(np.ravel(b), np.ravel(a))  # <a, b> = b^H a
+
+
+@pytest.mark.parametrize("N", [(9,), (8, 7), (6, 5, 4)])
+def test_adjoint_identity(N):
+    D = len(N)
+    om = W.uniform_random(37, D, seed=11)
+    x = _rand_c(N, 1)
+    y = _rand_c((37,), 2)
+    lhs = _inner(ndft.forward(om, x, N), y)
+    rhs = _inner(x, ndft.adjoint(om, y, N))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("N", [(8,), (9,), (8, 6), (5, 7), (4, 5, 6)])
+def test_on_grid_equals_fft(N):
+    """omega_k = 2 pi k / N gives exp(2 pi i k.floor(N/2)/N) FFT_N(x)[k mod N]."""
+    D = len(N)
+    ks = np.meshgrid(*[np.arange(-(n // 2), n - n // 2) for n in N], indexing="ij")
+    ks = np.stack([k.ravel() for k in ks], axis=-1)
+    om = (2.0 * np.pi * ks / np.array(N)[None, :])
+    x = _rand_c(N, 3)
+    y = ndft.forward(om, x, N)
+    F = np.fft.fftn(x)
+    idx = tuple((ks[:, d] % N[d]) for d in range(D))
+    phase = np.exp(2j * np.pi * np.sum(ks * (np.array(N) // 2)[None, :] / np.array(N)[None, :], axis=1))
+    expect = phase * F[idx]
+    assert np.max(np.abs(y - expect)) <= 1e-12 * np.max(np.abs(expect))
+    # Parseval on the full grid: ||A x||^2 = prod(N) ||x||^2
+    assert abs(np.sum(np.abs(y) ** 2) - np.prod(N) * np.sum(np.abs(x) ** 2)) <= 1e-12 * np.sum(np.abs(y) ** 2)
+
+
+def test_single_pixel_plane_wave():
+    N = (6, 7)
+    om = W.uniform_random(20, 2, seed=5)
+    j0 = (4, 1)
+    x = np.zeros(N, dtype=np.complex128)
+    x[j0] = 1.0
+    y = ndft.forward(om, x, N)
+    r = np.array([j0[0] - N[0] // 2, j0[1] - N[1] // 2], dtype=np.float64)
+    expect = np.exp(-1j * (om.astype(np.float64) @ r))
+    assert np.max(np.abs(y - expect)) <= 1e-14
+    # the omega-derivative of a single plane wave is -i r_d times it
+    g = _rand_c((1, 1, 20), 6)
+    dom = ndft.jac_omega_fwd(om, x[None], g, N)
+    for d in range(2):
+        expect_d = np.real(np.conj(-1j * r[d] * expect) * g[0, 0])
+        assert np.max(np.abs(dom[:, d] - expect_d)) <= 1e-13
+
+
+def test_row_and_pixel_subsets():
+    N = (6, 5)
+    om = W.uniform_random(23, 2, seed=7)
+    x = _rand_c((3,) + N, 8)
+    rows = np.array([22, 0, 5, 5, 17])
+    full = ndft.forward(om, x, N)
+    assert np.array_equal(ndft.forward(om, x, N, rows=rows), full[:, rows])
+    y = _rand_c((2, 23), 9)
+    pix = np.array([0, 29, 7, 13])
+    fa = ndft.adjoint(om, y, N).reshape(2, -1)
+    assert np.array_equal(ndft.adjoint(om, y, N, pix=pix), fa[:, pix])
+
+
+def _loss_fwd(om, x, smaps, yobs, N):
+    y = ndft.sense_forward(om, x, N, smaps)
+    return float(np.sum(np.abs(y - yobs) ** 2))
+
+
+@pytest.mark.parametrize("N,C", [((5,), 1), ((6, 5), 2), ((4, 3, 5), 1)])
+def test_jac_omega_fwd_finite_difference(N, C):
+    D = len(N)
+    M = 9
+    om = W.uniform_random(M, D, seed=21).astype(np.float64)
+    x = _rand_c((2,) + N, 22)
+    smaps = _rand_c((C,) + N, 23) if C > 1 else None
+    yobs = _rand_c((2, C, M), 24)
+    g = 2.0 * (ndft.sense_forward(om, x, N, smaps) - yobs)
+    grad = ndft.jac_omega_fwd(om, x, g, N, smaps)
+    h = 1e-6
+    fd = np.zeros_like(grad)
+    for m in range(M):
+        for d in range(D):
+            p = om.copy(); p[m, d] += h
+            q = om.copy(); q[m, d] -= h
+            fd[m, d] = (_loss_fwd(p, x, smaps, yobs, N) - _loss_fwd(q, x, smaps, yobs, N)) / (2 * h)
+    assert np.max(np.abs(fd - grad)) <= 1e-6 * np.max(np.abs(grad))
+
+
+@pytest.mark.parametrize("N,C", [((7,), 1), ((5, 6), 3)])
+def test_jac_omega_adj_finite_difference(N, C):
+    D = len(N)
+    M = 8
+    om = W.uniform_random(M, D, seed=31).astype(np.float64)
+    y = _rand_c((2, C, M), 32)
+    smaps = _rand_c((C,) + N, 33) if C > 1 else None
+    t = _rand_c((2,) + N, 34)
+
+    def loss(o):
+        return float(np.sum(np.abs(ndft.sense_adjoint(o, y, N, smaps) - t) ** 2))
+
+    g = 2.0 * (ndft.sense_adjoint(om, y, N, smaps) - t)
+    grad = ndft.jac_omega_adj(om, y, g, N, smaps)
+    h = 1e-6
+    fd = np.zeros_like(grad)
+    for m in range(M):
+        for d in range(D):
+            p = om.copy(); p[m, d] += h
+            q = om.copy(); q[m, d] -= h
+            fd[m, d] = (loss(p) - loss(q)) / (2 * h)
+    assert np.max(np.abs(fd - grad)) <= 1e-6 * np.max(np.abs(grad))
+
+
+def _dense_torch(om, N):
+    """Dense NDFT matrix built in torch FP64 from the definition, for autograd."""
+    grids = torch.meshgrid(*[torch.arange(n, dtype=torch.float64) - n // 2 for n in N], indexing="ij")
+    r = torch.stack([g.reshape(-1) for g in grids], dim=-1)  # [Ntot, D]
+    return torch.exp(-1j * (om @ r.T))
+
+
+@pytest.mark.parametrize("N", [(6, 4), (3, 4, 2)])
+def test_gradients_match_torch_autograd(N):
+    """Independent route: torch autograd through exp(-i omega r^T)."""
+    D = len(N)
+    M, B, C = 7, 2, 3
+    om_np = W.uniform_random(M, D, seed=41).astype(np.float64)
+    x_np = _rand_c((B,) + N, 42)
+    s_np = _rand_c((C,) + N, 43)
+    yobs_np = _rand_c((B, C, M), 44)
+
+    om = torch.tensor(om_np, requires_grad=True)
+    x = torch.tensor(x_np.reshape(B, -1), requires_grad=True)
+    s = torch.tensor(s_np.reshape(C, -1))
+    A = _dense_torch(om, N)
+    y = torch.einsum("mj,bcj->bcm", A, x[:, None, :] * s[None])
+    loss = torch.sum(torch.abs(y - torch.tensor(yobs_np)) ** 2)
+    loss.backward()
+    g = 2.0 * (ndft.sense_forward(om_np, x_np, N, s_np) - yobs_np)
+    gom = ndft.jac_omega_fwd(om_np, x_np, g, N, s_np)
+    gx = ndft.jac_x_fwd(om_np, g, N, s_np).reshape(B, -1)
+    assert np.max(np.abs(gom - om.grad.numpy())) <= 1e-10 * np.max(np.abs(gom))
+    assert np.max(np.abs(gx - x.grad.numpy())) <= 1e-10 * np.max(np.abs(gx))
+
+    # adjoint operator x_hat = E^H y
+    om2 = torch.tensor(om_np, requires_grad=True)
+    yv = torch.tensor(yobs_np, requires_grad=True)
+    A2 = _dense_torch(om2, N)
+    xh = torch.einsum("mj,bcm->bcj", A2.conj(), yv)
+    xh = torch.sum(xh * s.conj()[None], dim=1)
+    t = torch.tensor(x_np.reshape(B, -1))
+    loss2 = torch.sum(torch.abs(xh - t) ** 2)
+    loss2.backward()
+    g2 = 2.0 * (ndft.sense_adjoint(om_np, yobs_np, N, s_np).reshape(B, -1) - x_np.reshape(B, -1))
+    gom2 = ndft.jac_omega_adj(om_np, yobs_np, g2.reshape((B,) + N), N, s_np)
+    gy2 = ndft.jac_x_adj(om_np, g2.reshape((B,) + N), N, s_np)
+    assert np.max(np.abs(gom2 - om2.grad.numpy())) <= 1e-10 * np.max(np.abs(gom2))
+    assert np.max(np.abs(gy2 - yv.grad.numpy())) <= 1e-10 * np.max(np.abs(gy2))
+
+
+# ---------------------------------------------------------------------------
+# FP64 NUFFT reference (appendix steps)
+# ---------------------------------------------------------------------------
+
+def test_kb_window_ft_matches_quadrature():
+    from scipy import integrate
+    for J, sigma in [(6, 2.0), (5, 1.25), (4, 2.0)]:
+        beta = nufft_ref.kb_beta(J, sigma)
+        for f in [0.0, 0.01, 0.1, 0.2, 0.25, 0.4]:
+            val, _ = integrate.quad(lambda t: nufft_ref.kb_window(np.array([t]), J, beta)[0]
+                                    * math.cos(2 * math.pi * f * t), -J / 2, J / 2,
+                                    epsabs=1e-14, epsrel=1e-13, limit=200)
+            ft = nufft_ref.kb_window_ft(np.array([f]), J, beta)[0]
+            assert abs(ft - val) <= 1e-10 * abs(val)
+
+
+def test_beta_and_grid_rule():
+    assert abs(nufft_ref.kb_beta(6, 2.0) - math.pi * math.sqrt(19.45)) < 1e-12
+    assert abs(nufft_ref.kb_beta(6, 2.0) - 13.8551) < 1e-4
+    assert nufft_ref.grid_size(256, 2.0) == 512
+    assert nufft_ref.grid_size(64, 2.0) == 128
+    assert nufft_ref.grid_size(131, 2.0) == 262 + 8  # 270 = 2 * 3^3 * 5
+    assert nufft_ref.grid_size(100, 1.25) == 125
+    for n in range(20, 400, 7):
+        k = nufft_ref.grid_size(n, 2.0)
+        assert k >= 2 * n
+        r = k
+        for p in (2, 3, 5, 7):
+            while r % p == 0:
+                r //= p
+        assert r == 1
+
+
+def test_nufft_ref_adjoint_identity():
+    p = nufft_ref.Params((12, 10), 2.0, 6)
+    om = W.uniform_random(50, 2, seed=51)
+    x = _rand_c((12, 10), 52)
+    y = _rand_c((50,), 53)
+    lhs = _inner(nufft_ref.forward(p, om, x), y)
+    rhs = _inner(x, nufft_ref.adjoint(p, om, y))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("N", [(40,), (32, 24), (12, 10, 8)])
+def test_nufft_ref_approximates_ndft(N):
+    """Accuracy of sigma = 2, J = 6 within 2e-5 and improving with J."""
+    D = len(N)
+    om = W.uniform_random(300, D, seed=61)
+    x = _rand_c(N, 62)
+    y = _rand_c((300,), 63)
+    exact_f = ndft.forward(om, x, N)
+    exact_a = ndft.adjoint(om, y, N)
+    errs = []
+    for J in (4, 6, 8):
+        p = nufft_ref.Params(N, 2.0, J)
+        ef = ndft.rel_l2(nufft_ref.forward(p, om, x), exact_f)
+        ea = ndft.rel_l2(nufft_ref.adjoint(p, om, y), exact_a)
+        errs.append(max(ef, ea))
+    assert errs[1] < 2e-5
+    assert errs[0] > 3 * errs[1] > 9 * errs[2]
+
+
+def test_nufft_ref_jacobian_via_weighted_nufft():
+    """A(x (.) r^[d]) from the NUFFT approximates the exact Jacobian diagonal."""
+    N = (32, 32)
+    om = W.radial_2d(8, 64)
+    x = _rand_c(N, 71)
+    p = nufft_ref.Params(N, 2.0, 6)
+    for d in range(2):
+        approx = nufft_ref.forward(p, om, nufft_ref.coordinate_weighted(p, x, d))
+        exact = ndft.forward(om, x, N, wdim=d)
+        assert ndft.rel_l2(approx, exact) < 1e-4
+
+
+# ---------------------------------------------------------------------------
+# Index pass reference
+# ---------------------------------------------------------------------------
+
+def test_points_ref_properties():
+    K = (512, 384)
+    T = (32, 16)
+    om = np.concatenate([
+        W.radial_2d(16, 64),
+        np.array([[0.0, 0.0], [-np.pi, np.pi], [np.float32(np.pi) - 1e-6, -1e-30],
+                  [1e3, -7.5e2], [np.nextafter(np.float32(0), np.float32(1)), -0.0]], dtype=np.float32),
+        W.uniform_random(200, 2, seed=81, lo=-20.0, hi=20.0),
+    ]).astype(np.float32)
+    cell, frac, bad = points_ref.cells(om, K)
+    assert not bad.any()
+    for d in range(2):
+        u = om[:, d].astype(np.float64) * (K[d] / (2 * np.pi))
+        # cell + frac reproduces u modulo K up to the float32 rounding of frac
+        resid = np.mod(cell[:, d] + frac[:, d].astype(np.float64) - u + K[d] / 2, K[d]) - K[d] / 2
+        assert np.max(np.abs(resid)) <= 1e-6
+        assert np.all((cell[:, d] >= 0) & (cell[:, d] < K[d]))
+        assert np.all((frac[:, d] >= 0) & (frac[:, d] <= 1))
+    tid, nt = points_ref.tiles(cell, K, T)
+    assert nt == 16 * 24
+    perm, off = points_ref.tile_order(tid, nt)
+    # brute force: stable order = lexicographic (tile, index)
+    expect = sorted(range(len(tid)), key=lambda i: (int(tid[i]), i))
+    assert list(perm) == expect
+    for t in range(nt):
+        assert np.all(tid[perm[off[t]:off[t + 1]]] == t)
+    bad_om = np.array([[np.nan, 0.0], [0.0, np.inf], [1e30, 0.0]], dtype=np.float32)
+    c2, f2, b2 = points_ref.cells(bad_om, K)
+    assert b2.all() and not c2.any() and not f2.any()
