@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Throughput of the KB-NUFFT hot path on one MI355X.
+
+One step = one pass of the whole path over one batch of synthetic input:
+  index pass (set_points) -> forward A x -> omega-Jacobian (forward op,
+  upstream gradient g) -> adjoint A^H g,
+for B images of 256 x 256 (complex64, N(0,1)) sharing one trajectory of 64
+golden-angle radial spokes x 512 samples (M = 32768) with uniform +-pi/256
+jitter; sigma = 2, J = 6, FP32 arithmetic.  value = B * M / step time
+(non-uniform points per second, whole job).
+
+Per-kernel durations come from HIP events recorded by the library on the
+launch stream over the timed region; the dominant kernel class is reported
+against the HBM peak using the algorithmic bytes of the model below.  The
+CPU baseline times the FP64 oracle on a bounded sample on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "nonuniform pts/s (fwd+adj+ω-Jacobian), % HBM peak; served recon p50/p99 ms"
+HBM_PEAK_GBPS = 8000.0
+C8 = 8  # bytes per complex64
+
+
+def algorithmic_bytes(N, K, M, B, D):
+    """Bytes per step that each kernel class must move (no halos, no re-reads).
+
+    Point record = sorted index (4 B) + D cells (4 B) + D fractions (4 B).
+    """
+    pN = math.prod(N)
+    pK = math.prod(K)
+    rows = pN // N[-1]            # image rows along the last axis
+    first_out = rows * K[-1]      # elements after the first (last-axis) pass
+    prec = M * (4 + 8 * D)
+    out = {}
+    out["index"] = M * D * 4 + prec
+    # forward (1 channel / image) and omega-Jacobian (D channels / image)
+    out["fft_first"] = C8 * (B * pN + B * first_out) + C8 * (B * pN + D * B * first_out)
+    mid = 0
+    # mid passes expand axes D-2..0 one at a time: sizes before/after each pass
+    sizes = []
+    cur = list(N[:-1]) + [K[-1]]
+    for d in range(D - 2, -1, -1):
+        before = math.prod(cur)
+        cur[d] = K[d]
+        sizes.append((before, math.prod(cur)))
+    for before, after in sizes:
+        mid += C8 * (before + after)
+    out["fft_mid_fwd"] = mid * B * (1 + D)
+    out["gather"] = C8 * (B * pK + B * M) + prec
+    out["gather_jac"] = C8 * (D * B * pK + B * M) + prec + 4 * M * D
+    out["spread"] = C8 * (B * M + B * pK) + prec
+    out["fft_mid_inv"] = mid * B
+    out["fft_last_adj"] = C8 * (B * first_out + B * pN)
+    out["fill"] = 4 * M * D
+    return out
+
+
+def cpu_baseline(N, om, x, g, rows_all=True, npix=4096):
+    """FP64 oracle on the host: forward + D Jacobian rows for every point of
+    one image, adjoint on a seeded subset of pixels, scaled to the image."""
+    import numpy as np
+
+    from oracle import ndft
+
+    D = len(N)
+    M = om.shape[0]
+    pN = int(np.prod(N))
+    pix = np.random.default_rng(4242).choice(pN, npix, replace=False)
+    t0 = time.perf_counter()
+    ndft.forward(om, x, N)
+    for d in range(D):
+        ndft.forward(om, x, N, wdim=d)
+    t1 = time.perf_counter()
+    ndft.adjoint(om, g, N, pix=pix)
+    t2 = time.perf_counter()
+    t_image = (t1 - t0) + (t2 - t1) * pN / npix
+    return {
+        "value": M / t_image,
+        "unit": "pts/s",
+        "cores": ndft.num_threads(),
+        "kind": "oracle",
+        "sample": (f"one {N[0]}x{N[1]} image: direct FP64 NUDFT forward + {D} omega-Jacobian "
+                   f"rows for all M={M} points ({t1 - t0:.1f} s), adjoint on {npix} of {pN} "
+                   f"pixels ({t2 - t1:.1f} s) scaled by {pN / npix:.0f}"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-pixels", type=int, default=4096)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); "
+              "the path shards by image/coil with no communication, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2111_02912_amd import workloads as W
+    from paper_2111_02912_amd.nufft import KbNufft
+
+    dev = torch.device("cuda", 0)
+    B = args.batch
+    N, om, x = W.throughput_case(batch=B)
+    M = om.shape[0]
+    D = len(N)
+    g = W.complex_normal((B, 1, M), 2101)
+    p = KbNufft(N, device=dev)
+    om_t = torch.from_numpy(om).to(dev)
+    x_t = torch.from_numpy(x).to(dev)
+    g_t = torch.from_numpy(g).to(dev)
+    dom = torch.empty((M, D), dtype=torch.float32, device=dev)
+
+    def step():
+        p.set_points(om_t)
+        y = p.forward(x_t)
+        p.jac_omega_fwd(x_t, g_t, out=dom)
+        xa = p.adjoint(g_t)
+        return y, xa
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    p.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    p.timing(False)
+    kt = p.timing_read()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = B * M / ((t1 - t0) / args.steps)
+
+    alg = algorithmic_bytes(N, p.K, M, B, D)
+    kernels = {}
+    for name, (n, ms) in kt.items():
+        if n == 0:
+            continue
+        b = alg.get(name, 0) * args.steps
+        kernels[name] = {"launches": n, "avg_ms": ms / n,
+                         "ms_per_step": ms / args.steps,
+                         "alg_GBps": (b / (ms * 1e-3) / 1e9) if b else None}
+    dom_name = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    dk = kernels[dom_name]
+    per_launch_bytes = alg[dom_name] * args.steps / dk["launches"]
+    achieved = per_launch_bytes / (dk["avg_ms"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                "alg_bytes_per_launch": per_launch_bytes, "avg_launch_ms": dk["avg_ms"]}
+    total_alg = sum(alg.values())
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(N, om, x[0], g[0, 0], npix=args.cpu_pixels)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "2D KB-NUFFT step: index pass + forward + omega-Jacobian + adjoint",
+            "N": list(N), "K": list(p.K), "M": M, "batch": B, "sigma": 2.0, "J": 6,
+            "trajectory": "64 golden-angle radial spokes x 512 samples, uniform +-pi/256 jitter",
+            "images": "complex64, re/im i.i.d. N(0,1)",
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "step_alg_GBps": total_alg / (ms_step * 1e-3) / 1e9,
+        "kernels": kernels,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,231 @@
+/*
+ * kbnufft.h -- C ABI of the MI355X Kaiser-Bessel NUFFT library.
+ *
+ * Operation (Wang & Fessler, "Efficient approximation of Jacobian matrices
+ * involving a non-uniform fast Fourier transform", Sec. II-B eq. (e,ndft)):
+ *
+ *     A(omega) in C^{M x N},  a_ij = exp(-i omega_i . r_j),
+ *
+ * for M sample locations omega (an M x D real matrix, radians per voxel) and
+ * voxel centres r_j on a D-dimensional Cartesian grid.  The library applies
+ * a Kaiser-Bessel NUFFT approximation of A and A^H (appendix: scaling
+ * factors, zero-padded K-point FFT, J-tap interpolation), and the paper's
+ * Jacobians with respect to omega, evaluated as extra NUFFTs of images
+ * weighted by the coordinate grids r^[d] (Sec. II-C eq. (e,Ax), Sec. II-D
+ * eq. (e,A'y), JVP rule eq. (e,jac,Ax,v) of Sec. III), for the multi-coil
+ * SENSE model E = (I_C kron A) S of Sec. II-F.
+ *
+ * Conventions (all binding):
+ *   - D in {1, 2, 3}.  Images are row-major, axis 0 slowest; the coordinate
+ *     of index j on an axis of length n is r = j - floor(n/2).
+ *   - omega is float32 [M][D], row-major; column d pairs with image axis d.
+ *     Any finite value is accepted (the operator is 2 pi-periodic in omega).
+ *   - complex data are interleaved float32 pairs (re, im) ("c64"):
+ *       images  x      c64 [B][N_0]...[N_{D-1}]
+ *       maps    smaps  c64 [C][N_0]...[N_{D-1}]   (NULL: C must be 1, S = I)
+ *       k-space y      c64 [B][C][M]
+ *   - forward uses exp(-i ...), adjoint exp(+i ...), no normalisation.
+ *   - gradients follow PyTorch's convention for complex tensors: the
+ *     gradient of a real loss L w.r.t. z is dL/dRe z + i dL/dIm z.
+ *   - Every data pointer is a DEVICE pointer (HIP device memory) unless the
+ *     argument says "host".  The caller owns all input and output buffers;
+ *     the plan owns its internal buffers.
+ *   - Every call is asynchronous on `stream` (a hipStream_t, NULL = the
+ *     null stream) and never synchronises it, except kbn_check_error and a
+ *     workspace growth (see kbn_plan_create).
+ *   - A plan is not thread-safe: calls on one plan must be ordered (one
+ *     stream, or the caller's synchronisation).  Distinct plans are
+ *     independent.
+ *   - Calls return 0 on success or a negative KBN_ERR_* code; they never
+ *     throw and never abort.  kbn_last_error() gives a message for the last
+ *     failing call of the calling thread.
+ */
+#ifndef KBNUFFT_H
+#define KBNUFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KBN_OK 0
+#define KBN_ERR_INVALID_ARG (-1)     /* bad pointer, size, dimension or option */
+#define KBN_ERR_UNSUPPORTED (-2)     /* valid request outside supported sizes  */
+#define KBN_ERR_OOM (-3)             /* device allocation failed                */
+#define KBN_ERR_HIP (-4)             /* a HIP runtime call or launch failed      */
+#define KBN_ERR_NONFINITE (-5)       /* some omega was non-finite or too large  */
+#define KBN_ERR_NO_POINTS (-6)       /* operator call before kbn_set_points     */
+
+#define KBN_OP_FORWARD 0             /* the operator y = E x                    */
+#define KBN_OP_ADJOINT 1             /* the operator x = E^H y                  */
+
+typedef struct kbn_plan_s *kbn_plan;
+
+/* Plan options.  Zero-initialised fields take the defaults shown. */
+typedef struct {
+    double sigma;            /* grid oversampling factor, >= 1 (default 2.0)        */
+    int J;                   /* window width in grid cells, 2..8 (default 6)        */
+    int tile[3];             /* tile edge per axis for sorting and spreading
+                                (0 = automatic: 1D 256, 2D 32, 3D 16)               */
+    int64_t max_workspace;   /* byte cap for the plan's grid workspace; batches
+                                larger than fits are processed in chunks
+                                (0 = 4 GiB)                                          */
+} kbn_opts;
+
+/*
+ * Create a plan for images of shape N (host int64[D]).
+ *
+ * Chooses per axis K_d = smallest integer >= sigma N_d whose prime factors
+ * are 2, 3, 5, 7 (appendix: "K-point FFT ... via zero-padding"), the window
+ * psi(t) = I0(beta sqrt(1 - (2t/J)^2)) / I0(beta) with the Beatty et al.
+ * beta = pi sqrt((J/sigma)^2 (sigma - 1/2)^2 - 0.8) (the paper defers the
+ * window to its NUFFT library), scaling factors s_n = 1/psi_hat(r_n/K_d)
+ * (appendix "scaling factors s_n"), and FFT twiddles, all in FP64 on the
+ * host, and uploads them.  Synchronous (blocking) call.
+ *
+ * The grid workspace is allocated on first use and grown when a larger
+ * batch arrives; a growth synchronises `stream` before freeing the old
+ * buffer.
+ *
+ * Errors: INVALID_ARG (out == NULL, D not in 1..3, N_d < 1, sigma < 1,
+ * J outside 2..8), UNSUPPORTED (K_d > 1024 or K_d < 2J), OOM, HIP.
+ */
+int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts);
+
+/*
+ * Set (or replace) the M sample locations.  omega: device float32 [M][D].
+ *
+ * Computes, per point and axis, u = omega K_d / (2 pi) in FP64, the grid
+ * cell floor(u) mod K_d and the in-cell fraction (float32), the tile id, and
+ * a stable order of the points by tile (the appendix's offsets k_m and J
+ * taps k_m + j are derived from these).  omega is read during the call's
+ * stream work only; the caller may reuse it afterwards.  M = 0 is allowed.
+ *
+ * A non-finite omega (or |u| >= 2^40) sets a sticky device flag reported by
+ * kbn_check_error; such points give NaN in forward outputs and omega
+ * gradients and contribute nothing to adjoint outputs.
+ *
+ * Errors: INVALID_ARG (M < 0, M > 2^31 - 1, omega == NULL with M > 0),
+ * OOM, HIP.
+ */
+int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream);
+
+/*
+ * y[b][c] = A(omega) (s_c (.) x_b)   (type-2 NUFFT; Sec. II-B, II-F).
+ * x: c64 [B][N...]; smaps: c64 [C][N...] or NULL (then C == 1);
+ * y: c64 [B][C][M], overwritten.
+ * Errors: INVALID_ARG (B < 1, C < 1, NULL pointers, smaps NULL with C > 1),
+ * NO_POINTS, OOM, HIP.
+ */
+int kbn_forward(kbn_plan p, int B, int C, const void *x, const void *smaps, void *y,
+                void *stream);
+
+/*
+ * x_b = sum_c conj(s_c) (.) A(omega)^H y[b][c]   (type-1 NUFFT; Sec. II-D,
+ * II-F).  y: c64 [B][C][M]; x: c64 [B][N...], overwritten.
+ * Errors as kbn_forward.
+ */
+int kbn_adjoint(kbn_plan p, int B, int C, const void *y, const void *smaps, void *x,
+                void *stream);
+
+/*
+ * Gradient of a real loss w.r.t. omega through y = E(omega) x, given the
+ * upstream gradient g = dL/dy (c64 [B][C][M]):
+ *
+ *   domega[m][d] (+)= sum_{b,c} Im{ [A(s_c x_b (.) r^[d])]_m conj(g[b][c][m]) }
+ *
+ * which is eq. (e,Ax), dA x / d omega^[d] = -i diag{A (x (.) r^[d])}, applied
+ * through the JVP rule eq. (e,jac,Ax,v) with the NUFFT standing in for A.
+ * domega: device float32 [M][D]; accumulate = 0 overwrites it, 1 adds.
+ * Errors as kbn_forward.
+ */
+int kbn_jac_omega_fwd(kbn_plan p, int B, int C, const void *x, const void *smaps,
+                      const void *g, float *domega, int accumulate, void *stream);
+
+/*
+ * Gradient of a real loss w.r.t. omega through x = E(omega)^H y, given the
+ * upstream gradient g = dL/dx (c64 [B][N...]):
+ *
+ *   domega[m][d] (+)= sum_{b,c} Im{ [A(s_c g_b (.) r^[d])]_m conj(y[b][c][m]) }
+ *
+ * the transpose of eq. (e,A'y), dA^H y / d omega^[d] = i diag{r^[d]} A^H
+ * diag{y}, applied to g.  y: c64 [B][C][M].  Errors as kbn_forward.
+ */
+int kbn_jac_omega_adj(kbn_plan p, int B, int C, const void *y, const void *smaps,
+                      const void *g, float *domega, int accumulate, void *stream);
+
+/*
+ * Gradient w.r.t. the linear input (Sec. II-C: dAx/dx = A; Sec. II-D:
+ * dA^H y/dy = A^H):
+ *   op = KBN_OP_FORWARD: out = E^H g, g c64 [B][C][M], out c64 [B][N...];
+ *   op = KBN_OP_ADJOINT: out = E g,   g c64 [B][N...], out c64 [B][C][M].
+ * Errors as kbn_forward, plus INVALID_ARG for an unknown op.
+ */
+int kbn_jac_x(kbn_plan p, int op, int B, int C, const void *g, const void *smaps,
+              void *out, void *stream);
+
+/*
+ * Plan facts (host outputs; any pointer may be NULL):
+ *   K       int64[D]  oversampled grid size per axis
+ *   tile    int[D]    tile edge per axis; ntiles total tile count
+ *   beta    window shape parameter
+ *   M       current number of points (0 before kbn_set_points)
+ *   workspace_bytes  currently allocated grid workspace
+ */
+int kbn_plan_info(kbn_plan p, int64_t *K, int *tile, int *ntiles, double *beta,
+                  int64_t *M, int64_t *workspace_bytes);
+
+/*
+ * Copy the index pass results into caller device buffers (for testing and
+ * inspection; any pointer may be NULL):
+ *   order   int32 [M]          original index of the point at sorted position q
+ *   cell    int32 [D][M]       grid cell floor(u) mod K_d, in sorted order
+ *   frac    float32 [D][M]     u - floor(u) rounded to float32, sorted order
+ *   offsets int32 [ntiles + 2] first sorted position of each tile; entry
+ *                              ntiles is the end of the finite points, entry
+ *                              ntiles + 1 is M (flagged points sort last)
+ * Asynchronous on stream.
+ */
+int kbn_get_points(kbn_plan p, int *order, int *cell, float *frac, int *offsets,
+                   void *stream);
+
+/*
+ * Synchronise `stream` and report the sticky non-finite-omega flag:
+ * returns KBN_ERR_NONFINITE (and clears the flag) if any omega given to
+ * kbn_set_points since the last check was non-finite, else 0 (or HIP).
+ */
+int kbn_check_error(kbn_plan p, void *stream);
+
+/*
+ * Per-kernel timing, for measurement (not part of the operator).
+ *
+ * kbn_timing(p, 1) clears the counters and starts bracketing every kernel
+ * launch of the plan with HIP events recorded on the launch's own stream;
+ * kbn_timing(p, 0) stops recording.  kbn_timing_read waits for the recorded
+ * events and returns, for kernel class `cls`, the number of timed launches
+ * and their summed durations in milliseconds.  kbn_timing_name gives the
+ * class name ("index", "fft_first", "fft_mid_fwd", "fft_mid_inv",
+ * "fft_last_adj", "gather", "gather_jac", "spread", "fill"), or NULL for cls
+ * past the last class.
+ * Errors: INVALID_ARG (null plan, bad class), HIP.
+ */
+int kbn_timing(kbn_plan p, int enable);
+int kbn_timing_read(kbn_plan p, int cls, int64_t *launches, double *total_ms);
+const char *kbn_timing_name(int cls);
+
+/* Free the plan and its device buffers (synchronises the device). */
+int kbn_plan_destroy(kbn_plan p);
+
+/* Static description of an error code. */
+const char *kbn_strerror(int code);
+
+/* Message of the calling thread's last failing call ("" if none). */
+const char *kbn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KBNUFFT_H */

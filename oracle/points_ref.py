@@ -16,8 +16,8 @@ be compared bit for bit:
   tile  = cell // T per axis; tile id row-major over ceil(K/T) tiles per axis
   order = stable sort of the points by tile id (ties keep input order)
 
-Samples with a non-finite omega or |u| >= 2^40 are flagged and given
-cell 0, frac 0.
+Samples with a non-finite omega or |u| >= 2^40 are flagged, given cell 0,
+frac 0 and the extra tile id ntiles, so they sort after all finite points.
 """
 from __future__ import annotations
 
@@ -53,21 +53,31 @@ def cells(omega, K):
     return cell, frac, bad
 
 
-def tiles(cell, K, T):
-    """Row-major tile id of every point; returns (tile [M] int32, ntiles)."""
+def tiles(cell, K, T, bad=None):
+    """Row-major tile id of every point; returns (tile [M] int32, ntiles).
+
+    Flagged points (``bad``) get the id ntiles.
+    """
     cell = np.asarray(cell)
     D = cell.shape[1]
     nt = [-(-int(K[d]) // int(T[d])) for d in range(D)]
     tid = np.zeros(cell.shape[0], dtype=np.int64)
     for d in range(D):
         tid = tid * nt[d] + cell[:, d] // int(T[d])
-    return tid.astype(np.int32), int(np.prod(nt))
+    ntiles = int(np.prod(nt))
+    if bad is not None:
+        tid[np.asarray(bad)] = ntiles
+    return tid.astype(np.int32), ntiles
 
 
 def tile_order(tid, ntiles):
-    """Stable order of points by tile, and tile start offsets [ntiles + 1]."""
+    """Stable order of points by tile id, and offsets [ntiles + 2].
+
+    off[t] is the first sorted position of tile t, off[ntiles] the end of
+    the finite points and off[ntiles + 1] = M.
+    """
     perm = np.argsort(tid, kind="stable").astype(np.int32)
-    counts = np.bincount(tid, minlength=ntiles)
-    off = np.zeros(ntiles + 1, dtype=np.int32)
+    counts = np.bincount(tid, minlength=ntiles + 1)
+    off = np.zeros(ntiles + 2, dtype=np.int32)
     off[1:] = np.cumsum(counts)
     return perm, off

@@ -1,0 +1,145 @@
+// Internal declarations of the KB-NUFFT library (device kernels + host plan).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#define KBN_MAX_D 3
+#define KBN_MAX_J 8
+#define KBN_NCOEF 11        // polynomial coefficients per window piece (degree 10)
+#define KBN_MAX_STAGES 24
+#define KBN_MAX_K 1024      // largest oversampled grid edge handled by the LDS FFT
+#define KBN_MAX_TILES 16383 // tile histogram lives in LDS (ntiles + 1 counters)
+#define KBN_BLOCK 256
+
+// kernel classes reported by kbn_timing_read (order of kClassNames)
+#define KBN_CLASS_INDEX 0
+#define KBN_CLASS_FFT_FIRST 1
+#define KBN_CLASS_FFT_MID_FWD 2
+#define KBN_CLASS_FFT_MID_INV 3
+#define KBN_CLASS_FFT_LAST_ADJ 4
+#define KBN_CLASS_GATHER 5
+#define KBN_CLASS_GATHER_JAC 6
+#define KBN_CLASS_SPREAD 7
+#define KBN_CLASS_FILL 8
+#define KBN_NCLASS 9
+
+// Mixed-radix factorisation of one FFT length (radices 2, 3, 4, 5, 7, 8).
+struct KbnRadix {
+    int L;
+    int nst;
+    int r[KBN_MAX_STAGES];
+};
+
+// Geometry shared by the interpolation kernels (passed by value).
+struct KbnGeom {
+    int D;
+    int J;
+    int K[KBN_MAX_D];
+    int T[KBN_MAX_D];
+    int nt[KBN_MAX_D];
+    int ntiles;
+    const float *coef;  // [J][KBN_NCOEF] monomial coefficients in x = 2 f - 1
+};
+
+// ---------------------------------------------------------------------------
+// Index pass (points.hip)
+// ---------------------------------------------------------------------------
+struct KbnPointsBufs {
+    int *cell_tmp;   // [D][M] original order
+    float *frac_tmp; // [D][M]
+    int *tile;       // [M]
+    int *counts;     // [nbins][nchunks]
+    int *order;      // [M] sorted position -> original index
+    int *cell;       // [D][M] sorted
+    float *frac;     // [D][M] sorted
+    int *toff;       // [nbins + 1]
+    int *flag;       // sticky non-finite flag
+};
+
+hipError_t kbn_launch_points(int D, int64_t M, const float *omega, const double *scale,
+                             const int *K, const int *T, const int *nt, int ntiles,
+                             int chunk, int nchunks, const KbnPointsBufs &b, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// FFT passes (fft.hip)
+// ---------------------------------------------------------------------------
+struct KbnFirstPassArgs {      // forward: prologue + FFT along the last axis
+    const float2 *x;           // [B][R0][Nl] images (batch offset applied)
+    const float2 *smaps;       // [C][R0][Nl] or null
+    float2 *out;               // [nch][R0][L]
+    int64_t nlines;            // nch * R0
+    int R0;                    // rows per image (product of leading N)
+    int Nl;                    // last-axis image length
+    int C, nw;                 // coils, weight channels per coil (1 or D)
+    int weighted;              // 1: weight channel w multiplies by r^[w]
+    int D;
+    int N[KBN_MAX_D];
+    const float *deap[KBN_MAX_D];
+};
+
+struct KbnMidPassArgs {        // FFT along a non-last axis, strided
+    const float2 *in;
+    float2 *out;
+    int64_t outer;             // independent groups (channels x leading axes)
+    int nin, nout;             // line length in / out (pruned or cropped)
+    int inner;                 // product of the later axes' (grid) sizes
+    int pad_in;                // 1: input rows sit at r mod L (zero-padded)
+    int crop_out;              // 1: output rows are taken from r mod L
+};
+
+struct KbnLastAdjArgs {        // adjoint: IFFT along the last axis + crop + scale + coil sum
+    const float2 *in;          // [nb*C][R0][L]
+    const float2 *smaps;       // [C][R0][Nl] or null
+    float2 *x;                 // [nb][R0][Nl] (batch offset applied)
+    int64_t nlines;            // nb * R0
+    int R0, Nl, C;
+    int accumulate;
+    int D;
+    int N[KBN_MAX_D];
+    const float *deap[KBN_MAX_D];
+};
+
+hipError_t kbn_launch_first_pass(const KbnFirstPassArgs &a, const KbnRadix &rp,
+                                 const float2 *tw, int maxe, hipStream_t s);
+hipError_t kbn_launch_mid_pass(const KbnMidPassArgs &a, const KbnRadix &rp, const float2 *tw,
+                               int inverse, int maxe, hipStream_t s);
+hipError_t kbn_launch_last_adj(const KbnLastAdjArgs &a, const KbnRadix &rp, const float2 *tw,
+                               int maxe, hipStream_t s);
+int kbn_lines_per_block(const KbnRadix &rp, int maxe);
+
+// ---------------------------------------------------------------------------
+// Interpolation (interp.hip)
+// ---------------------------------------------------------------------------
+struct KbnGatherArgs {
+    const float2 *grid;        // [nch][prod K]
+    int64_t gsize;             // prod K
+    int nch;                   // channels in this chunk
+    int C, nw;                 // channel = (b_local * C + c) * nw + w
+    int64_t M;
+    const int *order;
+    const int *cell;
+    const float *frac;
+    const int *toff;           // toff[ntiles] = end of finite points
+    float2 *y;                 // mode 0: [B][C][M] with batch offset applied
+    const float2 *v;           // mode 1: [B][C][M] with batch offset applied
+    float *domega;             // mode 1: [M][D]
+};
+
+struct KbnSpreadArgs {
+    const float2 *y;           // [nb][C][M] batch offset applied
+    float2 *grid;              // [nch][prod K], nch = nb * C
+    int64_t gsize;
+    int nch;
+    int64_t M;
+    const int *order;
+    const int *cell;
+    const float *frac;
+    const int *toff;
+};
+
+hipError_t kbn_launch_gather(const KbnGeom &g, const KbnGatherArgs &a, int mode, hipStream_t s);
+hipError_t kbn_launch_spread(const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s);
+hipError_t kbn_launch_fill(float *p, int64_t n, float v, hipStream_t s);

@@ -1,0 +1,758 @@
+// Host side of the KB-NUFFT library: plan constants (FP64), buffer
+// management, pipeline dispatch and the C ABI declared in kbnufft.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kbn_internal.h"
+#include "kbnufft.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define KBN_HIP(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(KBN_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+bool debug_sync() {
+    static const int v = [] {
+        const char *e = std::getenv("KBN_DEBUG_SYNC");
+        return e ? std::atoi(e) : 0;
+    }();
+    return v != 0;
+}
+
+int launched(hipError_t e, const char *what, hipStream_t s) {
+    if (e != hipSuccess) return fail(KBN_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    if (debug_sync()) {
+        hipError_t e2 = hipStreamSynchronize(s);
+        if (e2 != hipSuccess)
+            return fail(KBN_ERR_HIP, std::string(what) + " (sync): " + hipGetErrorString(e2));
+    }
+    return KBN_OK;
+}
+
+const char *const kClassNames[KBN_NCLASS] = {"index",       "fft_first",    "fft_mid_fwd",
+                                               "fft_mid_inv", "fft_last_adj", "gather",
+                                               "gather_jac",  "spread",       "fill"};
+
+// Launch `expr` (a kernel launcher returning hipError_t) of kernel class
+// `cls`; with timing enabled the launch is bracketed by events on `stream`.
+#define KBN_LAUNCH(cls, expr, name)                                     \
+    do {                                                                \
+        hipEvent_t e0_ = nullptr;                                       \
+        if (p->timing) e0_ = timing_mark(p, stream);                    \
+        int rc_ = launched((expr), name, stream);                       \
+        if (p->timing && e0_) {                                         \
+            hipEvent_t e1_ = timing_mark(p, stream);                    \
+            if (e1_) p->pending.push_back({(cls), e0_, e1_});           \
+        }                                                               \
+        if (rc_ != KBN_OK) return rc_;                                  \
+    } while (0)
+
+// ---- window mathematics (FP64) -------------------------------------------
+
+// Modified Bessel function I0 by its power series sum_k (x^2/4)^k / (k!)^2
+// (all terms positive, so the partial sums are accurate to rounding).
+double bessel_i0(double x) {
+    const double q = 0.25 * x * x;
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 500; ++k) {
+        term *= q / ((double)k * (double)k);
+        sum += term;
+        if (term < 1e-17 * sum) break;
+    }
+    return sum;
+}
+
+struct Window {
+    int J;
+    double beta;
+    double i0beta;
+    double psi(double t) const {  // normalised KB window, zero outside |t| <= J/2
+        const double a = 1.0 - (2.0 * t / J) * (2.0 * t / J);
+        if (a < 0.0) return 0.0;
+        return bessel_i0(beta * std::sqrt(a)) / i0beta;
+    }
+    double psi_hat(double f) const {  // continuous Fourier transform of psi
+        const double z2 = beta * beta - (M_PI * J * f) * (M_PI * J * f);
+        double r;
+        if (z2 > 0) {
+            const double z = std::sqrt(z2);
+            r = std::sinh(z) / z;
+        } else if (z2 < 0) {
+            const double z = std::sqrt(-z2);
+            r = std::sin(z) / z;
+        } else {
+            r = 1.0;
+        }
+        return J * r / i0beta;
+    }
+};
+
+// Degree-(KBN_NCOEF-1) polynomial in x = 2f - 1, f in [0, 1], for each tap
+// piece psi(f + J/2 - 1 - j): Chebyshev interpolation, then monomial form.
+std::vector<float> window_polys(const Window &w) {
+    const int P = KBN_NCOEF - 1;
+    const int n = P + 1;
+    std::vector<float> out((size_t)w.J * KBN_NCOEF);
+    for (int j = 0; j < w.J; ++j) {
+        std::vector<double> fx(n), cheb(n, 0.0);
+        for (int k = 0; k < n; ++k) {
+            const double xk = std::cos(M_PI * (k + 0.5) / n);
+            const double f = 0.5 * (xk + 1.0);
+            fx[k] = w.psi(f + 0.5 * w.J - 1.0 - j);
+        }
+        for (int m = 0; m < n; ++m) {
+            double s = 0.0;
+            for (int k = 0; k < n; ++k) s += fx[k] * std::cos(M_PI * m * (k + 0.5) / n);
+            cheb[m] = (m == 0 ? 1.0 : 2.0) * s / n;
+        }
+        // T_m in monomial form by the three-term recurrence
+        std::vector<double> mono(n, 0.0), tprev(n, 0.0), tcur(n, 0.0), tnext(n, 0.0);
+        tprev[0] = 1.0;               // T0
+        tcur[1] = 1.0;                // T1
+        mono[0] += cheb[0];
+        if (n > 1) mono[1] += cheb[1];
+        for (int m = 2; m < n; ++m) {
+            std::fill(tnext.begin(), tnext.end(), 0.0);
+            for (int i = 0; i + 1 < n; ++i) tnext[i + 1] += 2.0 * tcur[i];
+            for (int i = 0; i < n; ++i) tnext[i] -= tprev[i];
+            for (int i = 0; i < n; ++i) mono[i] += cheb[m] * tnext[i];
+            tprev.swap(tcur);
+            tcur.swap(tnext);
+        }
+        for (int i = 0; i < n; ++i) out[(size_t)j * KBN_NCOEF + i] = (float)mono[i];
+    }
+    return out;
+}
+
+int smooth_size(double target) {  // smallest 7-smooth integer >= target
+    int k = (int)std::ceil(target - 1e-9);
+    if (k < 1) k = 1;
+    for (;; ++k) {
+        int r = k;
+        for (int p : {2, 3, 5, 7})
+            while (r % p == 0) r /= p;
+        if (r == 1) return k;
+    }
+}
+
+bool factor(int L, KbnRadix &rp) {
+    rp.L = L;
+    rp.nst = 0;
+    int r = L;
+    for (int f : {8, 4, 2, 3, 5, 7}) {
+        while (r % f == 0) {
+            if (rp.nst >= KBN_MAX_STAGES) return false;
+            rp.r[rp.nst++] = f;
+            r /= f;
+        }
+    }
+    return r == 1;
+}
+
+}  // namespace
+
+struct kbn_plan_s {
+    int D = 0;
+    int N[KBN_MAX_D] = {1, 1, 1};
+    int K[KBN_MAX_D] = {1, 1, 1};
+    int J = 6;
+    double sigma = 2.0, beta = 0.0;
+    int T[KBN_MAX_D] = {1, 1, 1};
+    int nt[KBN_MAX_D] = {1, 1, 1};
+    int ntiles = 1;
+    double scale[KBN_MAX_D] = {0, 0, 0};
+    KbnRadix rad[KBN_MAX_D];
+    float *deap[KBN_MAX_D] = {nullptr, nullptr, nullptr};
+    float2 *tw[KBN_MAX_D] = {nullptr, nullptr, nullptr};
+    float *coef = nullptr;
+    int *flag = nullptr;
+    int maxe = 16;
+    // points
+    int64_t M = -1, Mcap = 0;
+    int *cell_tmp = nullptr, *tile = nullptr, *order = nullptr, *cell = nullptr, *toff = nullptr;
+    float *frac_tmp = nullptr, *frac = nullptr;
+    int *counts = nullptr;
+    int64_t counts_cap = 0;
+    // grid workspace
+    float2 *ws = nullptr;
+    int64_t ws_bytes = 0, max_ws = 0;
+    // per-kernel-class event timing (kbn_timing)
+    struct Timed {
+        int cls;
+        hipEvent_t e0, e1;
+    };
+    bool timing = false;
+    std::vector<Timed> pending;
+    std::vector<hipEvent_t> pool;
+    double t_ms[KBN_NCLASS] = {};
+    int64_t t_n[KBN_NCLASS] = {};
+
+    int64_t gsize() const {
+        int64_t g = 1;
+        for (int d = 0; d < D; ++d) g *= K[d];
+        return g;
+    }
+    KbnGeom geom() const {
+        KbnGeom g;
+        g.D = D;
+        g.J = J;
+        for (int d = 0; d < KBN_MAX_D; ++d) {
+            g.K[d] = K[d];
+            g.T[d] = T[d];
+            g.nt[d] = nt[d];
+        }
+        g.ntiles = ntiles;
+        g.coef = coef;
+        return g;
+    }
+};
+
+namespace {
+
+hipEvent_t timing_mark(kbn_plan p, hipStream_t stream) {
+    hipEvent_t e = nullptr;
+    if (!p->pool.empty()) {
+        e = p->pool.back();
+        p->pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        return nullptr;
+    }
+    if (hipEventRecord(e, stream) != hipSuccess) {
+        p->pool.push_back(e);
+        return nullptr;
+    }
+    return e;
+}
+
+template <typename T>
+int dev_alloc(T **p, int64_t count) {
+    *p = nullptr;
+    if (count <= 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * (size_t)count);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(KBN_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    return KBN_OK;
+}
+
+template <typename T>
+void dev_free(T *&p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+void free_points(kbn_plan p) {
+    dev_free(p->cell_tmp);
+    dev_free(p->tile);
+    dev_free(p->order);
+    dev_free(p->cell);
+    dev_free(p->frac_tmp);
+    dev_free(p->frac);
+    dev_free(p->counts);
+    p->Mcap = 0;
+    p->counts_cap = 0;
+}
+
+void free_plan(kbn_plan p) {
+    for (auto &t : p->pending) {
+        (void)hipEventDestroy(t.e0);
+        (void)hipEventDestroy(t.e1);
+    }
+    for (auto e : p->pool) (void)hipEventDestroy(e);
+    free_points(p);
+    for (int d = 0; d < KBN_MAX_D; ++d) {
+        dev_free(p->deap[d]);
+        dev_free(p->tw[d]);
+    }
+    dev_free(p->coef);
+    dev_free(p->flag);
+    dev_free(p->toff);
+    dev_free(p->ws);
+    delete p;
+}
+
+int ensure_ws(kbn_plan p, int64_t bytes, hipStream_t stream) {
+    if (bytes <= p->ws_bytes) return KBN_OK;
+    KBN_HIP(hipStreamSynchronize(stream));
+    dev_free(p->ws);
+    p->ws_bytes = 0;
+    int rc = dev_alloc((char **)&p->ws, bytes);
+    if (rc != KBN_OK) return rc;
+    p->ws_bytes = bytes;
+    return KBN_OK;
+}
+
+// img: an image-space buffer (never empty); ksp: a k-space buffer, which
+// holds no element (and may be NULL) when M == 0.
+int check_common(kbn_plan p, int B, int C, const void *img, const void *smaps, const void *ksp) {
+    if (!p) return fail(KBN_ERR_INVALID_ARG, "null plan");
+    if (p->M < 0) return fail(KBN_ERR_NO_POINTS, "kbn_set_points has not been called");
+    if (B < 1 || C < 1) return fail(KBN_ERR_INVALID_ARG, "B and C must be >= 1");
+    if (!smaps && C != 1) return fail(KBN_ERR_INVALID_ARG, "C > 1 needs coil maps");
+    if (!img || (!ksp && p->M > 0)) return fail(KBN_ERR_INVALID_ARG, "null data pointer");
+    return KBN_OK;
+}
+
+int64_t img_rows(kbn_plan p) {  // product of the leading image axes
+    int64_t r = 1;
+    for (int d = 0; d + 1 < p->D; ++d) r *= p->N[d];
+    return r;
+}
+
+// Forward-type pipeline: scaling (+ coil map, + coordinate weight), FFT
+// passes, then gather.  mode 0 writes y; mode 1 folds the omega-Jacobian.
+int run_type2(kbn_plan p, int B, int C, int nw, int weighted, const float2 *x,
+              const float2 *smaps, int mode, float2 *y, const float2 *v, float *dom,
+              hipStream_t stream) {
+    const int D = p->D;
+    const int64_t gsz = p->gsize();
+    const int64_t per_img = (int64_t)C * nw * gsz * (int64_t)sizeof(float2) * 2;
+    int64_t bc = std::max<int64_t>(1, std::min<int64_t>(B, p->max_ws / per_img));
+    int rc = ensure_ws(p, bc * per_img, stream);
+    if (rc != KBN_OK) return rc;
+    float2 *bufA = p->ws;
+    float2 *bufB = p->ws + bc * C * nw * gsz;
+    const int64_t R0 = img_rows(p);
+    const int Nl = p->N[D - 1];
+    const KbnGeom geom = p->geom();
+    for (int64_t b0 = 0; b0 < B; b0 += bc) {
+        const int64_t nb = std::min<int64_t>(bc, B - b0);
+        const int64_t nch = nb * C * nw;
+        KbnFirstPassArgs fa;
+        fa.x = x + b0 * R0 * Nl;
+        fa.smaps = smaps;
+        fa.out = bufA;
+        fa.nlines = nch * R0;
+        fa.R0 = (int)R0;
+        fa.Nl = Nl;
+        fa.C = C;
+        fa.nw = nw;
+        fa.weighted = weighted;
+        fa.D = D;
+        for (int d = 0; d < KBN_MAX_D; ++d) {
+            fa.N[d] = p->N[d];
+            fa.deap[d] = p->deap[d];
+        }
+        KBN_LAUNCH(KBN_CLASS_FFT_FIRST, kbn_launch_first_pass(fa, p->rad[D - 1], p->tw[D - 1], p->maxe, stream),
+                   "first pass");
+        float2 *cur = bufA, *nxt = bufB;
+        for (int d = D - 2; d >= 0; --d) {
+            int64_t outer = nch, inner = 1;
+            for (int e = 0; e < d; ++e) outer *= p->N[e];
+            for (int e = d + 1; e < D; ++e) inner *= p->K[e];
+            KbnMidPassArgs ma;
+            ma.in = cur;
+            ma.out = nxt;
+            ma.outer = outer;
+            ma.nin = p->N[d];
+            ma.nout = p->K[d];
+            ma.inner = (int)inner;
+            ma.pad_in = 1;
+            ma.crop_out = 0;
+            KBN_LAUNCH(KBN_CLASS_FFT_MID_FWD, kbn_launch_mid_pass(ma, p->rad[d], p->tw[d], 0, p->maxe, stream), "mid pass");
+            std::swap(cur, nxt);
+        }
+        KbnGatherArgs ga;
+        ga.grid = cur;
+        ga.gsize = gsz;
+        ga.nch = (int)nch;
+        ga.C = C;
+        ga.nw = nw;
+        ga.M = p->M;
+        ga.order = p->order;
+        ga.cell = p->cell;
+        ga.frac = p->frac;
+        ga.toff = p->toff;
+        ga.y = mode == 0 ? y + b0 * C * p->M : nullptr;
+        ga.v = mode == 1 ? v + b0 * C * p->M : nullptr;
+        ga.domega = dom;
+        KBN_LAUNCH(mode == 0 ? KBN_CLASS_GATHER : KBN_CLASS_GATHER_JAC, kbn_launch_gather(geom, ga, mode, stream), "gather");
+    }
+    return KBN_OK;
+}
+
+// Adjoint pipeline: spread, inverse FFT passes with cropping, scaling and
+// conj(coil map) summed over coils.
+int run_type1(kbn_plan p, int B, int C, const float2 *y, const float2 *smaps, float2 *x,
+              hipStream_t stream) {
+    const int D = p->D;
+    const int64_t gsz = p->gsize();
+    const int64_t per_img = (int64_t)C * gsz * (int64_t)sizeof(float2) * 2;
+    int64_t bc = std::max<int64_t>(1, std::min<int64_t>(B, p->max_ws / per_img));
+    int rc = ensure_ws(p, bc * per_img, stream);
+    if (rc != KBN_OK) return rc;
+    float2 *bufA = p->ws;
+    float2 *bufB = p->ws + bc * C * gsz;
+    const int64_t R0 = img_rows(p);
+    const int Nl = p->N[D - 1];
+    const KbnGeom geom = p->geom();
+    for (int64_t b0 = 0; b0 < B; b0 += bc) {
+        const int64_t nb = std::min<int64_t>(bc, B - b0);
+        const int64_t nch = nb * C;
+        KbnSpreadArgs sa;
+        sa.y = y + b0 * C * p->M;
+        sa.grid = bufA;
+        sa.gsize = gsz;
+        sa.nch = (int)nch;
+        sa.M = p->M;
+        sa.order = p->order;
+        sa.cell = p->cell;
+        sa.frac = p->frac;
+        sa.toff = p->toff;
+        KBN_LAUNCH(KBN_CLASS_SPREAD, kbn_launch_spread(geom, sa, stream), "spread");
+        float2 *cur = bufA, *nxt = bufB;
+        for (int d = 0; d + 1 < D; ++d) {
+            int64_t outer = nch, inner = 1;
+            for (int e = 0; e < d; ++e) outer *= p->N[e];
+            for (int e = d + 1; e < D; ++e) inner *= p->K[e];
+            KbnMidPassArgs ma;
+            ma.in = cur;
+            ma.out = nxt;
+            ma.outer = outer;
+            ma.nin = p->K[d];
+            ma.nout = p->N[d];
+            ma.inner = (int)inner;
+            ma.pad_in = 0;
+            ma.crop_out = 1;
+            KBN_LAUNCH(KBN_CLASS_FFT_MID_INV, kbn_launch_mid_pass(ma, p->rad[d], p->tw[d], 1, p->maxe, stream), "mid pass");
+            std::swap(cur, nxt);
+        }
+        KbnLastAdjArgs la;
+        la.in = cur;
+        la.smaps = smaps;
+        la.x = x + b0 * R0 * Nl;
+        la.nlines = nb * R0;
+        la.R0 = (int)R0;
+        la.Nl = Nl;
+        la.C = C;
+        la.accumulate = 0;
+        la.D = D;
+        for (int d = 0; d < KBN_MAX_D; ++d) {
+            la.N[d] = p->N[d];
+            la.deap[d] = p->deap[d];
+        }
+        KBN_LAUNCH(KBN_CLASS_FFT_LAST_ADJ, kbn_launch_last_adj(la, p->rad[D - 1], p->tw[D - 1], p->maxe, stream),
+                   "last adjoint pass");
+    }
+    return KBN_OK;
+}
+
+int run_jac(kbn_plan p, int B, int C, const float2 *img, const float2 *smaps, const float2 *v,
+            float *dom, int accumulate, hipStream_t stream) {
+    if (!dom && p->M > 0) return fail(KBN_ERR_INVALID_ARG, "null domega");
+    if (!accumulate) KBN_LAUNCH(KBN_CLASS_FILL, kbn_launch_fill(dom, p->M * p->D, 0.f, stream), "fill");
+    if (p->M == 0) return KBN_OK;
+    return run_type2(p, B, C, p->D, 1, img, smaps, 1, nullptr, v, dom, stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts) {
+    if (!out) return fail(KBN_ERR_INVALID_ARG, "null output pointer");
+    *out = nullptr;
+    if (D < 1 || D > KBN_MAX_D || !N) return fail(KBN_ERR_INVALID_ARG, "D must be 1..3");
+    kbn_opts o;
+    std::memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    const double sigma = o.sigma == 0.0 ? 2.0 : o.sigma;
+    const int J = o.J == 0 ? 6 : o.J;
+    if (!(sigma >= 1.0) || sigma > 16.0) return fail(KBN_ERR_INVALID_ARG, "sigma must be in [1, 16]");
+    if (J < 2 || J > KBN_MAX_J) return fail(KBN_ERR_INVALID_ARG, "J must be in 2..8");
+    const double rad = (J / sigma) * (J / sigma) * (sigma - 0.5) * (sigma - 0.5) - 0.8;
+    if (!(rad > 0.0)) return fail(KBN_ERR_INVALID_ARG, "window shape undefined for this (J, sigma)");
+    kbn_plan p = new (std::nothrow) kbn_plan_s();
+    if (!p) return fail(KBN_ERR_OOM, "host allocation failed");
+    p->D = D;
+    p->J = J;
+    p->sigma = sigma;
+    p->beta = M_PI * std::sqrt(rad);
+    p->max_ws = o.max_workspace > 0 ? o.max_workspace : (int64_t)4 << 30;
+    if (const char *e = std::getenv("KBN_MAXE")) p->maxe = std::atoi(e) == 32 ? 32 : 16;
+    const int deftile = D == 1 ? 256 : (D == 2 ? 32 : 16);
+    int64_t ntiles = 1;
+    for (int d = 0; d < D; ++d) {
+        if (N[d] < 1 || N[d] > (1 << 20)) {
+            free_plan(p);
+            return fail(KBN_ERR_INVALID_ARG, "N_d must be >= 1");
+        }
+        p->N[d] = (int)N[d];
+        const int K = smooth_size(sigma * (double)N[d]);
+        if (K > KBN_MAX_K || K < 2 * J) {
+            free_plan(p);
+            return fail(KBN_ERR_UNSUPPORTED, "oversampled size K_d = " + std::to_string(K) +
+                                                 " outside [2J, " + std::to_string(KBN_MAX_K) + "]");
+        }
+        p->K[d] = K;
+        p->scale[d] = (double)K * (1.0 / (2.0 * M_PI));
+        int T = o.tile[d] > 0 ? o.tile[d] : deftile;
+        if (T < J) T = J;
+        if (T > K) T = K;
+        while (T > J && K % T != 0 && K % T < J) --T;
+        if (K % T != 0 && K % T < J) T = K;
+        p->T[d] = T;
+        p->nt[d] = (K + T - 1) / T;
+        ntiles *= p->nt[d];
+        if (!factor(K, p->rad[d])) {
+            free_plan(p);
+            return fail(KBN_ERR_UNSUPPORTED, "K_d not 7-smooth");
+        }
+    }
+    if (ntiles > KBN_MAX_TILES) {
+        free_plan(p);
+        return fail(KBN_ERR_UNSUPPORTED, "too many tiles; use larger tiles");
+    }
+    p->ntiles = (int)ntiles;
+
+    Window w{J, p->beta, bessel_i0(p->beta)};
+    int rc = KBN_OK;
+    for (int d = 0; d < D && rc == KBN_OK; ++d) {
+        std::vector<float> dp(p->N[d]);
+        for (int j = 0; j < p->N[d]; ++j) {
+            const double r = (double)(j - p->N[d] / 2);
+            dp[j] = (float)(1.0 / w.psi_hat(r / p->K[d]));
+        }
+        std::vector<float2> tw(p->K[d]);
+        for (int k = 0; k < p->K[d]; ++k) {
+            const double a = 2.0 * M_PI * (double)k / (double)p->K[d];
+            tw[k] = make_float2((float)std::cos(a), (float)-std::sin(a));
+        }
+        rc = dev_alloc(&p->deap[d], p->N[d]);
+        if (rc == KBN_OK) rc = dev_alloc(&p->tw[d], p->K[d]);
+        if (rc == KBN_OK && hipMemcpy(p->deap[d], dp.data(), sizeof(float) * dp.size(),
+                                      hipMemcpyHostToDevice) != hipSuccess)
+            rc = fail(KBN_ERR_HIP, "hipMemcpy (scaling factors)");
+        if (rc == KBN_OK && hipMemcpy(p->tw[d], tw.data(), sizeof(float2) * tw.size(),
+                                      hipMemcpyHostToDevice) != hipSuccess)
+            rc = fail(KBN_ERR_HIP, "hipMemcpy (twiddles)");
+    }
+    if (rc == KBN_OK) {
+        std::vector<float> cf = window_polys(w);
+        rc = dev_alloc(&p->coef, (int64_t)cf.size());
+        if (rc == KBN_OK && hipMemcpy(p->coef, cf.data(), sizeof(float) * cf.size(),
+                                      hipMemcpyHostToDevice) != hipSuccess)
+            rc = fail(KBN_ERR_HIP, "hipMemcpy (window)");
+    }
+    if (rc == KBN_OK) rc = dev_alloc(&p->flag, 1);
+    if (rc == KBN_OK && hipMemset(p->flag, 0, sizeof(int)) != hipSuccess)
+        rc = fail(KBN_ERR_HIP, "hipMemset (flag)");
+    if (rc == KBN_OK) rc = dev_alloc(&p->toff, (int64_t)p->ntiles + 2);
+    if (rc != KBN_OK) {
+        free_plan(p);
+        return rc;
+    }
+    *out = p;
+    return KBN_OK;
+}
+
+int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream_) {
+    hipStream_t stream = (hipStream_t)stream_;
+    if (!p) return fail(KBN_ERR_INVALID_ARG, "null plan");
+    if (M < 0 || M > 2147483647LL) return fail(KBN_ERR_INVALID_ARG, "M out of range");
+    if (M > 0 && !omega) return fail(KBN_ERR_INVALID_ARG, "null omega");
+    const int nbins = p->ntiles + 1;
+    int64_t chunk = std::max<int64_t>(256, (M * nbins + (1 << 18) - 1) >> 18);
+    chunk = (chunk + 63) / 64 * 64;
+    const int64_t nchunks = M > 0 ? (M + chunk - 1) / chunk : 0;
+    if (M > p->Mcap || nchunks * nbins > p->counts_cap) {
+        KBN_HIP(hipStreamSynchronize(stream));
+        free_points(p);
+        const int64_t cap = std::max<int64_t>(M, 1);
+        const int D = p->D;
+        int rc = dev_alloc(&p->cell_tmp, cap * D);
+        if (rc == KBN_OK) rc = dev_alloc(&p->frac_tmp, cap * D);
+        if (rc == KBN_OK) rc = dev_alloc(&p->tile, cap);
+        if (rc == KBN_OK) rc = dev_alloc(&p->order, cap);
+        if (rc == KBN_OK) rc = dev_alloc(&p->cell, cap * D);
+        if (rc == KBN_OK) rc = dev_alloc(&p->frac, cap * D);
+        if (rc == KBN_OK) rc = dev_alloc(&p->counts, std::max<int64_t>(nchunks * nbins, 1));
+        if (rc != KBN_OK) {
+            free_points(p);
+            p->M = -1;
+            return rc;
+        }
+        p->Mcap = cap;
+        p->counts_cap = std::max<int64_t>(nchunks * nbins, 1);
+    }
+    KbnPointsBufs b;
+    b.cell_tmp = p->cell_tmp;
+    b.frac_tmp = p->frac_tmp;
+    b.tile = p->tile;
+    b.counts = p->counts;
+    b.order = p->order;
+    b.cell = p->cell;
+    b.frac = p->frac;
+    b.toff = p->toff;
+    b.flag = p->flag;
+    KBN_LAUNCH(KBN_CLASS_INDEX, kbn_launch_points(p->D, M, omega, p->scale, p->K, p->T, p->nt, p->ntiles,
+                                 (int)chunk, (int)nchunks, b, stream),
+               "index pass");
+    p->M = M;
+    return KBN_OK;
+}
+
+int kbn_forward(kbn_plan p, int B, int C, const void *x, const void *smaps, void *y,
+                void *stream) {
+    int rc = check_common(p, B, C, x, smaps, y);
+    if (rc != KBN_OK) return rc;
+    if (p->M == 0) return KBN_OK;
+    return run_type2(p, B, C, 1, 0, (const float2 *)x, (const float2 *)smaps, 0, (float2 *)y,
+                     nullptr, nullptr, (hipStream_t)stream);
+}
+
+int kbn_adjoint(kbn_plan p, int B, int C, const void *y, const void *smaps, void *x,
+                void *stream) {
+    int rc = check_common(p, B, C, x, smaps, y);
+    if (rc != KBN_OK) return rc;
+    return run_type1(p, B, C, (const float2 *)y, (const float2 *)smaps, (float2 *)x,
+                     (hipStream_t)stream);
+}
+
+int kbn_jac_omega_fwd(kbn_plan p, int B, int C, const void *x, const void *smaps, const void *g,
+                      float *domega, int accumulate, void *stream) {
+    int rc = check_common(p, B, C, x, smaps, g);
+    if (rc != KBN_OK) return rc;
+    return run_jac(p, B, C, (const float2 *)x, (const float2 *)smaps, (const float2 *)g, domega,
+                   accumulate, (hipStream_t)stream);
+}
+
+int kbn_jac_omega_adj(kbn_plan p, int B, int C, const void *y, const void *smaps, const void *g,
+                      float *domega, int accumulate, void *stream) {
+    int rc = check_common(p, B, C, g, smaps, y);
+    if (rc != KBN_OK) return rc;
+    return run_jac(p, B, C, (const float2 *)g, (const float2 *)smaps, (const float2 *)y, domega,
+                   accumulate, (hipStream_t)stream);
+}
+
+int kbn_jac_x(kbn_plan p, int op, int B, int C, const void *g, const void *smaps, void *out,
+              void *stream) {
+    if (op == KBN_OP_FORWARD) return kbn_adjoint(p, B, C, g, smaps, out, stream);
+    if (op == KBN_OP_ADJOINT) return kbn_forward(p, B, C, g, smaps, out, stream);
+    return fail(KBN_ERR_INVALID_ARG, "unknown op");
+}
+
+int kbn_plan_info(kbn_plan p, int64_t *K, int *tile, int *ntiles, double *beta, int64_t *M,
+                  int64_t *workspace_bytes) {
+    if (!p) return fail(KBN_ERR_INVALID_ARG, "null plan");
+    for (int d = 0; d < p->D; ++d) {
+        if (K) K[d] = p->K[d];
+        if (tile) tile[d] = p->T[d];
+    }
+    if (ntiles) *ntiles = p->ntiles;
+    if (beta) *beta = p->beta;
+    if (M) *M = p->M < 0 ? 0 : p->M;
+    if (workspace_bytes) *workspace_bytes = p->ws_bytes;
+    return KBN_OK;
+}
+
+int kbn_get_points(kbn_plan p, int *order, int *cell, float *frac, int *offsets, void *stream_) {
+    hipStream_t stream = (hipStream_t)stream_;
+    if (!p) return fail(KBN_ERR_INVALID_ARG, "null plan");
+    if (p->M < 0) return fail(KBN_ERR_NO_POINTS, "kbn_set_points has not been called");
+    const int64_t M = p->M;
+    if (M > 0) {
+        if (order) KBN_HIP(hipMemcpyAsync(order, p->order, sizeof(int) * M, hipMemcpyDeviceToDevice, stream));
+        if (cell)
+            KBN_HIP(hipMemcpyAsync(cell, p->cell, sizeof(int) * M * p->D, hipMemcpyDeviceToDevice, stream));
+        if (frac)
+            KBN_HIP(hipMemcpyAsync(frac, p->frac, sizeof(float) * M * p->D, hipMemcpyDeviceToDevice, stream));
+    }
+    if (offsets)
+        KBN_HIP(hipMemcpyAsync(offsets, p->toff, sizeof(int) * (p->ntiles + 2),
+                               hipMemcpyDeviceToDevice, stream));
+    return KBN_OK;
+}
+
+int kbn_check_error(kbn_plan p, void *stream) {
+    if (!p) return fail(KBN_ERR_INVALID_ARG, "null plan");
+    KBN_HIP(hipStreamSynchronize((hipStream_t)stream));
+    int h = 0;
+    KBN_HIP(hipMemcpy(&h, p->flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (h) {
+        KBN_HIP(hipMemset(p->flag, 0, sizeof(int)));
+        return fail(KBN_ERR_NONFINITE, "non-finite or out-of-range omega");
+    }
+    return KBN_OK;
+}
+
+int kbn_plan_destroy(kbn_plan p) {
+    if (!p) return fail(KBN_ERR_INVALID_ARG, "null plan");
+    (void)hipDeviceSynchronize();
+    free_plan(p);
+    return KBN_OK;
+}
+
+int kbn_timing(kbn_plan p, int enable) {
+    if (!p) return fail(KBN_ERR_INVALID_ARG, "null plan");
+    if (enable) {
+        for (auto &t : p->pending) {
+            p->pool.push_back(t.e0);
+            p->pool.push_back(t.e1);
+        }
+        p->pending.clear();
+        for (int c = 0; c < KBN_NCLASS; ++c) {
+            p->t_ms[c] = 0.0;
+            p->t_n[c] = 0;
+        }
+    }
+    p->timing = enable != 0;
+    return KBN_OK;
+}
+
+int kbn_timing_read(kbn_plan p, int cls, int64_t *launches, double *total_ms) {
+    if (!p || cls < 0 || cls >= KBN_NCLASS) return fail(KBN_ERR_INVALID_ARG, "bad plan or class");
+    for (auto &t : p->pending) {
+        KBN_HIP(hipEventSynchronize(t.e1));
+        float ms = 0.f;
+        KBN_HIP(hipEventElapsedTime(&ms, t.e0, t.e1));
+        p->t_ms[t.cls] += ms;
+        p->t_n[t.cls] += 1;
+        p->pool.push_back(t.e0);
+        p->pool.push_back(t.e1);
+    }
+    p->pending.clear();
+    if (launches) *launches = p->t_n[cls];
+    if (total_ms) *total_ms = p->t_ms[cls];
+    return KBN_OK;
+}
+
+const char *kbn_timing_name(int cls) {
+    return (cls >= 0 && cls < KBN_NCLASS) ? kClassNames[cls] : nullptr;
+}
+
+const char *kbn_strerror(int code) {
+    switch (code) {
+        case KBN_OK: return "success";
+        case KBN_ERR_INVALID_ARG: return "invalid argument";
+        case KBN_ERR_UNSUPPORTED: return "unsupported size";
+        case KBN_ERR_OOM: return "out of device memory";
+        case KBN_ERR_HIP: return "HIP runtime error";
+        case KBN_ERR_NONFINITE: return "non-finite sample location";
+        case KBN_ERR_NO_POINTS: return "no sample locations set";
+        default: return "unknown error";
+    }
+}
+
+const char *kbn_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,224 @@
+"""Torch-facing wrapper of the C ABI: one plan per image shape.
+
+All arithmetic runs in the HIP library; this module checks tensor
+arguments, allocates outputs with PyTorch and passes device pointers and the
+current HIP stream through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import check
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class KbNufft:
+    """Kaiser-Bessel NUFFT plan for images of shape ``N`` on one GPU.
+
+    Shapes: omega [M, D] float32; images [B, *N] complex64; coil maps
+    [C, *N] complex64; k-space [B, C, M] complex64.
+    """
+
+    def __init__(self, N: Sequence[int], sigma: float = 2.0, J: int = 6,
+                 tile: Optional[Sequence[int]] = None, max_workspace: int = 0,
+                 device=None):
+        self.N = tuple(int(n) for n in N)
+        self.D = len(self.N)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        L = _lib.lib()
+        opts = _lib.KbnOpts()
+        opts.sigma = float(sigma)
+        opts.J = int(J)
+        if tile is not None:
+            for d, t in enumerate(tile):
+                opts.tile[d] = int(t)
+        opts.max_workspace = int(max_workspace)
+        arr = (ctypes.c_int64 * self.D)(*self.N)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(L.kbn_plan_create(ctypes.byref(h), self.D, arr, ctypes.byref(opts)), "kbn_plan_create")
+        self._h = h
+        self.M = None
+        info = self.info()
+        self.K = info["K"]
+        self.beta = info["beta"]
+        self.tile = info["tile"]
+        self.ntiles = info["ntiles"]
+
+    # -- lifecycle -------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.lib().kbn_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- argument checks ---------------------------------------------------
+    def _img(self, x: torch.Tensor, name: str) -> torch.Tensor:
+        if x.dtype != torch.complex64 or x.device != self.device:
+            raise TypeError(f"{name} must be complex64 on {self.device}")
+        if tuple(x.shape[-self.D:]) != self.N:
+            raise ValueError(f"{name} trailing shape {tuple(x.shape[-self.D:])} != {self.N}")
+        return x.reshape((-1,) + self.N).contiguous()
+
+    def _ksp(self, y: torch.Tensor, B: int, C: int, name: str) -> torch.Tensor:
+        if y.dtype != torch.complex64 or y.device != self.device:
+            raise TypeError(f"{name} must be complex64 on {self.device}")
+        if y.numel() != B * C * self.M:
+            raise ValueError(f"{name} has {y.numel()} elements, expected B*C*M = {B * C * self.M}")
+        return y.reshape(B, C, self.M).contiguous()
+
+    def _maps(self, smaps):
+        if smaps is None:
+            return None, 1
+        s = self._img(smaps, "smaps")
+        return s, s.shape[0]
+
+    def _need_points(self):
+        if self.M is None:
+            raise RuntimeError("set_points() has not been called")
+
+    # -- C ABI calls -------------------------------------------------------
+    def set_points(self, omega: torch.Tensor):
+        if omega.dtype != torch.float32 or omega.device != self.device or omega.dim() != 2 \
+                or omega.shape[1] != self.D:
+            raise TypeError(f"omega must be float32 [M, {self.D}] on {self.device}")
+        om = omega.contiguous()
+        check(_lib.lib().kbn_set_points(self._h, om.shape[0], _ptr(om), _stream(self.device)),
+              "kbn_set_points")
+        self.M = int(om.shape[0])
+        self._omega_keep = om  # keep alive until the stream has consumed it
+        return self
+
+    def forward(self, x: torch.Tensor, smaps: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """y[b, c] = A(omega)(s_c * x_b); returns [B, C, M]."""
+        self._need_points()
+        xx = self._img(x, "x")
+        s, C = self._maps(smaps)
+        B = xx.shape[0]
+        y = torch.empty((B, C, self.M), dtype=torch.complex64, device=self.device)
+        check(_lib.lib().kbn_forward(self._h, B, C, _ptr(xx), _ptr(s), _ptr(y), _stream(self.device)),
+              "kbn_forward")
+        return y
+
+    def adjoint(self, y: torch.Tensor, smaps: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """x_b = sum_c conj(s_c) A(omega)^H y[b, c]; y [B, C, M] -> [B, *N]."""
+        self._need_points()
+        s, C = self._maps(smaps)
+        B = y.numel() // (C * self.M) if self.M else y.shape[0]
+        yy = self._ksp(y, B, C, "y")
+        x = torch.empty((B,) + self.N, dtype=torch.complex64, device=self.device)
+        check(_lib.lib().kbn_adjoint(self._h, B, C, _ptr(yy), _ptr(s), _ptr(x), _stream(self.device)),
+              "kbn_adjoint")
+        return x
+
+    def jac_omega_fwd(self, x: torch.Tensor, g: torch.Tensor, smaps=None, out=None,
+                      accumulate: bool = False) -> torch.Tensor:
+        """dL/domega for y = E x given g = dL/dy; returns [M, D] float32."""
+        self._need_points()
+        xx = self._img(x, "x")
+        s, C = self._maps(smaps)
+        B = xx.shape[0]
+        gg = self._ksp(g, B, C, "g")
+        dom = out if out is not None else torch.empty((self.M, self.D), dtype=torch.float32, device=self.device)
+        check(_lib.lib().kbn_jac_omega_fwd(self._h, B, C, _ptr(xx), _ptr(s), _ptr(gg), _ptr(dom),
+                                           int(accumulate), _stream(self.device)), "kbn_jac_omega_fwd")
+        return dom
+
+    def jac_omega_adj(self, y: torch.Tensor, g: torch.Tensor, smaps=None, out=None,
+                      accumulate: bool = False) -> torch.Tensor:
+        """dL/domega for x = E^H y given g = dL/dx; returns [M, D] float32."""
+        self._need_points()
+        gg = self._img(g, "g")
+        s, C = self._maps(smaps)
+        B = gg.shape[0]
+        yy = self._ksp(y, B, C, "y")
+        dom = out if out is not None else torch.empty((self.M, self.D), dtype=torch.float32, device=self.device)
+        check(_lib.lib().kbn_jac_omega_adj(self._h, B, C, _ptr(yy), _ptr(s), _ptr(gg), _ptr(dom),
+                                           int(accumulate), _stream(self.device)), "kbn_jac_omega_adj")
+        return dom
+
+    def jac_x(self, op: int, g: torch.Tensor, smaps=None) -> torch.Tensor:
+        """Gradient w.r.t. the linear input: E^H g (op FORWARD) or E g (op ADJOINT)."""
+        self._need_points()
+        s, C = self._maps(smaps)
+        if op == _lib.KBN_OP_FORWARD:
+            B = g.numel() // (C * self.M)
+            gg = self._ksp(g, B, C, "g")
+            out = torch.empty((B,) + self.N, dtype=torch.complex64, device=self.device)
+        elif op == _lib.KBN_OP_ADJOINT:
+            gg = self._img(g, "g")
+            B = gg.shape[0]
+            out = torch.empty((B, C, self.M), dtype=torch.complex64, device=self.device)
+        else:
+            raise ValueError("op must be KBN_OP_FORWARD or KBN_OP_ADJOINT")
+        check(_lib.lib().kbn_jac_x(self._h, op, B, C, _ptr(gg), _ptr(s), _ptr(out), _stream(self.device)),
+              "kbn_jac_x")
+        return out
+
+    def info(self) -> dict:
+        K = (ctypes.c_int64 * 3)()
+        T = (ctypes.c_int * 3)()
+        nt = ctypes.c_int()
+        beta = ctypes.c_double()
+        M = ctypes.c_int64()
+        ws = ctypes.c_int64()
+        check(_lib.lib().kbn_plan_info(self._h, K, T, ctypes.byref(nt), ctypes.byref(beta),
+                                       ctypes.byref(M), ctypes.byref(ws)), "kbn_plan_info")
+        return {"K": tuple(K[d] for d in range(self.D)), "tile": tuple(T[d] for d in range(self.D)),
+                "ntiles": nt.value, "beta": beta.value, "M": M.value, "workspace_bytes": ws.value}
+
+    def get_points(self) -> dict:
+        """Index pass results: sorted order, cells, fractions, tile offsets."""
+        self._need_points()
+        M, D = self.M, self.D
+        dev = self.device
+        order = torch.empty(max(M, 1), dtype=torch.int32, device=dev)
+        cell = torch.empty((D, max(M, 1)), dtype=torch.int32, device=dev)
+        frac = torch.empty((D, max(M, 1)), dtype=torch.float32, device=dev)
+        off = torch.empty(self.ntiles + 2, dtype=torch.int32, device=dev)
+        check(_lib.lib().kbn_get_points(self._h, _ptr(order), _ptr(cell), _ptr(frac), _ptr(off),
+                                        _stream(self.device)), "kbn_get_points")
+        return {"order": order[:M], "cell": cell[:, :M], "frac": frac[:, :M], "offsets": off}
+
+    def timing(self, enable: bool):
+        """Start (clearing counters) or stop per-kernel event timing."""
+        check(_lib.lib().kbn_timing(self._h, int(bool(enable))), "kbn_timing")
+
+    def timing_read(self) -> dict:
+        """{class name: (launches, total ms)} of the timed launches so far."""
+        L = _lib.lib()
+        out = {}
+        c = 0
+        while True:
+            name = L.kbn_timing_name(c)
+            if name is None:
+                break
+            n = ctypes.c_int64()
+            ms = ctypes.c_double()
+            check(L.kbn_timing_read(self._h, c, ctypes.byref(n), ctypes.byref(ms)), "kbn_timing_read")
+            out[name.decode()] = (n.value, ms.value)
+            c += 1
+        return out
+
+    def check_error(self) -> int:
+        """Synchronise and return the sticky non-finite flag (0 or KBN_ERR_NONFINITE)."""
+        rc = _lib.lib().kbn_check_error(self._h, _stream(self.device))
+        if rc not in (_lib.KBN_OK, _lib.KBN_ERR_NONFINITE):
+            check(rc, "kbn_check_error")
+        return rc

@@ -283,6 +283,12 @@ def test_points_ref_properties():
     assert list(perm) == expect
     for t in range(nt):
         assert np.all(tid[perm[off[t]:off[t + 1]]] == t)
-    bad_om = np.array([[np.nan, 0.0], [0.0, np.inf], [1e30, 0.0]], dtype=np.float32)
+    assert off[nt] == off[nt + 1] == len(tid)
+    bad_om = np.array([[0.5, 0.5], [np.nan, 0.0], [0.0, np.inf], [1e30, 0.0], [0.25, 0.0]],
+                      dtype=np.float32)
     c2, f2, b2 = points_ref.cells(bad_om, K)
-    assert b2.all() and not c2.any() and not f2.any()
+    assert list(b2) == [False, True, True, True, False]
+    assert not c2[b2].any() and not f2[b2].any()
+    t2, nt2 = points_ref.tiles(c2, K, T, b2)
+    p2, o2 = points_ref.tile_order(t2, nt2)
+    assert list(p2[-3:]) == [1, 2, 3] and o2[nt2] == 2 and o2[nt2 + 1] == 5
