@@ -207,8 +207,8 @@ int kbn_check_error(kbn_plan p, void *stream);
  * events and returns, for kernel class `cls`, the number of timed launches
  * and their summed durations in milliseconds.  kbn_timing_name gives the
  * class name ("index", "fft_first", "fft_mid_fwd", "fft_mid_inv",
- * "fft_last_adj", "gather", "gather_jac", "spread", "fill"), or NULL for cls
- * past the last class.
+ * "fft_last_adj", "gather", "gather_jac", "spread"), or NULL for cls past
+ * the last class.
  * Errors: INVALID_ARG (null plan, bad class), HIP.
  */
 int kbn_timing(kbn_plan p, int enable);

@@ -21,6 +21,8 @@
 // grid needs neither zero-initialisation nor global atomics.
 #include "kbn_internal.h"
 
+#include <algorithm>
+
 namespace {
 
 __device__ __forceinline__ void tap_origin(int J, int cell, float frac, int &start, float &f) {
@@ -52,6 +54,160 @@ __device__ __forceinline__ int wrapk(int i, int K) {  // i in [-K, 2K)
     return i < 0 ? i + K : (i >= K ? i - K : i);
 }
 
+// Tap reach of a point in cell c: taps lie in [c - LO, c + HI].
+template <int J>
+struct Reach {
+    static constexpr int LO = (J & 1) ? J / 2 : J / 2 - 1;
+    static constexpr int HI = (J & 1) ? J / 2 + 1 : J / 2;
+};
+
+// Staged gather: one workgroup per subproblem (<= KBN_SUB sorted points of
+// one tile).  For each channel the tile's grid region (tile plus the tap
+// reach) is loaded into LDS with coalesced reads, then every thread
+// interpolates its point from LDS.  Subproblems of the extra tile id ntiles
+// hold the flagged points, whose outputs are NaN.
+template <int D, int J, int MODE>
+__global__ void __launch_bounds__(KBN_BLOCK) k_gather_staged(KbnGeom g, KbnGatherArgs a, int cg) {
+    extern __shared__ float2 reg[];
+    const int s = blockIdx.x;
+    if (s >= *a.nsub) return;
+    const int tile = a.subs[2 * s];
+    const int p0 = a.subs[2 * s + 1];
+    const int ch0 = blockIdx.y * cg;
+    const int ch1 = min(ch0 + cg, a.nch);
+    const float qnan = __builtin_nanf("");
+    if (tile == g.ntiles) {  // flagged points
+        const int p = p0 + threadIdx.x;
+        if (p < a.M) {
+            const int q = a.order[p];
+            if (MODE == 0) {
+                for (int ch = ch0; ch < ch1; ++ch) a.y[(int64_t)ch * a.M + q] = make_float2(qnan, qnan);
+            } else {
+                float *part = a.part + (int64_t)blockIdx.y * a.M * D;
+                for (int d = 0; d < D; ++d) part[(int64_t)q * D + d] = qnan;
+            }
+        }
+        return;
+    }
+    const int p1 = min(p0 + KBN_SUB, a.toff[tile + 1]);
+    int o[D], E[D];
+    {
+        int rem = tile;
+#pragma unroll
+        for (int d = D - 1; d >= 0; --d) {
+            const int tc = rem % g.nt[d];
+            rem /= g.nt[d];
+            const int a0 = tc * g.T[d];
+            const int te = min(g.T[d], g.K[d] - a0);
+            o[d] = a0 - Reach<J>::LO;
+            E[d] = te + Reach<J>::LO + Reach<J>::HI;
+        }
+    }
+    int R = 1;
+#pragma unroll
+    for (int d = 0; d < D; ++d) R *= E[d];
+
+    const int p = p0 + (int)threadIdx.x;
+    const bool act = p < p1;
+    int q = 0;
+    float w[D][J];
+    int base = 0;  // region offset of the point's first tap
+    if (act) {
+        q = a.order[p];
+        int stride = 1;
+#pragma unroll
+        for (int d = D - 1; d >= 0; --d) {
+            int start;
+            float f;
+            tap_origin(J, a.cell[d * a.M + p], a.frac[d * a.M + p], start, f);
+            kb_weights<J>(f, g.coef, w[d]);
+            base += (start - o[d]) * stride;
+            stride *= E[d];
+        }
+    }
+    float jac[KBN_MAX_D] = {0.f, 0.f, 0.f};
+    for (int ch = ch0; ch < ch1; ++ch) {
+        float2 vv = make_float2(0.f, 0.f);
+        if (MODE == 1 && act) vv = a.v[(int64_t)(ch / a.nw) * a.M + q];
+        const float2 *G = a.grid + (int64_t)ch * a.gsize;
+        for (int i = threadIdx.x; i < R; i += KBN_BLOCK) {
+            int rem = i;
+            int64_t gi = 0, gstride = 1;
+#pragma unroll
+            for (int d = D - 1; d >= 0; --d) {
+                const int e = rem % E[d];
+                rem /= E[d];
+                gi += (int64_t)wrapk(o[d] + e, g.K[d]) * gstride;
+                gstride *= g.K[d];
+            }
+            reg[i] = G[gi];
+        }
+        __syncthreads();
+        if (act) {
+            float2 acc = make_float2(0.f, 0.f);
+            if (D == 1) {
+#pragma unroll
+                for (int j0 = 0; j0 < J; ++j0) {
+                    const float2 v = reg[base + j0];
+                    acc.x = fmaf(w[0][j0], v.x, acc.x);
+                    acc.y = fmaf(w[0][j0], v.y, acc.y);
+                }
+            } else if (D == 2) {
+#pragma unroll
+                for (int j0 = 0; j0 < J; ++j0) {
+                    const float2 *row = reg + base + j0 * E[D - 1];
+                    float2 t = make_float2(0.f, 0.f);
+#pragma unroll
+                    for (int j1 = 0; j1 < J; ++j1) {
+                        const float2 v = row[j1];
+                        t.x = fmaf(w[1][j1], v.x, t.x);
+                        t.y = fmaf(w[1][j1], v.y, t.y);
+                    }
+                    acc.x = fmaf(w[0][j0], t.x, acc.x);
+                    acc.y = fmaf(w[0][j0], t.y, acc.y);
+                }
+            } else {
+#pragma unroll
+                for (int j0 = 0; j0 < J; ++j0) {
+                    float2 t1 = make_float2(0.f, 0.f);
+#pragma unroll
+                    for (int j1 = 0; j1 < J; ++j1) {
+                        const float2 *row = reg + base + (j0 * E[1] + j1) * E[2];
+                        float2 t = make_float2(0.f, 0.f);
+#pragma unroll
+                        for (int j2 = 0; j2 < J; ++j2) {
+                            const float2 v = row[j2];
+                            t.x = fmaf(w[2][j2], v.x, t.x);
+                            t.y = fmaf(w[2][j2], v.y, t.y);
+                        }
+                        t1.x = fmaf(w[1][j1], t.x, t1.x);
+                        t1.y = fmaf(w[1][j1], t.y, t1.y);
+                    }
+                    acc.x = fmaf(w[0][j0], t1.x, acc.x);
+                    acc.y = fmaf(w[0][j0], t1.y, acc.y);
+                }
+            }
+            if (MODE == 0) {
+                a.y[(int64_t)ch * a.M + q] = acc;
+            } else {
+                const int wd = ch % a.nw;
+                const float im = acc.y * vv.x - acc.x * vv.y;  // Im{acc conj(v)}
+#pragma unroll
+                for (int d = 0; d < D; ++d)
+                    if (wd == d) jac[d] += im;
+            }
+        }
+        __syncthreads();
+    }
+    if (MODE == 1 && act) {
+        float *part = a.part + (int64_t)blockIdx.y * a.M * D;
+#pragma unroll
+        for (int d = 0; d < D; ++d) part[(int64_t)q * D + d] = jac[d];
+    }
+}
+
+// Direct gather (no staging): one thread per sorted point reads its taps from
+// the grid in global memory; used when a staged region does not fit in LDS.
 template <int D, int J, int MODE>
 __global__ void __launch_bounds__(KBN_BLOCK) k_gather(KbnGeom g, KbnGatherArgs a, int cg) {
     const int64_t p = (int64_t)blockIdx.x * KBN_BLOCK + threadIdx.x;
@@ -134,144 +290,176 @@ __global__ void __launch_bounds__(KBN_BLOCK) k_gather(KbnGeom g, KbnGatherArgs a
             const int wd = ch % a.nw;
             const int64_t bc = ch / a.nw;
             const float2 v = a.v[bc * a.M + q];
-            jac[wd] += acc.y * v.x - acc.x * v.y;  // Im{acc conj(v)}
+            const float im = acc.y * v.x - acc.x * v.y;  // Im{acc conj(v)}
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+                if (wd == d) jac[d] += im;
         }
     }
     if (MODE == 1) {
+        float *part = a.part + (int64_t)blockIdx.y * a.M * D;
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            float val = bad ? __builtin_nanf("") : jac[d];
-            atomicAdd(&a.domega[(int64_t)q * D + d], val);
-        }
+        for (int d = 0; d < D; ++d) part[(int64_t)q * D + d] = bad ? __builtin_nanf("") : jac[d];
     }
 }
 
-// Distinct tiles along one axis whose samples can reach [a0, a0 + te).
-// A sample in cell c touches cells [c - lo, c + hi] (lo = J/2 - 1 and
-// hi = J/2 for even J; lo = hi = J/2 for odd J, covering both tap origins),
-// so the contributing cells are [a0 - hi, a0 + te - 1 + lo], modulo K.
-__device__ __forceinline__ int axis_neighbours(int a0, int te, int K, int T, int J, int *out) {
-    const int lo = (J & 1) ? J / 2 : J / 2 - 1;
-    const int hi = J / 2;
-    int cur = a0 - hi;
-    if (cur < 0) cur += K;
-    int remaining = te + lo + hi;
-    int n = 0;
-    while (remaining > 0 && n < 4) {
-        const int t = cur / T;
-        bool seen = false;
-        for (int i = 0; i < n; ++i) seen |= out[i] == t;
-        if (!seen) out[n++] = t;
-        int tend = (t + 1) * T;
-        if (tend > K) tend = K;
-        remaining -= tend - cur;
-        cur = tend == K ? 0 : tend;
-    }
-    return n;
-}
+// LDS accumulator pitch of a tile axis: odd for every axis but the first,
+// so that lanes stepping along any axis hit distinct LDS banks.
+__host__ __device__ inline int acc_pitch(int d, int te) { return d == 0 ? te : (te | 1); }
 
-template <int D, int J>
-__global__ void __launch_bounds__(KBN_BLOCK) k_spread(KbnGeom g, KbnSpreadArgs a, int cg) {
-    extern __shared__ float lacc[];  // [cg][te_0]...[te_{D-1}] complex, interleaved
-    const int tile = blockIdx.x;
-    int tc[KBN_MAX_D], a0[KBN_MAX_D], te[KBN_MAX_D];
+// Channel plane stride (in float2) of the spread accumulator: padded so that
+// consecutive planes start 12 LDS banks apart.
+__host__ __device__ inline int spread_plane(int psize) { return psize + ((6 - psize) % 32 + 32) % 32; }
+
+// Owner-computes spread.  Workgroup = (owner tile, channel group); the
+// samples reaching the tile come from a precomputed list (index pass).  For a
+// batch of list entries the workgroup stages in LDS each sample's local tap
+// origin, its window weights and its k-space values; then every lane of a
+// wave owns one (trailing tap, channel) pair and, entry after entry, adds its
+// product into the tile accumulator with a plain LDS read-modify-write.  For
+// one entry all lanes touch distinct cells, and waves own disjoint channels,
+// so no two lanes ever update the same cell concurrently: no atomics, and a
+// fixed accumulation order.
+//   A = 1: lanes = (tap along the last axis) x (64 / J channels)
+//   A = 2: lanes = (taps along the last two axes) x (64 / J^2 channels)
+template <int D, int J, int A>
+__global__ void __launch_bounds__(KBN_BLOCK) k_spread(KbnGeom g, KbnSpreadArgs a, int cw, int nwave) {
+    constexpr int EB = KBN_SPREAD_EB;
+    constexpr int LANES_TAP = A == 1 ? J : J * J;
+    extern __shared__ float smem[];
+    const int tile = a.otile_order[blockIdx.y];   // owner tiles, most entries first
+    const int ngroup = nwave * cw;                 // channels per workgroup
+    const int ch0 = blockIdx.x * ngroup;
+    const int nchg = min(ngroup, a.nch - ch0);
+    int a0[KBN_MAX_D], te[KBN_MAX_D], pt[KBN_MAX_D];
     {
         int rem = tile;
         for (int d = D - 1; d >= 0; --d) {
-            tc[d] = rem % g.nt[d];
-            rem /= g.nt[d];
-            a0[d] = tc[d] * g.T[d];
-            te[d] = min(g.T[d], g.K[d] - a0[d]);
+            const int tc = rem % g.nto[d];
+            rem /= g.nto[d];
+            a0[d] = tc * g.To[d];
+            te[d] = min(g.To[d], g.K[d] - a0[d]);
+            pt[d] = acc_pitch(d, te[d]);
         }
     }
-    int tsize = 1;
-    for (int d = 0; d < D; ++d) tsize *= te[d];
-    const int ch0 = blockIdx.y * cg;
-    const int nchg = min(cg, a.nch - ch0);
-    for (int i = threadIdx.x; i < 2 * nchg * tsize; i += KBN_BLOCK) lacc[i] = 0.f;
-    __syncthreads();
+    int psize = 1, tsize = 1;
+    for (int d = 0; d < D; ++d) {
+        psize *= pt[d];
+        tsize *= te[d];
+    }
+    const int plane = spread_plane(psize);         // float2 per channel plane
+    float2 *acc = reinterpret_cast<float2 *>(smem);
+    int *ent_p = reinterpret_cast<int *>(acc + (size_t)ngroup * plane);
+    int *ent_l = ent_p + EB;                       // [EB][D]
+    float *ent_w = reinterpret_cast<float *>(ent_l + EB * D);  // [EB][D][J]
+    float2 *ent_y = reinterpret_cast<float2 *>(ent_w + EB * D * J);  // [ngroup][EB + 1]
+    const int nthr = nwave * 64;
+    for (int i = threadIdx.x; i < nchg * plane; i += nthr) acc[i] = make_float2(0.f, 0.f);
 
-    int nb[KBN_MAX_D][4], nn[KBN_MAX_D];
-    for (int d = 0; d < D; ++d) nn[d] = axis_neighbours(a0[d], te[d], g.K[d], g.T[d], J, nb[d]);
-    int ncombo = 1;
-    for (int d = 0; d < D; ++d) ncombo *= nn[d];
-    for (int cmb = 0; cmb < ncombo; ++cmb) {
-        int rem = cmb, nt_id = 0;
-        for (int d = 0; d < D; ++d) {
-            const int i = rem % nn[d];
-            rem /= nn[d];
-            nt_id = nt_id * g.nt[d] + nb[d][i];
-        }
-        const int pbeg = a.toff[nt_id], pend = a.toff[nt_id + 1];
-        for (int p = pbeg + threadIdx.x; p < pend; p += KBN_BLOCK) {
-            int loc[D][J];
-            unsigned mask[D];
-            float f[D];
-            bool any = true;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int cc = lane / LANES_TAP;
+    const int jin = lane - cc * LANES_TAP;
+    const int cl = wave * cw + cc;                 // channel of this lane within the group
+    const bool lane_on = cc < cw && cl < nchg;
+    // inner-tap coordinates of this lane
+    const int jb = A == 1 ? jin : jin % J;         // last axis
+    const int ja = A == 1 ? 0 : jin / J;           // second-to-last axis (A == 2)
+
+    const int e0 = a.ooff[tile], e1 = a.ooff[tile + 1];
+    for (int eb = e0; eb < e1; eb += EB) {
+        const int n = min(EB, e1 - eb);
+        __syncthreads();  // previous batch fully consumed (and acc zeroed)
+        if ((int)threadIdx.x < n) {
+            const int t = threadIdx.x;
+            const int p = a.oent[eb + t];
+            ent_p[t] = p;
 #pragma unroll
             for (int d = 0; d < D; ++d) {
                 int start;
-                tap_origin(J, a.cell[d * a.M + p], a.frac[d * a.M + p], start, f[d]);
-                int l0 = start - a0[d];
-                if (l0 < 0) l0 += g.K[d];
-                if (l0 < 0) l0 += g.K[d];
-                mask[d] = 0u;
-#pragma unroll
-                for (int j = 0; j < J; ++j) {
-                    int l = l0 + j;
-                    if (l >= g.K[d]) l -= g.K[d];
-                    loc[d][j] = l;
-                    if (l < te[d]) mask[d] |= 1u << j;
-                }
-                any = any && mask[d] != 0u;
+                float f;
+                tap_origin(J, a.cell[d * a.M + p], a.frac[d * a.M + p], start, f);
+                int l = start - a0[d];
+                if (l < 0) l += g.K[d];
+                if (l < 0) l += g.K[d];
+                ent_l[t * D + d] = l;
+                kb_weights<J>(f, g.coef, ent_w + (t * D + d) * J);
             }
-            if (!any) continue;
-            float w[D][J];
-#pragma unroll
-            for (int d = 0; d < D; ++d) kb_weights<J>(f[d], g.coef, w[d]);
-            const int q = a.order[p];
-            for (int c = 0; c < nchg; ++c) {
-                const float2 yv = a.y[(int64_t)(ch0 + c) * a.M + q];
-                float *base = lacc + 2 * c * tsize;
-                if (D == 1) {
-#pragma unroll
-                    for (int j0 = 0; j0 < J; ++j0) {
-                        if (!(mask[0] >> j0 & 1u)) continue;
-                        float *cell = base + 2 * loc[0][j0];
-                        atomicAdd(cell, w[0][j0] * yv.x);
-                        atomicAdd(cell + 1, w[0][j0] * yv.y);
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < n * nchg; idx += nthr) {
+            const int c = idx / n;
+            const int i = idx - c * n;
+            ent_y[c * (EB + 1) + i] = a.ys[(int64_t)(ch0 + c) * a.M + ent_p[i]];
+        }
+        __syncthreads();
+        if (lane_on) {
+            float2 *accc = acc + (size_t)cl * plane;
+            const float2 *yc = ent_y + cl * (EB + 1);
+            for (int i = 0; i < n; ++i) {
+                const int *li = ent_l + i * D;
+                const float *wi = ent_w + i * D * J;
+                // trailing axis
+                int lb = li[D - 1] + jb;
+                if (lb >= g.K[D - 1]) lb -= g.K[D - 1];
+                bool in = lb < te[D - 1];
+                float wv = wi[(D - 1) * J + jb];
+                int inner = lb;
+                if (A == 2) {
+                    int la = li[D - 2] + ja;
+                    if (la >= g.K[D - 2]) la -= g.K[D - 2];
+                    in = in && la < te[D - 2];
+                    wv *= wi[(D - 2) * J + ja];
+                    inner += la * pt[D - 1];
+                }
+                const float2 yv = yc[i];
+                const float2 v = make_float2(wv * yv.x, wv * yv.y);
+                if (D - A == 0) {
+                    if (in) {
+                        float2 o = accc[inner];
+                        accc[inner] = make_float2(o.x + v.x, o.y + v.y);
                     }
-                } else if (D == 2) {
+                } else if (D - A == 1) {
+                    // all reads of this entry first (distinct rows), then the writes
+                    const int stride0 = D == 2 ? pt[1] : pt[1] * pt[2];
+                    float2 o[J];
+                    int cidx[J];
+                    bool ok[J];
 #pragma unroll
                     for (int j0 = 0; j0 < J; ++j0) {
-                        if (!(mask[0] >> j0 & 1u)) continue;
-                        const float2 r0 = make_float2(w[0][j0] * yv.x, w[0][j0] * yv.y);
-                        float *rowp = base + 2 * loc[0][j0] * te[1];
+                        int l0 = li[0] + j0;
+                        if (l0 >= g.K[0]) l0 -= g.K[0];
+                        ok[j0] = in && l0 < te[0];
+                        cidx[j0] = l0 * stride0 + inner;
+                        if (ok[j0]) o[j0] = accc[cidx[j0]];
+                    }
+#pragma unroll
+                    for (int j0 = 0; j0 < J; ++j0) {
+                        const float w0 = wi[j0];
+                        if (ok[j0]) accc[cidx[j0]] = make_float2(fmaf(w0, v.x, o[j0].x), fmaf(w0, v.y, o[j0].y));
+                    }
+                } else {  // D == 3, A == 1: one row of J cells per j0, reads before writes
+#pragma unroll
+                    for (int j0 = 0; j0 < J; ++j0) {
+                        int l0 = li[0] + j0;
+                        if (l0 >= g.K[0]) l0 -= g.K[0];
+                        const float w0 = wi[j0];
+                        float2 o[J];
+                        int cidx[J];
+                        bool ok[J];
 #pragma unroll
                         for (int j1 = 0; j1 < J; ++j1) {
-                            if (!(mask[1] >> j1 & 1u)) continue;
-                            float *cell = rowp + 2 * loc[1][j1];
-                            atomicAdd(cell, w[1][j1] * r0.x);
-                            atomicAdd(cell + 1, w[1][j1] * r0.y);
+                            int l1 = li[1] + j1;
+                            if (l1 >= g.K[1]) l1 -= g.K[1];
+                            ok[j1] = in && l0 < te[0] && l1 < te[1];
+                            cidx[j1] = (l0 * pt[1] + l1) * pt[2] + inner;
+                            if (ok[j1]) o[j1] = accc[cidx[j1]];
                         }
-                    }
-                } else {
-#pragma unroll
-                    for (int j0 = 0; j0 < J; ++j0) {
-                        if (!(mask[0] >> j0 & 1u)) continue;
-                        const float2 r0 = make_float2(w[0][j0] * yv.x, w[0][j0] * yv.y);
 #pragma unroll
                         for (int j1 = 0; j1 < J; ++j1) {
-                            if (!(mask[1] >> j1 & 1u)) continue;
-                            const float2 r1 = make_float2(w[1][j1] * r0.x, w[1][j1] * r0.y);
-                            float *rowp = base + 2 * (loc[0][j0] * te[1] + loc[1][j1]) * te[2];
-#pragma unroll
-                            for (int j2 = 0; j2 < J; ++j2) {
-                                if (!(mask[2] >> j2 & 1u)) continue;
-                                float *cell = rowp + 2 * loc[2][j2];
-                                atomicAdd(cell, w[2][j2] * r1.x);
-                                atomicAdd(cell + 1, w[2][j2] * r1.y);
-                            }
+                            const float w01 = w0 * wi[J + j1];
+                            if (ok[j1])
+                                accc[cidx[j1]] = make_float2(fmaf(w01, v.x, o[j1].x), fmaf(w01, v.y, o[j1].y));
                         }
                     }
                 }
@@ -282,64 +470,141 @@ __global__ void __launch_bounds__(KBN_BLOCK) k_spread(KbnGeom g, KbnSpreadArgs a
     // write the owned tile of every channel in the group
     for (int c = 0; c < nchg; ++c) {
         float2 *G = a.grid + (int64_t)(ch0 + c) * a.gsize;
-        const float *src = lacc + 2 * c * tsize;
-        for (int i = threadIdx.x; i < tsize; i += KBN_BLOCK) {
+        const float2 *src = acc + (size_t)c * plane;
+        for (int i = threadIdx.x; i < tsize; i += nthr) {
             int rem = i;
             int64_t off = 0, stride = 1;
+            int lo = 0, lstride = 1;
             for (int d = D - 1; d >= 0; --d) {
                 const int l = rem % te[d];
                 rem /= te[d];
                 off += (int64_t)(a0[d] + l) * stride;
                 stride *= g.K[d];
+                lo += l * lstride;
+                lstride *= pt[d];
             }
-            G[off] = make_float2(src[2 * i], src[2 * i + 1]);
+            G[off] = src[lo];
         }
     }
 }
 
-__global__ void k_fill(float *p, int64_t n, float v) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+// ys[ch][p] = y[ch][order[p]]: k-space values in tile order, so that the
+// spread reads them with coalesced loads.
+__global__ void __launch_bounds__(KBN_BLOCK)
+k_permute(const float2 *__restrict__ y, float2 *__restrict__ ys, const int *__restrict__ order,
+          int64_t M) {
+    const int64_t p = (int64_t)blockIdx.x * KBN_BLOCK + threadIdx.x;
+    if (p >= M) return;
+    const int64_t ch = blockIdx.y;
+    ys[ch * M + p] = y[ch * M + order[p]];
 }
+
+// dst[i] = (accumulate ? dst[i] : 0) + sum_g part[g][i], summed in group order.
+__global__ void __launch_bounds__(KBN_BLOCK)
+k_reduce_parts(float *__restrict__ dst, const float *__restrict__ part, int64_t n, int groups,
+               int accumulate) {
+    const int64_t i = (int64_t)blockIdx.x * KBN_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    float s = accumulate ? dst[i] : 0.f;
+    for (int g = 0; g < groups; ++g) s += part[(int64_t)g * n + i];
+    dst[i] = s;
+}
+
+}  // namespace
+
+// Launch shape of the gather: staged (LDS region fits 48 KiB) or direct, and
+// the channel grouping (whole weight-channel sets per group).
+KbnGatherShape kbn_gather_shape(const KbnGeom &g, int64_t M, int nch, int nw) {
+    KbnGatherShape sh;
+    const int lo = (g.J & 1) ? g.J / 2 : g.J / 2 - 1;
+    const int hi = (g.J & 1) ? g.J / 2 + 1 : g.J / 2;
+    int64_t region = 1;
+    for (int d = 0; d < g.D; ++d) region *= (int64_t)std::min(g.T[d], g.K[d]) + lo + hi;
+    sh.lds = sizeof(float2) * (size_t)region;
+    sh.staged = sh.lds <= 48 * 1024;
+    const int64_t nbc = std::max(1, nch / nw);
+    int64_t blocks;
+    if (sh.staged)
+        blocks = (M + KBN_SUB - 1) / KBN_SUB + g.ntiles + 1;
+    else
+        blocks = (M + KBN_BLOCK - 1) / KBN_BLOCK;
+    sh.blocks = blocks;
+    // aim for ~2048 workgroups over point blocks x channel groups
+    const int64_t groups = std::max<int64_t>(1, std::min<int64_t>(nbc, (2048 + blocks - 1) / blocks));
+    sh.cg = (int)(((nbc + groups - 1) / groups) * nw);
+    sh.groups = (nch + sh.cg - 1) / sh.cg;
+    return sh;
+}
+
+namespace {
 
 template <int D, int J>
 hipError_t gather_dj(const KbnGeom &g, const KbnGatherArgs &a, int mode, hipStream_t s) {
     if (a.M == 0 || a.nch == 0) return hipSuccess;
-    // channel groups: keep whole (b, c) sets of weight channels together
-    int cg = a.nch;
-    const int64_t pblocks = (a.M + KBN_BLOCK - 1) / KBN_BLOCK;
-    const int64_t want = 2048;  // workgroups to aim for
-    if (pblocks * 1 < want) {
-        int groups = (int)((want + pblocks - 1) / pblocks);
-        if (groups > a.nch / a.nw) groups = a.nch / a.nw;
-        if (groups < 1) groups = 1;
-        cg = ((a.nch / a.nw + groups - 1) / groups) * a.nw;
+    const KbnGatherShape sh = kbn_gather_shape(g, a.M, a.nch, a.nw);
+    dim3 grid((unsigned)sh.blocks, (unsigned)sh.groups);
+    if (sh.staged) {
+        if (mode == 0)
+            k_gather_staged<D, J, 0><<<grid, dim3(KBN_BLOCK), sh.lds, s>>>(g, a, sh.cg);
+        else
+            k_gather_staged<D, J, 1><<<grid, dim3(KBN_BLOCK), sh.lds, s>>>(g, a, sh.cg);
     } else {
-        cg = a.nw * ((8 + a.nw - 1) / a.nw);
-        if (cg > a.nch) cg = a.nch;
+        if (mode == 0)
+            k_gather<D, J, 0><<<grid, dim3(KBN_BLOCK), 0, s>>>(g, a, sh.cg);
+        else
+            k_gather<D, J, 1><<<grid, dim3(KBN_BLOCK), 0, s>>>(g, a, sh.cg);
     }
-    const int ng = (a.nch + cg - 1) / cg;
-    dim3 grid((unsigned)pblocks, (unsigned)ng);
-    if (mode == 0)
-        k_gather<D, J, 0><<<grid, dim3(KBN_BLOCK), 0, s>>>(g, a, cg);
-    else
-        k_gather<D, J, 1><<<grid, dim3(KBN_BLOCK), 0, s>>>(g, a, cg);
+    if (mode == 1) {
+        const int64_t n = a.M * g.D;
+        k_reduce_parts<<<dim3((unsigned)((n + KBN_BLOCK - 1) / KBN_BLOCK)), dim3(KBN_BLOCK), 0, s>>>(
+            a.domega, a.part, n, sh.groups, a.accumulate);
+    }
     return hipGetLastError();
+}
+
+// Launch shape of the spread: lanes per tap group (A), channels per wave,
+// waves per workgroup, and the LDS bytes.
+struct SpreadShape {
+    int A, cw, nwave;
+    size_t lds;
+};
+
+SpreadShape spread_shape(const KbnGeom &g, int nch) {
+    SpreadShape sh;
+    const int J = g.J, D = g.D;
+    sh.A = (D >= 2 && nch < 64 / J) ? 2 : 1;
+    sh.cw = sh.A == 1 ? 64 / J : std::max(1, 64 / (J * J));
+    int psize = 1;
+    for (int d = 0; d < D; ++d) psize *= acc_pitch(d, std::min(g.To[d], g.K[d]));
+    const int plane = spread_plane(psize);
+    const int EB = KBN_SPREAD_EB;
+    auto bytes = [&](int nw) {
+        const int ng = nw * sh.cw;
+        return sizeof(float2) * (size_t)ng * plane + sizeof(int) * EB * (1 + D) +
+               sizeof(float) * EB * D * J + sizeof(float2) * (size_t)ng * (EB + 1);
+    };
+    sh.nwave = 1;
+    const int want = (nch + sh.cw - 1) / sh.cw;  // waves that have channels
+    while (sh.nwave < 2 && sh.nwave < want && bytes(sh.nwave + 1) <= KBN_SPREAD_LDS) ++sh.nwave;
+    sh.lds = bytes(sh.nwave);
+    return sh;
 }
 
 template <int D, int J>
 hipError_t spread_dj(const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s) {
     if (a.nch == 0) return hipSuccess;
-    int tmax = 1;
-    for (int d = 0; d < D; ++d) tmax *= g.T[d] < g.K[d] ? g.T[d] : g.K[d];
-    const size_t per_ch = sizeof(float2) * (size_t)tmax;
-    int cg = (int)((48 * 1024) / per_ch);
-    if (cg < 1) cg = 1;
-    if (cg > 8) cg = 8;
-    if (cg > a.nch) cg = a.nch;
-    const int ng = (a.nch + cg - 1) / cg;
-    dim3 grid((unsigned)g.ntiles, (unsigned)ng);
-    k_spread<D, J><<<grid, dim3(KBN_BLOCK), per_ch * cg, s>>>(g, a, cg);
+    const SpreadShape sh = spread_shape(g, a.nch);
+    const int ngroup = sh.nwave * sh.cw;
+    const int ng = (a.nch + ngroup - 1) / ngroup;
+    if (a.M > 0) {
+        dim3 pgrid((unsigned)((a.M + KBN_BLOCK - 1) / KBN_BLOCK), (unsigned)a.nch);
+        k_permute<<<pgrid, dim3(KBN_BLOCK), 0, s>>>(a.y, a.ys, a.order, a.M);
+    }
+    dim3 grid((unsigned)ng, (unsigned)g.ntiles_own);
+    if (sh.A == 1 || D == 1)
+        k_spread<D, J, 1><<<grid, dim3(64 * sh.nwave), sh.lds, s>>>(g, a, sh.cw, sh.nwave);
+    else
+        k_spread<D, J, (D >= 2 ? 2 : 1)><<<grid, dim3(64 * sh.nwave), sh.lds, s>>>(g, a, sh.cw, sh.nwave);
     return hipGetLastError();
 }
 
@@ -387,9 +652,4 @@ hipError_t kbn_launch_spread(const KbnGeom &g, const KbnSpreadArgs &a, hipStream
     }
 }
 
-hipError_t kbn_launch_fill(float *p, int64_t n, float v, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    const int64_t blocks = (n + KBN_BLOCK - 1) / KBN_BLOCK;
-    k_fill<<<dim3((unsigned)blocks), dim3(KBN_BLOCK), 0, s>>>(p, n, v);
-    return hipGetLastError();
-}
+

@@ -13,6 +13,9 @@
 #define KBN_MAX_K 1024      // largest oversampled grid edge handled by the LDS FFT
 #define KBN_MAX_TILES 16383 // tile histogram lives in LDS (ntiles + 1 counters)
 #define KBN_BLOCK 256
+#define KBN_SUB 256        // sorted points per gather subproblem (one per thread)
+#define KBN_SPREAD_EB 64   // list entries staged per spread batch
+#define KBN_SPREAD_LDS (64 * 1024)  // LDS budget of one spread workgroup
 
 // kernel classes reported by kbn_timing_read (order of kClassNames)
 #define KBN_CLASS_INDEX 0
@@ -23,8 +26,7 @@
 #define KBN_CLASS_GATHER 5
 #define KBN_CLASS_GATHER_JAC 6
 #define KBN_CLASS_SPREAD 7
-#define KBN_CLASS_FILL 8
-#define KBN_NCLASS 9
+#define KBN_NCLASS 8
 
 // Mixed-radix factorisation of one FFT length (radices 2, 3, 4, 5, 7, 8).
 struct KbnRadix {
@@ -41,6 +43,9 @@ struct KbnGeom {
     int T[KBN_MAX_D];
     int nt[KBN_MAX_D];
     int ntiles;
+    int To[KBN_MAX_D];  // spread owner tile edge per axis
+    int nto[KBN_MAX_D];
+    int ntiles_own;
     const float *coef;  // [J][KBN_NCOEF] monomial coefficients in x = 2 f - 1
 };
 
@@ -57,7 +62,17 @@ struct KbnPointsBufs {
     float *frac;     // [D][M] sorted
     int *toff;       // [nbins + 1]
     int *flag;       // sticky non-finite flag
+    int *subs;       // [ceil(M / KBN_SUB) + nbins][2] (bin, first sorted position)
+    int *nsub;       // number of subproblems
 };
+
+// Owner-tile touch lists for the spread (entries = sorted sample positions,
+// grouped by owner tile; ooff[t]..ooff[t+1] is tile t's range).
+hipError_t kbn_launch_owner_lists(int D, int J, int ntiles_sort, const int *K, const int *To,
+                                  const int *nto, int ntiles_own, int64_t M, int chunk,
+                                  int nchunks, const int *cell, const float *frac,
+                                  const int *toff, int *counts, int *ooff, int *entries,
+                                  int *otile_order, hipStream_t s);
 
 hipError_t kbn_launch_points(int D, int64_t M, const float *omega, const double *scale,
                              const int *K, const int *T, const int *nt, int ntiles,
@@ -123,13 +138,26 @@ struct KbnGatherArgs {
     const int *cell;
     const float *frac;
     const int *toff;           // toff[ntiles] = end of finite points
+    const int *subs;           // gather subproblems [n][2] (tile, first sorted position)
+    const int *nsub;
     float2 *y;                 // mode 0: [B][C][M] with batch offset applied
     const float2 *v;           // mode 1: [B][C][M] with batch offset applied
     float *domega;             // mode 1: [M][D]
+    float *part;               // mode 1: [groups][M][D] per-group partial gradients
+    int accumulate;            // mode 1: add the reduced gradient onto domega
 };
+
+struct KbnGatherShape {
+    bool staged;
+    size_t lds;
+    int64_t blocks;
+    int cg, groups;
+};
+KbnGatherShape kbn_gather_shape(const KbnGeom &g, int64_t M, int nch, int nw);
 
 struct KbnSpreadArgs {
     const float2 *y;           // [nb][C][M] batch offset applied
+    float2 *ys;                // [nb*C][M] workspace: y in sorted order
     float2 *grid;              // [nch][prod K], nch = nb * C
     int64_t gsize;
     int nch;
@@ -138,8 +166,10 @@ struct KbnSpreadArgs {
     const int *cell;
     const float *frac;
     const int *toff;
+    const int *ooff;           // owner tile t's entries: oent[ooff[t] .. ooff[t+1])
+    const int *oent;           // sorted sample positions, grouped by owner tile
+    const int *otile_order;    // owner tiles by decreasing entry count (coarse)
 };
 
 hipError_t kbn_launch_gather(const KbnGeom &g, const KbnGatherArgs &a, int mode, hipStream_t s);
 hipError_t kbn_launch_spread(const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s);
-hipError_t kbn_launch_fill(float *p, int64_t n, float v, hipStream_t s);

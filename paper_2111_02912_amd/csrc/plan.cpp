@@ -48,7 +48,7 @@ int launched(hipError_t e, const char *what, hipStream_t s) {
 
 const char *const kClassNames[KBN_NCLASS] = {"index",       "fft_first",    "fft_mid_fwd",
                                                "fft_mid_inv", "fft_last_adj", "gather",
-                                               "gather_jac",  "spread",       "fill"};
+                                               "gather_jac",  "spread"};
 
 // Launch `expr` (a kernel launcher returning hipError_t) of kernel class
 // `cls`; with timing enabled the launch is bracketed by events on `stream`.
@@ -177,6 +177,9 @@ struct kbn_plan_s {
     int T[KBN_MAX_D] = {1, 1, 1};
     int nt[KBN_MAX_D] = {1, 1, 1};
     int ntiles = 1;
+    int To[KBN_MAX_D] = {1, 1, 1};   // spread owner tiles
+    int nto[KBN_MAX_D] = {1, 1, 1};
+    int ntiles_own = 1;
     double scale[KBN_MAX_D] = {0, 0, 0};
     KbnRadix rad[KBN_MAX_D];
     float *deap[KBN_MAX_D] = {nullptr, nullptr, nullptr};
@@ -190,6 +193,8 @@ struct kbn_plan_s {
     float *frac_tmp = nullptr, *frac = nullptr;
     int *counts = nullptr;
     int64_t counts_cap = 0;
+    int *subs = nullptr, *nsub = nullptr;
+    int *ooff = nullptr, *oent = nullptr, *otile_order = nullptr;
     // grid workspace
     float2 *ws = nullptr;
     int64_t ws_bytes = 0, max_ws = 0;
@@ -219,6 +224,11 @@ struct kbn_plan_s {
             g.nt[d] = nt[d];
         }
         g.ntiles = ntiles;
+        for (int d = 0; d < KBN_MAX_D; ++d) {
+            g.To[d] = To[d];
+            g.nto[d] = nto[d];
+        }
+        g.ntiles_own = ntiles_own;
         g.coef = coef;
         return g;
     }
@@ -268,6 +278,8 @@ void free_points(kbn_plan p) {
     dev_free(p->frac_tmp);
     dev_free(p->frac);
     dev_free(p->counts);
+    dev_free(p->subs);
+    dev_free(p->oent);
     p->Mcap = 0;
     p->counts_cap = 0;
 }
@@ -286,6 +298,9 @@ void free_plan(kbn_plan p) {
     dev_free(p->coef);
     dev_free(p->flag);
     dev_free(p->toff);
+    dev_free(p->nsub);
+    dev_free(p->ooff);
+    dev_free(p->otile_order);
     dev_free(p->ws);
     delete p;
 }
@@ -322,15 +337,20 @@ int64_t img_rows(kbn_plan p) {  // product of the leading image axes
 // passes, then gather.  mode 0 writes y; mode 1 folds the omega-Jacobian.
 int run_type2(kbn_plan p, int B, int C, int nw, int weighted, const float2 *x,
               const float2 *smaps, int mode, float2 *y, const float2 *v, float *dom,
-              hipStream_t stream) {
+              int accumulate, hipStream_t stream) {
     const int D = p->D;
     const int64_t gsz = p->gsize();
     const int64_t per_img = (int64_t)C * nw * gsz * (int64_t)sizeof(float2) * 2;
     int64_t bc = std::max<int64_t>(1, std::min<int64_t>(B, p->max_ws / per_img));
-    int rc = ensure_ws(p, bc * per_img, stream);
+    const KbnGeom geom0 = p->geom();
+    // per-group partial omega-gradients (mode 1), sized for the largest chunk
+    const KbnGatherShape sh = kbn_gather_shape(geom0, p->M, (int)(bc * C * nw), nw);
+    const int64_t part_bytes = mode == 1 ? (int64_t)sh.groups * p->M * D * (int64_t)sizeof(float) : 0;
+    int rc = ensure_ws(p, bc * per_img + part_bytes, stream);
     if (rc != KBN_OK) return rc;
     float2 *bufA = p->ws;
     float2 *bufB = p->ws + bc * C * nw * gsz;
+    float *part = (float *)(p->ws + 2 * bc * C * nw * gsz);
     const int64_t R0 = img_rows(p);
     const int Nl = p->N[D - 1];
     const KbnGeom geom = p->geom();
@@ -382,9 +402,13 @@ int run_type2(kbn_plan p, int B, int C, int nw, int weighted, const float2 *x,
         ga.cell = p->cell;
         ga.frac = p->frac;
         ga.toff = p->toff;
+        ga.subs = p->subs;
+        ga.nsub = p->nsub;
         ga.y = mode == 0 ? y + b0 * C * p->M : nullptr;
         ga.v = mode == 1 ? v + b0 * C * p->M : nullptr;
         ga.domega = dom;
+        ga.part = part;
+        ga.accumulate = (accumulate || b0 > 0) ? 1 : 0;
         KBN_LAUNCH(mode == 0 ? KBN_CLASS_GATHER : KBN_CLASS_GATHER_JAC, kbn_launch_gather(geom, ga, mode, stream), "gather");
     }
     return KBN_OK;
@@ -396,12 +420,13 @@ int run_type1(kbn_plan p, int B, int C, const float2 *y, const float2 *smaps, fl
               hipStream_t stream) {
     const int D = p->D;
     const int64_t gsz = p->gsize();
-    const int64_t per_img = (int64_t)C * gsz * (int64_t)sizeof(float2) * 2;
+    const int64_t per_img = (int64_t)C * (gsz * 2 + p->M) * (int64_t)sizeof(float2);
     int64_t bc = std::max<int64_t>(1, std::min<int64_t>(B, p->max_ws / per_img));
     int rc = ensure_ws(p, bc * per_img, stream);
     if (rc != KBN_OK) return rc;
     float2 *bufA = p->ws;
     float2 *bufB = p->ws + bc * C * gsz;
+    float2 *bufY = p->ws + 2 * bc * C * gsz;
     const int64_t R0 = img_rows(p);
     const int Nl = p->N[D - 1];
     const KbnGeom geom = p->geom();
@@ -410,6 +435,7 @@ int run_type1(kbn_plan p, int B, int C, const float2 *y, const float2 *smaps, fl
         const int64_t nch = nb * C;
         KbnSpreadArgs sa;
         sa.y = y + b0 * C * p->M;
+        sa.ys = bufY;
         sa.grid = bufA;
         sa.gsize = gsz;
         sa.nch = (int)nch;
@@ -418,6 +444,9 @@ int run_type1(kbn_plan p, int B, int C, const float2 *y, const float2 *smaps, fl
         sa.cell = p->cell;
         sa.frac = p->frac;
         sa.toff = p->toff;
+        sa.ooff = p->ooff;
+        sa.oent = p->oent;
+        sa.otile_order = p->otile_order;
         KBN_LAUNCH(KBN_CLASS_SPREAD, kbn_launch_spread(geom, sa, stream), "spread");
         float2 *cur = bufA, *nxt = bufB;
         for (int d = 0; d + 1 < D; ++d) {
@@ -459,9 +488,8 @@ int run_type1(kbn_plan p, int B, int C, const float2 *y, const float2 *smaps, fl
 int run_jac(kbn_plan p, int B, int C, const float2 *img, const float2 *smaps, const float2 *v,
             float *dom, int accumulate, hipStream_t stream) {
     if (!dom && p->M > 0) return fail(KBN_ERR_INVALID_ARG, "null domega");
-    if (!accumulate) KBN_LAUNCH(KBN_CLASS_FILL, kbn_launch_fill(dom, p->M * p->D, 0.f, stream), "fill");
     if (p->M == 0) return KBN_OK;
-    return run_type2(p, B, C, p->D, 1, img, smaps, 1, nullptr, v, dom, stream);
+    return run_type2(p, B, C, p->D, 1, img, smaps, 1, nullptr, v, dom, accumulate, stream);
 }
 
 }  // namespace
@@ -523,6 +551,24 @@ int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts
         return fail(KBN_ERR_UNSUPPORTED, "too many tiles; use larger tiles");
     }
     p->ntiles = (int)ntiles;
+    // spread owner tiles: small enough that several channels' accumulators fit in LDS
+    int64_t ntiles_own = 1;
+    const int defown = D == 1 ? 128 : 16;
+    for (int d = 0; d < D; ++d) {
+        const int K = p->K[d];
+        int T = std::max(defown, J);
+        if (T > K) T = K;
+        while (T > J && K % T != 0 && K % T < J) --T;
+        if (K % T != 0 && K % T < J) T = K;
+        p->To[d] = T;
+        p->nto[d] = (K + T - 1) / T;
+        ntiles_own *= p->nto[d];
+    }
+    if (ntiles_own > KBN_MAX_TILES) {
+        free_plan(p);
+        return fail(KBN_ERR_UNSUPPORTED, "too many spread tiles");
+    }
+    p->ntiles_own = (int)ntiles_own;
 
     Window w{J, p->beta, bessel_i0(p->beta)};
     int rc = KBN_OK;
@@ -557,6 +603,9 @@ int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts
     if (rc == KBN_OK && hipMemset(p->flag, 0, sizeof(int)) != hipSuccess)
         rc = fail(KBN_ERR_HIP, "hipMemset (flag)");
     if (rc == KBN_OK) rc = dev_alloc(&p->toff, (int64_t)p->ntiles + 2);
+    if (rc == KBN_OK) rc = dev_alloc(&p->nsub, 1);
+    if (rc == KBN_OK) rc = dev_alloc(&p->ooff, (int64_t)p->ntiles_own + 1);
+    if (rc == KBN_OK) rc = dev_alloc(&p->otile_order, (int64_t)p->ntiles_own);
     if (rc != KBN_OK) {
         free_plan(p);
         return rc;
@@ -571,10 +620,15 @@ int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream_) {
     if (M < 0 || M > 2147483647LL) return fail(KBN_ERR_INVALID_ARG, "M out of range");
     if (M > 0 && !omega) return fail(KBN_ERR_INVALID_ARG, "null omega");
     const int nbins = p->ntiles + 1;
-    int64_t chunk = std::max<int64_t>(256, (M * nbins + (1 << 18) - 1) >> 18);
+    int64_t chunk = std::max<int64_t>(1024, (M * nbins + (1 << 17) - 1) >> 17);
     chunk = (chunk + 63) / 64 * 64;
     const int64_t nchunks = M > 0 ? (M + chunk - 1) / chunk : 0;
-    if (M > p->Mcap || nchunks * nbins > p->counts_cap) {
+    const int nbins_o = p->ntiles_own;
+    int64_t chunk_o = std::max<int64_t>(1024, (M * nbins_o + (1 << 17) - 1) >> 17);
+    chunk_o = (chunk_o + 63) / 64 * 64;
+    const int64_t nchunks_o = M > 0 ? (M + chunk_o - 1) / chunk_o : 0;
+    const int64_t counts_need = std::max<int64_t>(std::max(nchunks * nbins, nchunks_o * nbins_o), 1);
+    if (M > p->Mcap || counts_need > p->counts_cap) {
         KBN_HIP(hipStreamSynchronize(stream));
         free_points(p);
         const int64_t cap = std::max<int64_t>(M, 1);
@@ -585,14 +639,16 @@ int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream_) {
         if (rc == KBN_OK) rc = dev_alloc(&p->order, cap);
         if (rc == KBN_OK) rc = dev_alloc(&p->cell, cap * D);
         if (rc == KBN_OK) rc = dev_alloc(&p->frac, cap * D);
-        if (rc == KBN_OK) rc = dev_alloc(&p->counts, std::max<int64_t>(nchunks * nbins, 1));
+        if (rc == KBN_OK) rc = dev_alloc(&p->counts, counts_need);
+        if (rc == KBN_OK) rc = dev_alloc(&p->subs, 2 * ((cap + KBN_SUB - 1) / KBN_SUB + nbins));
+        if (rc == KBN_OK) rc = dev_alloc(&p->oent, cap << D);
         if (rc != KBN_OK) {
             free_points(p);
             p->M = -1;
             return rc;
         }
         p->Mcap = cap;
-        p->counts_cap = std::max<int64_t>(nchunks * nbins, 1);
+        p->counts_cap = counts_need;
     }
     KbnPointsBufs b;
     b.cell_tmp = p->cell_tmp;
@@ -604,9 +660,16 @@ int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream_) {
     b.frac = p->frac;
     b.toff = p->toff;
     b.flag = p->flag;
+    b.subs = p->subs;
+    b.nsub = p->nsub;
     KBN_LAUNCH(KBN_CLASS_INDEX, kbn_launch_points(p->D, M, omega, p->scale, p->K, p->T, p->nt, p->ntiles,
                                  (int)chunk, (int)nchunks, b, stream),
                "index pass");
+    KBN_LAUNCH(KBN_CLASS_INDEX,
+               kbn_launch_owner_lists(p->D, p->J, p->ntiles, p->K, p->To, p->nto, p->ntiles_own, M,
+                                      (int)chunk_o, (int)nchunks_o, p->cell, p->frac, p->toff,
+                                      p->counts, p->ooff, p->oent, p->otile_order, stream),
+               "spread lists");
     p->M = M;
     return KBN_OK;
 }
@@ -617,7 +680,7 @@ int kbn_forward(kbn_plan p, int B, int C, const void *x, const void *smaps, void
     if (rc != KBN_OK) return rc;
     if (p->M == 0) return KBN_OK;
     return run_type2(p, B, C, 1, 0, (const float2 *)x, (const float2 *)smaps, 0, (float2 *)y,
-                     nullptr, nullptr, (hipStream_t)stream);
+                     nullptr, nullptr, 0, (hipStream_t)stream);
 }
 
 int kbn_adjoint(kbn_plan p, int B, int C, const void *y, const void *smaps, void *x,

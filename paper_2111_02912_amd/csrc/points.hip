@@ -80,35 +80,47 @@ k_tile_hist(int64_t M, int chunk, int nchunks, int nbins, const int *__restrict_
     for (int i = threadIdx.x; i < nbins; i += 64) counts[(int64_t)i * nchunks + ch] = hist[i];
 }
 
-// Single-workgroup exclusive scan of the bin-major count matrix; also emits
-// the tile offsets toff[b] = first sorted position of bin b, toff[nbins] = M.
+// Single-workgroup exclusive scan of the bin-major count matrix (S entries,
+// in place), 4096 entries per round with coalesced loads, wave shuffles and
+// one LDS exchange per 1024-entry slab.  Also emits toff[b] = first position
+// of bin b and toff[nbins] = total count.
 __global__ void __launch_bounds__(1024)
-k_scan(int64_t S, int nchunks, int nbins, int64_t M, int *__restrict__ counts,
-       int *__restrict__ toff) {
-    __shared__ int part[1024];
+k_scan(int64_t S, int nchunks, int nbins, int *__restrict__ counts, int *__restrict__ toff) {
+    __shared__ int wsum[16];
     const int tid = threadIdx.x;
-    const int64_t seg = (S + 1023) / 1024;
-    const int64_t beg = tid * seg;
-    const int64_t end = beg + seg < S ? beg + seg : S;
-    int sum = 0;
-    for (int64_t i = beg; i < end; ++i) sum += counts[i];
-    part[tid] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {  // Hillis-Steele inclusive scan
-        int v = tid >= off ? part[tid - off] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    int run = part[tid] - sum;  // exclusive prefix of this segment
-    for (int64_t i = beg; i < end; ++i) {
-        const int c = counts[i];
-        counts[i] = run;
-        run += c;
+    const int lane = tid & 63, wid = tid >> 6;
+    int run = 0;  // identical in every thread
+    for (int64_t base = 0; base < S; base += 4096) {
+        int v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t i = base + (int64_t)k * 1024 + tid;
+            v[k] = i < S ? counts[i] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            int x = v[k];
+            for (int o = 1; o < 64; o <<= 1) {  // inclusive wave scan
+                const int y = __shfl_up(x, o, 64);
+                if (lane >= o) x += y;
+            }
+            if (lane == 63) wsum[wid] = x;
+            __syncthreads();
+            int wpre = 0, slab = 0;
+            for (int w = 0; w < 16; ++w) {
+                const int ws = wsum[w];
+                if (w < wid) wpre += ws;
+                slab += ws;
+            }
+            __syncthreads();
+            const int64_t i = base + (int64_t)k * 1024 + tid;
+            if (i < S) counts[i] = run + wpre + x - v[k];
+            run += slab;
+        }
     }
     __syncthreads();
     for (int b = tid; b < nbins; b += 1024) toff[b] = S > 0 ? counts[(int64_t)b * nchunks] : 0;
-    if (tid == 0) toff[nbins] = (int)M;
+    if (tid == 0) toff[nbins] = run;
 }
 
 // One wavefront per chunk: stable scatter.  Lanes with equal tile ids are
@@ -154,7 +166,219 @@ k_tile_scatter(int D, int64_t M, int chunk, int nchunks, int nbins, int nbits,
     }
 }
 
+// Subproblem list: bin t with n points contributes ceil(n / sub) entries
+// (bin, first sorted position); the last bin holds the flagged points.
+// Single workgroup; subs holds at most ceil(M / sub) + nbins entries.
+__global__ void __launch_bounds__(1024)
+k_subproblems(int nbins, int sub, const int *__restrict__ toff, int *__restrict__ subs,
+              int *__restrict__ nsub) {
+    __shared__ int part[1024];
+    const int tid = threadIdx.x;
+    const int seg = (nbins + 1023) / 1024;
+    const int beg = tid * seg;
+    const int end = min(beg + seg, nbins);
+    int sum = 0;
+    for (int t = beg; t < end; ++t) sum += (toff[t + 1] - toff[t] + sub - 1) / sub;
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int run = part[tid] - sum;
+    for (int t = beg; t < end; ++t) {
+        for (int q = toff[t]; q < toff[t + 1]; q += sub) {
+            subs[2 * run] = t;
+            subs[2 * run + 1] = q;
+            ++run;
+        }
+    }
+    if (tid == 1023) *nsub = part[1023];
+}
+
+// ---------------------------------------------------------------------------
+// Owner-tile touch lists for the spread.  A finite sample whose J taps along
+// axis d start at grid cell s_d reaches owner tiles floor(wrap(s_d)/To_d) and
+// floor(wrap(s_d + J - 1)/To_d) (one or two tiles per axis, since To_d >= J
+// and no owner tile is narrower than J).  Every (sample, reached tile) pair
+// becomes one entry; entries are grouped by tile with a counting sort whose
+// order inside a tile is fixed (chunk order, then combination index, then
+// sample order), so the spread's accumulation order is deterministic.
+struct OwnerGeom {
+    int D, J, ntiles_sort;
+    int K[3], To[3], nto[3];
+};
+
+__device__ __forceinline__ int touch_tiles(const OwnerGeom &o, int p, int64_t M,
+                                           const int *__restrict__ cell,
+                                           const float *__restrict__ frac, int first[3],
+                                           int num[3]) {
+    int total = 1;
+    for (int d = 0; d < o.D; ++d) {
+        const int c = cell[d * M + p];
+        const float f = frac[d * M + p];
+        int start;
+        if ((o.J & 1) == 0)
+            start = c - o.J / 2 + 1;
+        else
+            start = f >= 0.5f ? c - o.J / 2 + 1 : c - o.J / 2;
+        int s0 = start < 0 ? start + o.K[d] : start;
+        int s1 = start + o.J - 1;
+        if (s1 >= o.K[d]) s1 -= o.K[d];
+        if (s1 < 0) s1 += o.K[d];
+        const int t0 = s0 / o.To[d], t1 = s1 / o.To[d];
+        first[d] = t0;
+        num[d] = t0 == t1 ? 1 : 2;
+        total *= num[d];
+    }
+    return total;
+}
+
+// k-th reached tile of a sample (k < total), row-major over the axes.
+__device__ __forceinline__ int touch_tile_id(const OwnerGeom &o, const int first[3],
+                                             const int num[3], int k) {
+    int id = 0;
+    int rem = k;
+    int sel[3];
+    for (int d = o.D - 1; d >= 0; --d) {
+        sel[d] = rem % num[d];
+        rem /= num[d];
+    }
+    for (int d = 0; d < o.D; ++d) {
+        int t = first[d] + sel[d];
+        if (t >= o.nto[d]) t -= o.nto[d];
+        id = id * o.nto[d] + t;
+    }
+    return id;
+}
+
+__global__ void __launch_bounds__(64)
+k_owner_hist(OwnerGeom o, int64_t M, int chunk, int nchunks, int nbins,
+             const int *__restrict__ cell, const float *__restrict__ frac,
+             const int *__restrict__ toff, int *__restrict__ counts) {
+    extern __shared__ int hist[];
+    const int ch = blockIdx.x;
+    for (int i = threadIdx.x; i < nbins; i += 64) hist[i] = 0;
+    __syncthreads();
+    const int64_t ngood = toff[o.ntiles_sort];
+    const int64_t beg = (int64_t)ch * chunk;
+    const int64_t end = beg + chunk < ngood ? beg + chunk : ngood;
+    for (int64_t p = beg + threadIdx.x; p < end; p += 64) {
+        int first[3], num[3];
+        const int tot = touch_tiles(o, (int)p, M, cell, frac, first, num);
+        for (int k = 0; k < tot; ++k) atomicAdd(&hist[touch_tile_id(o, first, num, k)], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nbins; i += 64) counts[(int64_t)i * nchunks + ch] = hist[i];
+}
+
+__global__ void __launch_bounds__(64)
+k_owner_scatter(OwnerGeom o, int64_t M, int chunk, int nchunks, int nbins, int nbits,
+                const int *__restrict__ cell, const float *__restrict__ frac,
+                const int *__restrict__ toff, const int *__restrict__ counts,
+                int *__restrict__ entries) {
+    extern __shared__ int cursor[];
+    const int ch = blockIdx.x;
+    const int lane = threadIdx.x;
+    for (int i = lane; i < nbins; i += 64) cursor[i] = counts[(int64_t)i * nchunks + ch];
+    __syncthreads();
+    const int64_t ngood = toff[o.ntiles_sort];
+    const int64_t beg = (int64_t)ch * chunk;
+    const int64_t end = beg + chunk < ngood ? beg + chunk : ngood;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int maxk = 1 << o.D;
+    for (int64_t base = beg; base < end; base += 64) {
+        const int64_t p = base + lane;
+        const bool valid = p < end;
+        int first[3] = {0, 0, 0}, num[3] = {1, 1, 1};
+        int tot = 0;
+        if (valid) tot = touch_tiles(o, (int)p, M, cell, frac, first, num);
+        for (int k = 0; k < maxk; ++k) {
+            const bool act = k < tot;
+            const int t = act ? touch_tile_id(o, first, num, k) : -1;
+            unsigned long long peers = ~0ull;
+            for (int bit = 0; bit <= nbits; ++bit) {
+                const bool on = (t >> bit) & 1;
+                const unsigned long long bal = __ballot(on);
+                peers &= on ? bal : ~bal;
+            }
+            const int rank = __popcll(peers & below);
+            const int cnt = __popcll(peers);
+            int pos = 0;
+            if (act) pos = cursor[t] + rank;
+            __syncthreads();
+            if (act && rank == 0) cursor[t] = pos + cnt;
+            __syncthreads();
+            if (act) entries[pos] = (int)p;
+        }
+    }
+}
+
+// Owner tiles in decreasing order of entry count (bins of log2 count), so
+// that the spread dispatches its longest workgroups first.  The order inside
+// a bin is arbitrary; tiles are independent, so results do not depend on it.
+__global__ void __launch_bounds__(1024)
+k_tile_order(int ntiles, const int *__restrict__ ooff, int *__restrict__ order) {
+    __shared__ int hist[33];
+    __shared__ int start[33];
+    const int tid = threadIdx.x;
+    if (tid < 33) hist[tid] = 0;
+    __syncthreads();
+    for (int t = tid; t < ntiles; t += 1024) {
+        const int c = ooff[t + 1] - ooff[t];
+        const int key = c == 0 ? 32 : __clz(c);  // larger counts -> smaller key
+        atomicAdd(&hist[key], 1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int r = 0;
+        for (int k = 0; k < 33; ++k) {
+            start[k] = r;
+            r += hist[k];
+        }
+    }
+    __syncthreads();
+    for (int t = tid; t < ntiles; t += 1024) {
+        const int c = ooff[t + 1] - ooff[t];
+        const int key = c == 0 ? 32 : __clz(c);
+        order[atomicAdd(&start[key], 1)] = t;
+    }
+}
+
 }  // namespace
+
+hipError_t kbn_launch_owner_lists(int D, int J, int ntiles_sort, const int *K, const int *To,
+                                  const int *nto, int ntiles_own, int64_t M, int chunk,
+                                  int nchunks, const int *cell, const float *frac,
+                                  const int *toff, int *counts, int *ooff, int *entries,
+                                  int *otile_order, hipStream_t s) {
+    OwnerGeom o;
+    o.D = D;
+    o.J = J;
+    o.ntiles_sort = ntiles_sort;
+    for (int d = 0; d < 3; ++d) {
+        o.K[d] = d < D ? K[d] : 1;
+        o.To[d] = d < D ? To[d] : 1;
+        o.nto[d] = d < D ? nto[d] : 1;
+    }
+    const int nbins = ntiles_own;
+    if (M > 0)
+        k_owner_hist<<<dim3(nchunks), dim3(64), sizeof(int) * nbins, s>>>(
+            o, M, chunk, nchunks, nbins, cell, frac, toff, counts);
+    const int64_t S = (int64_t)nbins * (M > 0 ? nchunks : 0);
+    // ooff[nbins] receives the total entry count
+    k_scan<<<dim3(1), dim3(1024), 0, s>>>(S, M > 0 ? nchunks : 1, nbins, counts, ooff);
+    if (M > 0) {
+        int nbits = 0;
+        while ((1 << nbits) < nbins) ++nbits;
+        k_owner_scatter<<<dim3(nchunks), dim3(64), sizeof(int) * nbins, s>>>(
+            o, M, chunk, nchunks, nbins, nbits, cell, frac, toff, counts, entries);
+    }
+    k_tile_order<<<dim3(1), dim3(1024), 0, s>>>(nbins, ooff, otile_order);
+    return hipGetLastError();
+}
 
 hipError_t kbn_launch_points(int D, int64_t M, const float *omega, const double *scale,
                              const int *K, const int *T, const int *nt, int ntiles,
@@ -170,7 +394,7 @@ hipError_t kbn_launch_points(int D, int64_t M, const float *omega, const double 
                                                                           b.tile, b.counts);
     }
     const int64_t S = (int64_t)nbins * (M > 0 ? nchunks : 0);
-    k_scan<<<dim3(1), dim3(1024), 0, s>>>(S, M > 0 ? nchunks : 1, nbins, M, b.counts, b.toff);
+    k_scan<<<dim3(1), dim3(1024), 0, s>>>(S, M > 0 ? nchunks : 1, nbins, b.counts, b.toff);
     if (M > 0) {
         int nbits = 0;
         while ((1 << nbits) < nbins) ++nbits;
@@ -178,5 +402,6 @@ hipError_t kbn_launch_points(int D, int64_t M, const float *omega, const double 
             D, M, chunk, nchunks, nbins, nbits, b.tile, b.counts, b.cell_tmp, b.frac_tmp, b.order,
             b.cell, b.frac);
     }
+    k_subproblems<<<dim3(1), dim3(1024), 0, s>>>(nbins, KBN_SUB, b.toff, b.subs, b.nsub);
     return hipGetLastError();
 }
