@@ -104,6 +104,9 @@ def main():
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-images", type=int, default=2)
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="after the run, copy this many bytes device-to-device once (a "
+                         "known-size reference dispatch for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); "
@@ -197,6 +200,13 @@ def main():
         "kernels": kernels,
     }
     print(json.dumps(out), flush=True)
+    if args.copy_calib:
+        n = args.copy_calib // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

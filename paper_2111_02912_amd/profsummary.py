@@ -1,0 +1,132 @@
+"""Turn rocprofv3 CSV output into the short text summaries kept under profiles/.
+
+  python -m paper_2111_02912_amd.profsummary stats KERNEL_STATS_CSV --cmd "..."
+  python -m paper_2111_02912_amd.profsummary pmc FETCH_CSV WRITE_CSV --calib-bytes N
+         --cmd-fetch "..." --cmd-write "..." [--json OUT.json]
+
+The pmc mode scales each kernel's FETCH_SIZE / WRITE_SIZE (KiB per dispatch)
+by the ratio "known bytes / counter reading" of the calibration copy kernel
+(a device-to-device copy of N bytes in the same run) and reports bytes per
+dispatch.  --json writes {kernel class: {fetch, write, sources}} where
+sources is a hash of the HIP sources, so a reader can tell whether the
+counters still describe the current kernels.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+import sys
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+# kernel symbol fragment -> timing class of the library
+CLASSES = [
+    ("k_first_pass", "fft_first"),
+    ("k_mid_pass<16, false>", "fft_mid_fwd"), ("k_mid_pass<32, false>", "fft_mid_fwd"),
+    ("k_mid_pass<16, true>", "fft_mid_inv"), ("k_mid_pass<32, true>", "fft_mid_inv"),
+    ("k_last_adj", "fft_last_adj"),
+    ("k_gather_staged<2, 6, 0>", "gather"), ("k_gather_staged<2, 6, 1>", "gather_jac"),
+    ("k_spread", "spread"), ("k_permute", "spread"),
+]
+
+
+def sources_hash() -> str:
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".cpp", ".h")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def short(name: str) -> str:
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "")
+    return name.split("(")[0] if "(" in name else name
+
+
+def stats(path: str, cmd: str) -> str:
+    rows = list(csv.DictReader(open(path)))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    out = [f"# rocprofv3 --kernel-trace --stats summary", f"# command: {cmd}",
+           f"# source hash: {sources_hash()}", "",
+           f"{'kernel':58s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>6s}"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        out.append(f"{short(r['Name'])[:58]:58s} {int(r['Calls']):6d} "
+                   f"{float(r['AverageNs']) / 1e3:10.1f} {float(r['MinNs']) / 1e3:10.1f} "
+                   f"{float(r['MaxNs']) / 1e3:10.1f} {100 * float(r['TotalDurationNs']) / total:6.2f}")
+    return "\n".join(out) + "\n"
+
+
+def _per_kernel(path):
+    agg = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return agg
+
+
+def pmc(fetch_csv, write_csv, calib_bytes, cmd_f, cmd_w, json_out=None) -> str:
+    fa = _per_kernel(fetch_csv)
+    wa = _per_kernel(write_csv)
+
+    def calib(agg):
+        # the calibration copy is the largest single dispatch of a copy kernel
+        best = None
+        for name, vals in agg.items():
+            if "elementwise" in name or "copyBuffer" in name:
+                v = max(vals)
+                best = v if best is None or v > best else best
+        return best
+
+    cf, cw = calib(fa), calib(wa)
+    sf = calib_bytes / (cf * 1024.0) if cf else float("nan")
+    sw = calib_bytes / (cw * 1024.0) if cw else float("nan")
+    out = ["# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE per dispatch (mean over dispatches)",
+           f"# fetch command: {cmd_f}", f"# write command: {cmd_w}",
+           f"# calibration: device copy of {calib_bytes} bytes read FETCH_SIZE={cf:.0f} KiB, "
+           f"WRITE_SIZE={cw:.0f} KiB -> scale fetch x{sf:.4f}, write x{sw:.4f}",
+           f"# source hash: {sources_hash()}", "",
+           f"{'kernel':58s} {'n':>4s} {'fetch_MB':>10s} {'write_MB':>10s}"]
+    classes = {}
+    for name in sorted(set(fa) | set(wa)):
+        f = sum(fa.get(name, [0])) / max(len(fa.get(name, [])), 1) * 1024.0 * sf
+        w = sum(wa.get(name, [0])) / max(len(wa.get(name, [])), 1) * 1024.0 * sw
+        out.append(f"{short(name)[:58]:58s} {len(fa.get(name, [])):4d} {f / 1e6:10.2f} {w / 1e6:10.2f}")
+        for frag, cls in CLASSES:
+            if frag in name:
+                c = classes.setdefault(cls, {"fetch": 0.0, "write": 0.0})
+                c["fetch"] += f
+                c["write"] += w
+    if json_out:
+        with open(json_out, "w") as fh:
+            json.dump({"sources": sources_hash(), "calib_bytes": calib_bytes,
+                       "classes": classes}, fh, indent=1)
+    return "\n".join(out) + "\n"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="mode", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("--cmd", required=True)
+    p = sub.add_parser("pmc")
+    p.add_argument("fetch_csv")
+    p.add_argument("write_csv")
+    p.add_argument("--calib-bytes", type=int, required=True)
+    p.add_argument("--cmd-fetch", required=True)
+    p.add_argument("--cmd-write", required=True)
+    p.add_argument("--json")
+    a = ap.parse_args()
+    if a.mode == "stats":
+        sys.stdout.write(stats(a.csv, a.cmd))
+    else:
+        sys.stdout.write(pmc(a.fetch_csv, a.write_csv, a.calib_bytes, a.cmd_fetch, a.cmd_write, a.json))
+
+
+if __name__ == "__main__":
+    main()
