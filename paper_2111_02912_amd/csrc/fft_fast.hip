@@ -1,0 +1,489 @@
+// Compile-time specialised FFT passes for the common oversampled grid sizes.
+//
+// Same operations as the generic passes in fft.hip (forward first pass with
+// the scaling / coil / coordinate-weight prologue, strided forward and
+// inverse passes with zero-padding and cropping, last inverse pass with
+// crop, scaling and coil sum), for L in a fixed set.  With L and the number
+// E of elements per thread known at compile time, every radix, stride and
+// index is a constant.  Each thread holds the inputs of its E / R
+// butterflies in registers; stage 0 reads them straight from global memory
+// (zero-padding rows are never read), the last stage writes straight to
+// global memory (cropped rows are never written), and only the stages in
+// between exchange data through LDS.
+//
+// Butterfly ownership (Stockham, natural order in and out): in stage s with
+// radix R and span Ns, thread u of a line owns butterflies j = u + TL*b,
+// b < E/R (TL = L/E threads per line); butterfly j reads elements
+// j + q*L/R and writes element (j - j%Ns)*R + j%Ns + q*Ns, q < R.
+#include "kbn_internal.h"
+
+#include <hip/hip_runtime.h>
+
+namespace {
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+template <bool INV>
+__device__ __forceinline__ float2 rot(float2 a) {  // * -i (forward) or * +i (inverse)
+    return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// ---- small DFTs (forward sign exp(-2 pi i / R), conjugate for INV) --------
+template <int R, bool INV>
+struct SDft;
+template <bool INV>
+struct SDft<2, INV> {
+    static __device__ __forceinline__ void run(float2 *a) {
+        const float2 t = a[0];
+        a[0] = cadd(t, a[1]);
+        a[1] = csub(t, a[1]);
+    }
+};
+template <bool INV>
+struct SDft<4, INV> {
+    static __device__ __forceinline__ void run(float2 *a) {
+        const float2 t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+        const float2 t2 = cadd(a[1], a[3]), t3 = rot<INV>(csub(a[1], a[3]));
+        a[0] = cadd(t0, t2);
+        a[2] = csub(t0, t2);
+        a[1] = cadd(t1, t3);
+        a[3] = csub(t1, t3);
+    }
+};
+template <bool INV>
+struct SDft<8, INV> {
+    static __device__ __forceinline__ void run(float2 *a) {
+        float2 e[4] = {a[0], a[2], a[4], a[6]};
+        float2 o[4] = {a[1], a[3], a[5], a[7]};
+        SDft<4, INV>::run(e);
+        SDft<4, INV>::run(o);
+        const float r = 0.70710678118654752f;
+        float2 w1, w3;
+        if (!INV) {
+            w1 = make_float2(r * (o[1].x + o[1].y), r * (o[1].y - o[1].x));
+            w3 = make_float2(r * (o[3].y - o[3].x), -r * (o[3].x + o[3].y));
+        } else {
+            w1 = make_float2(r * (o[1].x - o[1].y), r * (o[1].x + o[1].y));
+            w3 = make_float2(-r * (o[3].x + o[3].y), r * (o[3].x - o[3].y));
+        }
+        const float2 w2 = rot<INV>(o[2]);
+        a[0] = cadd(e[0], o[0]);
+        a[4] = csub(e[0], o[0]);
+        a[1] = cadd(e[1], w1);
+        a[5] = csub(e[1], w1);
+        a[2] = cadd(e[2], w2);
+        a[6] = csub(e[2], w2);
+        a[3] = cadd(e[3], w3);
+        a[7] = csub(e[3], w3);
+    }
+};
+template <int R>
+struct STrig;
+template <>
+struct STrig<3> {
+    static constexpr float c[3] = {1.0f, -0.5f, -0.5f};
+    static constexpr float s[3] = {0.0f, 0.86602540378443865f, -0.86602540378443865f};
+};
+template <>
+struct STrig<5> {
+    static constexpr float c[5] = {1.0f, 0.30901699437494742f, -0.80901699437494742f,
+                                   -0.80901699437494742f, 0.30901699437494742f};
+    static constexpr float s[5] = {0.0f, 0.95105651629515357f, 0.58778525229247313f,
+                                   -0.58778525229247313f, -0.95105651629515357f};
+};
+template <int R, bool INV>
+struct SDftOdd {
+    static __device__ __forceinline__ void run(float2 *a) {
+        constexpr int H = (R - 1) / 2;
+        float2 sp[H], sm[H];
+#pragma unroll
+        for (int n = 1; n <= H; ++n) {
+            sp[n - 1] = cadd(a[n], a[R - n]);
+            sm[n - 1] = csub(a[n], a[R - n]);
+        }
+        const float2 a0 = a[0];
+        float2 sum = a0;
+#pragma unroll
+        for (int n = 0; n < H; ++n) sum = cadd(sum, sp[n]);
+        a[0] = sum;
+#pragma unroll
+        for (int k = 1; k <= H; ++k) {
+            float2 A = a0, Bv = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int n = 1; n <= H; ++n) {
+                const int idx = (n * k) % R;
+                A.x += sp[n - 1].x * STrig<R>::c[idx];
+                A.y += sp[n - 1].y * STrig<R>::c[idx];
+                Bv.x += sm[n - 1].x * STrig<R>::s[idx];
+                Bv.y += sm[n - 1].y * STrig<R>::s[idx];
+            }
+            const float2 iB = make_float2(-Bv.y, Bv.x);
+            a[k] = INV ? cadd(A, iB) : csub(A, iB);
+            a[R - k] = INV ? csub(A, iB) : cadd(A, iB);
+        }
+    }
+};
+template <bool INV>
+struct SDft<3, INV> : SDftOdd<3, INV> {};
+template <bool INV>
+struct SDft<5, INV> : SDftOdd<5, INV> {};
+
+// ---- compile-time radix plan -----------------------------------------------
+constexpr int pick_radix(int rem, int E) {
+    return (rem % 8 == 0 && E % 8 == 0)   ? 8
+           : (rem % 4 == 0 && E % 4 == 0) ? 4
+           : (rem % 2 == 0 && E % 2 == 0) ? 2
+           : (rem % 3 == 0 && E % 3 == 0) ? 3
+           : (rem % 5 == 0 && E % 5 == 0) ? 5
+                                          : 0;
+}
+constexpr int rem_at(int L, int E, int s) {
+    int rem = L;
+    for (int i = 0; i < s; ++i) rem /= pick_radix(rem, E);
+    return rem;
+}
+constexpr int nstages(int L, int E) {
+    int rem = L, n = 0;
+    while (rem > 1) {
+        const int r = pick_radix(rem, E);
+        if (r == 0) return -1;
+        rem /= r;
+        ++n;
+    }
+    return n;
+}
+
+template <int L_, int E_, bool INV_>
+struct Fft {
+    static constexpr int L = L_, E = E_, TL = L_ / E_;
+    static constexpr bool INV = INV_;
+    static constexpr int NST = nstages(L_, E_);
+    static_assert(NST > 0, "no radix plan for this (L, E)");
+    template <int S>
+    static constexpr int R() { return pick_radix(rem_at(L, E, S), E); }
+    template <int S>
+    static constexpr int Ns() { return L / rem_at(L, E, S); }
+    // input position of register element i = b*R + q in stage S
+    template <int S>
+    static __device__ __forceinline__ int in_pos(int u, int i) {
+        constexpr int Rr = R<S>();
+        return u + TL * (i / Rr) + (i % Rr) * (L / Rr);
+    }
+    // output position of register element i after stage S
+    template <int S>
+    static __device__ __forceinline__ int out_pos(int u, int i) {
+        constexpr int Rr = R<S>(), N = Ns<S>();
+        const int j = u + TL * (i / Rr);
+        const int k = j % N;
+        return (j - k) * Rr + k + (i % Rr) * N;
+    }
+    // twiddles and butterflies of stage S on the registers
+    template <int S>
+    static __device__ __forceinline__ void bfly(float2 (&v)[E], int u, const float2 *__restrict__ tw) {
+        constexpr int Rr = R<S>(), N = Ns<S>(), NB = E / Rr, TS = L / (N * Rr);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if (N > 1) {
+                const int k = (u + TL * b) % N;
+#pragma unroll
+                for (int q = 1; q < Rr; ++q) {
+                    float2 t = tw[q * k * TS];
+                    if (INV) t.y = -t.y;
+                    v[b * Rr + q] = cmul(v[b * Rr + q], t);
+                }
+            }
+            SDft<Rr, INV>::run(&v[b * Rr]);
+        }
+    }
+};
+
+// Runs stages S..NST-1.  `lds_idx(pos)` maps a line position to its LDS
+// index; `sink(i, pos, value)` consumes the last stage's outputs.
+template <class F, int S>
+struct Stages {
+    template <class LdsIdx, class Sink>
+    static __device__ __forceinline__ void run(float2 (&v)[F::E], int u, const float2 *tw, float2 *lds,
+                                               LdsIdx lds_idx, Sink sink) {
+        F::template bfly<S>(v, u, tw);
+        if constexpr (S + 1 < F::NST) {
+            if (S > 0) __syncthreads();  // stage S's LDS reads are done everywhere
+#pragma unroll
+            for (int i = 0; i < F::E; ++i) lds[lds_idx(F::template out_pos<S>(u, i))] = v[i];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < F::E; ++i) v[i] = lds[lds_idx(F::template in_pos<S + 1>(u, i))];
+            Stages<F, S + 1>::run(v, u, tw, lds, lds_idx, sink);
+        } else {
+#pragma unroll
+            for (int i = 0; i < F::E; ++i) sink(i, F::template out_pos<S>(u, i), v[i]);
+        }
+    }
+};
+
+// image index of line position p for a line of n values centred at r = 0
+// (r = j - floor(n/2) sits at p = r mod L); -1 for zero-padding positions
+template <int L>
+__device__ __forceinline__ int pos_to_img(int p, int n) {
+    const int h = n / 2;
+    if (p < n - h) return p + h;
+    if (p >= L - h) return p - L + h;
+    return -1;
+}
+
+// ---- strided pass along a non-last axis -------------------------------------
+// lines = LINES adjacent columns; LDS layout [position][column] (column fastest)
+template <int L, int E, bool INV>
+__global__ void __launch_bounds__(KBN_BLOCK) k_cols(KbnMidPassArgs a, const float2 *__restrict__ tw) {
+    using F = Fft<L, E, INV>;
+    constexpr int LINES = KBN_BLOCK / F::TL;
+    __shared__ float2 lds[L * LINES];
+    const int l = threadIdx.x % LINES;
+    const int u = threadIdx.x / LINES;
+    const int ntile = (a.inner + LINES - 1) / LINES;
+    const int64_t o = blockIdx.x / ntile;
+    const int c0 = (int)(blockIdx.x - o * ntile) * LINES;
+    const bool col_ok = c0 + l < a.inner;
+    const float2 *in = a.in + (o * a.nin) * (int64_t)a.inner + c0 + l;
+    float2 *out = a.out + (o * a.nout) * (int64_t)a.inner + c0 + l;
+    float2 v[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int p = F::template in_pos<0>(u, i);
+        const int r = a.pad_in ? pos_to_img<L>(p, a.nin) : p;
+        v[i] = (col_ok && r >= 0) ? in[(int64_t)r * a.inner] : make_float2(0.f, 0.f);
+    }
+    auto lds_idx = [](int pos) { return pos * LINES; };
+    float2 *ldsl = lds + l;
+    auto sink = [&](int, int pos, float2 val) {
+        const int r = a.crop_out ? pos_to_img<L>(pos, a.nout) : pos;
+        if (col_ok && r >= 0) out[(int64_t)r * a.inner] = val;
+    };
+    Stages<F, 0>::run(v, u, tw, ldsl, lds_idx, sink);
+}
+
+// ---- forward first pass along the last axis (with prologue) ----------------
+// LDS layout [line][position]
+template <int L, int E>
+__global__ void __launch_bounds__(KBN_BLOCK) k_rows_first(KbnFirstPassArgs a, const float2 *__restrict__ tw) {
+    using F = Fft<L, E, false>;
+    constexpr int LINES = KBN_BLOCK / F::TL;
+    __shared__ float2 lds[L * LINES];
+    __shared__ float2 twl[L];
+    for (int i = threadIdx.x; i < L; i += KBN_BLOCK) twl[i] = tw[i];
+    const int li = threadIdx.x / F::TL;
+    const int u = threadIdx.x % F::TL;
+    const int64_t line = (int64_t)blockIdx.x * LINES + li;
+    const bool line_ok = line < a.nlines;
+    const int Nl = a.Nl;
+    float2 v[E];
+    // per-line constants
+    int64_t xrow = 0, srow = 0;
+    float lf = 0.f;
+    int wsel = -1;
+    if (line_ok) {
+        const int64_t ch = line / a.R0;
+        const int row = (int)(line - ch * a.R0);
+        const int w = (int)(ch % a.nw);
+        const int64_t cc = ch / a.nw;
+        const int c = (int)(cc % a.C);
+        const int64_t bl = cc / a.C;
+        wsel = a.weighted ? w : -1;
+        xrow = (bl * a.R0 + row) * (int64_t)Nl;
+        srow = ((int64_t)c * a.R0 + row) * Nl;
+        float f = 1.f;
+        int rem = row;
+        for (int d = a.D - 2; d >= 0; --d) {
+            const int id = rem % a.N[d];
+            rem /= a.N[d];
+            f *= a.deap[d][id];
+            if (wsel == d) f *= (float)(id - a.N[d] / 2);
+        }
+        lf = f;
+    }
+    const float *deap_l = a.deap[a.D - 1];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int p = F::template in_pos<0>(u, i);
+        const int j = pos_to_img<L>(p, Nl);
+        float2 x = make_float2(0.f, 0.f);
+        if (line_ok && j >= 0) {
+            x = a.x[xrow + j];
+            float f = lf * deap_l[j];
+            if (wsel == a.D - 1) f *= (float)(j - Nl / 2);
+            if (a.smaps) x = cmul(x, a.smaps[srow + j]);
+            x = make_float2(x.x * f, x.y * f);
+        }
+        v[i] = x;
+    }
+    __syncthreads();  // twiddles in LDS
+    float2 *out = a.out + line * L;
+    auto lds_idx = [](int pos) { return pos; };
+    float2 *ldsl = lds + li * L;
+    auto sink = [&](int, int pos, float2 val) {
+        if (line_ok) out[pos] = val;
+    };
+    Stages<F, 0>::run(v, u, twl, ldsl, lds_idx, sink);
+}
+
+// ---- last inverse pass along the last axis (crop, scaling, coil sum) -------
+template <int L, int E>
+__global__ void __launch_bounds__(KBN_BLOCK) k_rows_last_adj(KbnLastAdjArgs a, const float2 *__restrict__ tw) {
+    using F = Fft<L, E, true>;
+    constexpr int LINES = KBN_BLOCK / F::TL;
+    __shared__ float2 lds[L * LINES];
+    __shared__ float2 twl[L];
+    for (int i = threadIdx.x; i < L; i += KBN_BLOCK) twl[i] = tw[i];
+    const int li = threadIdx.x / F::TL;
+    const int u = threadIdx.x % F::TL;
+    const int64_t line = (int64_t)blockIdx.x * LINES + li;
+    const bool line_ok = line < a.nlines;
+    const int Nl = a.Nl;
+    int64_t bl = 0;
+    int row = 0;
+    float lf = 0.f;
+    if (line_ok) {
+        bl = line / a.R0;
+        row = (int)(line - bl * a.R0);
+        float f = 1.f;
+        int rem = row;
+        for (int d = a.D - 2; d >= 0; --d) {
+            const int id = rem % a.N[d];
+            rem /= a.N[d];
+            f *= a.deap[d][id];
+        }
+        lf = f;
+    }
+    const float *deap_l = a.deap[a.D - 1];
+    float2 acc[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) acc[i] = make_float2(0.f, 0.f);
+    __syncthreads();  // twiddles in LDS
+    for (int c = 0; c < a.C; ++c) {
+        const float2 *in = a.in + (((bl * a.C + c) * a.R0) + row) * (int64_t)L;
+        float2 v[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int p = F::template in_pos<0>(u, i);
+            v[i] = line_ok ? in[p] : make_float2(0.f, 0.f);
+        }
+        if (c > 0) __syncthreads();  // previous coil's last LDS reads are done
+        const float2 *srow = a.smaps ? a.smaps + ((int64_t)c * a.R0 + row) * Nl : nullptr;
+        auto lds_idx = [](int pos) { return pos; };
+        float2 *ldsl = lds + li * L;
+        auto sink = [&](int i, int pos, float2 val) {
+            const int j = pos_to_img<L>(pos, Nl);
+            if (line_ok && j >= 0) {
+                if (srow) val = cmulc(val, srow[j]);
+                const float f = lf * deap_l[j];
+                acc[i].x += val.x * f;
+                acc[i].y += val.y * f;
+            }
+        };
+        Stages<F, 0>::run(v, u, twl, ldsl, lds_idx, sink);
+    }
+    // write: register element i of the last stage holds line position out_pos
+    float2 *x = a.x + line * Nl;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int pos = F::template out_pos<F::NST - 1>(u, i);
+        const int j = pos_to_img<L>(pos, Nl);
+        if (line_ok && j >= 0) {
+            if (a.accumulate) {
+                const float2 o = x[j];
+                x[j] = make_float2(o.x + acc[i].x, o.y + acc[i].y);
+            } else {
+                x[j] = acc[i];
+            }
+        }
+    }
+}
+
+// Elements per thread for each specialised length: rows (last axis) and
+// columns (strided axes, 64 KiB of LDS per workgroup).
+constexpr int row_e(int L) {
+    return L == 128 ? 8 : L == 256 ? 8 : L == 512 ? 8 : L == 1024 ? 16 : L == 192 ? 12
+           : L == 384 ? 12 : L == 640 ? 20 : L == 768 ? 24 : 0;
+}
+constexpr int col_e(int L) {
+    return L == 128 ? 8 : L == 256 ? 16 : L == 512 ? 32 : L == 1024 ? 32 : L == 192 ? 12
+           : L == 384 ? 24 : L == 640 ? 20 : L == 768 ? 24 : 0;
+}
+
+template <int L>
+hipError_t launch_cols(const KbnMidPassArgs &a, const float2 *tw, int inverse, hipStream_t s) {
+    constexpr int E = col_e(L);
+    constexpr int LINES = KBN_BLOCK / (L / E);
+    const int64_t ntile = (a.inner + LINES - 1) / LINES;
+    const dim3 grid((unsigned)(a.outer * ntile));
+    if (inverse)
+        k_cols<L, E, true><<<grid, dim3(KBN_BLOCK), 0, s>>>(a, tw);
+    else
+        k_cols<L, E, false><<<grid, dim3(KBN_BLOCK), 0, s>>>(a, tw);
+    return hipGetLastError();
+}
+
+template <int L>
+hipError_t launch_rows_first(const KbnFirstPassArgs &a, const float2 *tw, hipStream_t s) {
+    constexpr int E = row_e(L);
+    constexpr int LINES = KBN_BLOCK / (L / E);
+    const dim3 grid((unsigned)((a.nlines + LINES - 1) / LINES));
+    k_rows_first<L, E><<<grid, dim3(KBN_BLOCK), 0, s>>>(a, tw);
+    return hipGetLastError();
+}
+
+template <int L>
+hipError_t launch_rows_last(const KbnLastAdjArgs &a, const float2 *tw, hipStream_t s) {
+    constexpr int E = row_e(L);
+    constexpr int LINES = KBN_BLOCK / (L / E);
+    const dim3 grid((unsigned)((a.nlines + LINES - 1) / LINES));
+    k_rows_last_adj<L, E><<<grid, dim3(KBN_BLOCK), 0, s>>>(a, tw);
+    return hipGetLastError();
+}
+
+#define KBN_FAST_SIZES(X) X(128) X(192) X(256) X(384) X(512) X(640) X(768) X(1024)
+
+}  // namespace
+
+bool kbn_fast_fft_size(int L) {
+    switch (L) {
+#define KBN_CASE(n) case n:
+        KBN_FAST_SIZES(KBN_CASE)
+#undef KBN_CASE
+        return true;
+        default: return false;
+    }
+}
+
+hipError_t kbn_launch_fast_mid(const KbnMidPassArgs &a, int L, const float2 *tw, int inverse,
+                               hipStream_t s) {
+    switch (L) {
+#define KBN_CASE(n) case n: return launch_cols<n>(a, tw, inverse, s);
+        KBN_FAST_SIZES(KBN_CASE)
+#undef KBN_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t kbn_launch_fast_first(const KbnFirstPassArgs &a, int L, const float2 *tw, hipStream_t s) {
+    switch (L) {
+#define KBN_CASE(n) case n: return launch_rows_first<n>(a, tw, s);
+        KBN_FAST_SIZES(KBN_CASE)
+#undef KBN_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t kbn_launch_fast_last(const KbnLastAdjArgs &a, int L, const float2 *tw, hipStream_t s) {
+    switch (L) {
+#define KBN_CASE(n) case n: return launch_rows_last<n>(a, tw, s);
+        KBN_FAST_SIZES(KBN_CASE)
+#undef KBN_CASE
+        default: return hipErrorInvalidValue;
+    }
+}

@@ -125,6 +125,14 @@ hipError_t kbn_launch_last_adj(const KbnLastAdjArgs &a, const KbnRadix &rp, cons
                                int maxe, hipStream_t s);
 int kbn_lines_per_block(const KbnRadix &rp, int maxe);
 
+// Compile-time specialised passes (fft_fast.hip) for the lengths where
+// kbn_fast_fft_size() is true; they return hipErrorInvalidValue otherwise.
+bool kbn_fast_fft_size(int L);
+hipError_t kbn_launch_fast_first(const KbnFirstPassArgs &a, int L, const float2 *tw, hipStream_t s);
+hipError_t kbn_launch_fast_mid(const KbnMidPassArgs &a, int L, const float2 *tw, int inverse,
+                               hipStream_t s);
+hipError_t kbn_launch_fast_last(const KbnLastAdjArgs &a, int L, const float2 *tw, hipStream_t s);
+
 // ---------------------------------------------------------------------------
 // Interpolation (interp.hip)
 // ---------------------------------------------------------------------------

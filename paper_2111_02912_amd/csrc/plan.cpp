@@ -187,6 +187,7 @@ struct kbn_plan_s {
     float *coef = nullptr;
     int *flag = nullptr;
     int maxe = 16;
+    bool fast_fft = true;  // use the specialised FFT passes where available
     // points
     int64_t M = -1, Mcap = 0;
     int *cell_tmp = nullptr, *tile = nullptr, *order = nullptr, *cell = nullptr, *toff = nullptr;
@@ -372,8 +373,13 @@ int run_type2(kbn_plan p, int B, int C, int nw, int weighted, const float2 *x,
             fa.N[d] = p->N[d];
             fa.deap[d] = p->deap[d];
         }
-        KBN_LAUNCH(KBN_CLASS_FFT_FIRST, kbn_launch_first_pass(fa, p->rad[D - 1], p->tw[D - 1], p->maxe, stream),
-                   "first pass");
+        if (p->fast_fft && kbn_fast_fft_size(p->K[D - 1]))
+            KBN_LAUNCH(KBN_CLASS_FFT_FIRST, kbn_launch_fast_first(fa, p->K[D - 1], p->tw[D - 1], stream),
+                       "first pass");
+        else
+            KBN_LAUNCH(KBN_CLASS_FFT_FIRST,
+                       kbn_launch_first_pass(fa, p->rad[D - 1], p->tw[D - 1], p->maxe, stream),
+                       "first pass");
         float2 *cur = bufA, *nxt = bufB;
         for (int d = D - 2; d >= 0; --d) {
             int64_t outer = nch, inner = 1;
@@ -388,7 +394,12 @@ int run_type2(kbn_plan p, int B, int C, int nw, int weighted, const float2 *x,
             ma.inner = (int)inner;
             ma.pad_in = 1;
             ma.crop_out = 0;
-            KBN_LAUNCH(KBN_CLASS_FFT_MID_FWD, kbn_launch_mid_pass(ma, p->rad[d], p->tw[d], 0, p->maxe, stream), "mid pass");
+            if (p->fast_fft && kbn_fast_fft_size(p->K[d]))
+                KBN_LAUNCH(KBN_CLASS_FFT_MID_FWD, kbn_launch_fast_mid(ma, p->K[d], p->tw[d], 0, stream),
+                           "mid pass");
+            else
+                KBN_LAUNCH(KBN_CLASS_FFT_MID_FWD,
+                           kbn_launch_mid_pass(ma, p->rad[d], p->tw[d], 0, p->maxe, stream), "mid pass");
             std::swap(cur, nxt);
         }
         KbnGatherArgs ga;
@@ -462,7 +473,12 @@ int run_type1(kbn_plan p, int B, int C, const float2 *y, const float2 *smaps, fl
             ma.inner = (int)inner;
             ma.pad_in = 0;
             ma.crop_out = 1;
-            KBN_LAUNCH(KBN_CLASS_FFT_MID_INV, kbn_launch_mid_pass(ma, p->rad[d], p->tw[d], 1, p->maxe, stream), "mid pass");
+            if (p->fast_fft && kbn_fast_fft_size(p->K[d]))
+                KBN_LAUNCH(KBN_CLASS_FFT_MID_INV, kbn_launch_fast_mid(ma, p->K[d], p->tw[d], 1, stream),
+                           "mid pass");
+            else
+                KBN_LAUNCH(KBN_CLASS_FFT_MID_INV,
+                           kbn_launch_mid_pass(ma, p->rad[d], p->tw[d], 1, p->maxe, stream), "mid pass");
             std::swap(cur, nxt);
         }
         KbnLastAdjArgs la;
@@ -479,8 +495,13 @@ int run_type1(kbn_plan p, int B, int C, const float2 *y, const float2 *smaps, fl
             la.N[d] = p->N[d];
             la.deap[d] = p->deap[d];
         }
-        KBN_LAUNCH(KBN_CLASS_FFT_LAST_ADJ, kbn_launch_last_adj(la, p->rad[D - 1], p->tw[D - 1], p->maxe, stream),
-                   "last adjoint pass");
+        if (p->fast_fft && kbn_fast_fft_size(p->K[D - 1]))
+            KBN_LAUNCH(KBN_CLASS_FFT_LAST_ADJ, kbn_launch_fast_last(la, p->K[D - 1], p->tw[D - 1], stream),
+                       "last adjoint pass");
+        else
+            KBN_LAUNCH(KBN_CLASS_FFT_LAST_ADJ,
+                       kbn_launch_last_adj(la, p->rad[D - 1], p->tw[D - 1], p->maxe, stream),
+                       "last adjoint pass");
     }
     return KBN_OK;
 }
@@ -517,6 +538,7 @@ int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts
     p->beta = M_PI * std::sqrt(rad);
     p->max_ws = o.max_workspace > 0 ? o.max_workspace : (int64_t)4 << 30;
     if (const char *e = std::getenv("KBN_MAXE")) p->maxe = std::atoi(e) == 32 ? 32 : 16;
+    if (const char *e = std::getenv("KBN_GENERIC_FFT")) p->fast_fft = std::atoi(e) == 0;
     const int deftile = D == 1 ? 256 : (D == 2 ? 32 : 16);
     int64_t ntiles = 1;
     for (int d = 0; d < D; ++d) {

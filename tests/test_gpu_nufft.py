@@ -243,3 +243,27 @@ def test_throughput_shape_sampled(dev):
     dom = _np(p.jac_omega_fwd(_c(x, dev), _c(g, dev)))
     exact_j = ndft.jac_omega_fwd(om, x, g, N, rows=rows)
     assert ndft.rel_l2(dom[rows], exact_j) < TOL_JAC
+
+
+@pytest.mark.parametrize("N", [(64, 96), (160, 128), (48, 40, 64)])
+def test_specialised_fft_matches_generic(N, dev, monkeypatch):
+    """The compile-time specialised FFT passes and the generic ones agree, and
+    both match the oracle (K = 128, 192, 320->generic, 256, 96->generic...)."""
+    _say(f"specialised vs generic FFT N={N}")
+    D = len(N)
+    om = W.uniform_random(2500, D, seed=91)
+    M = om.shape[0]
+    x = W.complex_normal((2,) + N, 92)
+    g = W.complex_normal((2, 1, M), 93)
+    outs = []
+    for generic in ("0", "1"):
+        monkeypatch.setenv("KBN_GENERIC_FFT", generic)
+        p = _plan(N, dev)
+        p.set_points(_f(om, dev))
+        outs.append((_np(p.forward(_c(x, dev))), _np(p.adjoint(_c(g, dev))),
+                     _np(p.jac_omega_fwd(_c(x, dev), _c(g, dev)))))
+    for a, b in zip(*outs):
+        assert ndft.rel_l2(a, b) < 2e-6
+    ref = nufft_ref.Params(N, 2.0, 6)
+    assert ndft.rel_l2(outs[0][0][:, 0], nufft_ref.forward(ref, om, x)) < TOL_STEPS
+    assert ndft.rel_l2(outs[0][1], nufft_ref.adjoint(ref, om, g[:, 0])) < TOL_STEPS
