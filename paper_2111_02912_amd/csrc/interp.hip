@@ -326,8 +326,12 @@ template <int D, int J, int A>
 __global__ void __launch_bounds__(KBN_BLOCK) k_spread(KbnGeom g, KbnSpreadArgs a, int cw, int nwave) {
     constexpr int EB = KBN_SPREAD_EB;
     constexpr int LANES_TAP = A == 1 ? J : J * J;
+    constexpr int NEG = -(1 << 28);                // offset of a tap outside the tile
     extern __shared__ float smem[];
-    const int tile = a.otile_order[blockIdx.y];   // owner tiles, most entries first
+    const int wk = blockIdx.y;                     // work item
+    if (wk >= a.scounts[0]) return;
+    const int tile = a.swork[4 * wk];
+    const int slot = a.swork[4 * wk + 3];
     const int ngroup = nwave * cw;                 // channels per workgroup
     const int ch0 = blockIdx.x * ngroup;
     const int nchg = min(ngroup, a.nch - ch0);
@@ -343,16 +347,19 @@ __global__ void __launch_bounds__(KBN_BLOCK) k_spread(KbnGeom g, KbnSpreadArgs a
         }
     }
     int psize = 1, tsize = 1;
-    for (int d = 0; d < D; ++d) {
+    int stride[KBN_MAX_D];
+    for (int d = D - 1; d >= 0; --d) {
+        stride[d] = psize;
         psize *= pt[d];
         tsize *= te[d];
     }
     const int plane = spread_plane(psize);         // float2 per channel plane
     float2 *acc = reinterpret_cast<float2 *>(smem);
-    int *ent_p = reinterpret_cast<int *>(acc + (size_t)ngroup * plane);
-    int *ent_l = ent_p + EB;                       // [EB][D]
-    float *ent_w = reinterpret_cast<float *>(ent_l + EB * D);  // [EB][D][J]
-    float2 *ent_y = reinterpret_cast<float2 *>(ent_w + EB * D * J);  // [ngroup][EB + 1]
+    // per staged entry and axis tap: (offset in the tile accumulator or NEG
+    // when outside the tile, as int bits; weight)
+    float2 *ent_ow = reinterpret_cast<float2 *>(acc + (size_t)ngroup * plane);  // [EB][D][J]
+    int *ent_p = reinterpret_cast<int *>(ent_ow + EB * D * J);
+    float2 *ent_y = reinterpret_cast<float2 *>(ent_p + EB);  // [ngroup][EB + 1]
     const int nthr = nwave * 64;
     for (int i = threadIdx.x; i < nchg * plane; i += nthr) acc[i] = make_float2(0.f, 0.f);
 
@@ -362,129 +369,198 @@ __global__ void __launch_bounds__(KBN_BLOCK) k_spread(KbnGeom g, KbnSpreadArgs a
     const int jin = lane - cc * LANES_TAP;
     const int cl = wave * cw + cc;                 // channel of this lane within the group
     const bool lane_on = cc < cw && cl < nchg;
-    // inner-tap coordinates of this lane
-    const int jb = A == 1 ? jin : jin % J;         // last axis
-    const int ja = A == 1 ? 0 : jin / J;           // second-to-last axis (A == 2)
+    const int jb = A == 1 ? jin : jin % J;         // tap along the last axis
+    const int ja = A == 1 ? 0 : jin / J;           // tap along the axis before it (A == 2)
 
-    const int e0 = a.ooff[tile], e1 = a.ooff[tile + 1];
+    const int e0 = a.swork[4 * wk + 1], e1 = a.swork[4 * wk + 2];
     for (int eb = e0; eb < e1; eb += EB) {
         const int n = min(EB, e1 - eb);
         __syncthreads();  // previous batch fully consumed (and acc zeroed)
         if ((int)threadIdx.x < n) {
+            // stage entry t: precomputed record -> per-axis tap offsets and weights
             const int t = threadIdx.x;
-            const int p = a.oent[eb + t];
-            ent_p[t] = p;
+            const int e = eb + t;
+            ent_p[t] = a.rec_p[e];
 #pragma unroll
             for (int d = 0; d < D; ++d) {
-                int start;
-                float f;
-                tap_origin(J, a.cell[d * a.M + p], a.frac[d * a.M + p], start, f);
-                int l = start - a0[d];
-                if (l < 0) l += g.K[d];
-                if (l < 0) l += g.K[d];
-                ent_l[t * D + d] = l;
-                kb_weights<J>(f, g.coef, ent_w + (t * D + d) * J);
+                const int l = a.rec_l[(int64_t)e * D + d];
+                float w[J];
+                kb_weights<J>(a.rec_f[(int64_t)e * D + d], g.coef, w);
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    int loc = l + j;
+                    if (loc >= g.K[d]) loc -= g.K[d];
+                    const int off = loc < te[d] ? loc * stride[d] : NEG;
+                    ent_ow[(t * D + d) * J + j] = make_float2(__int_as_float(off), w[j]);
+                }
             }
         }
         __syncthreads();
-        for (int idx = threadIdx.x; idx < n * nchg; idx += nthr) {
-            const int c = idx / n;
-            const int i = idx - c * n;
-            ent_y[c * (EB + 1) + i] = a.ys[(int64_t)(ch0 + c) * a.M + ent_p[i]];
+        // k-space values of the staged entries: EB entries x channels, with
+        // nthr / EB channels per pass (nthr is a multiple of EB)
+        {
+            const int i = threadIdx.x % EB;
+            const int cstep = nthr / EB;
+            if (i < n) {
+                const int pi = ent_p[i];
+                for (int c = threadIdx.x / EB; c < nchg; c += cstep)
+                    ent_y[c * (EB + 1) + i] = a.ys[(int64_t)(ch0 + c) * a.M + pi];
+            }
         }
         __syncthreads();
         if (lane_on) {
             float2 *accc = acc + (size_t)cl * plane;
             const float2 *yc = ent_y + cl * (EB + 1);
             for (int i = 0; i < n; ++i) {
-                const int *li = ent_l + i * D;
-                const float *wi = ent_w + i * D * J;
-                // trailing axis
-                int lb = li[D - 1] + jb;
-                if (lb >= g.K[D - 1]) lb -= g.K[D - 1];
-                bool in = lb < te[D - 1];
-                float wv = wi[(D - 1) * J + jb];
-                int inner = lb;
+                const float2 *owi = ent_ow + i * D * J;
+                const float2 ib = owi[(D - 1) * J + jb];
+                int inner = __float_as_int(ib.x);
+                float wv = ib.y;
                 if (A == 2) {
-                    int la = li[D - 2] + ja;
-                    if (la >= g.K[D - 2]) la -= g.K[D - 2];
-                    in = in && la < te[D - 2];
-                    wv *= wi[(D - 2) * J + ja];
-                    inner += la * pt[D - 1];
+                    const float2 ia = owi[(D - 2) * J + ja];
+                    inner += __float_as_int(ia.x);
+                    wv *= ia.y;
                 }
                 const float2 yv = yc[i];
                 const float2 v = make_float2(wv * yv.x, wv * yv.y);
-                if (D - A == 0) {
-                    if (in) {
-                        float2 o = accc[inner];
-                        accc[inner] = make_float2(o.x + v.x, o.y + v.y);
+                constexpr int NO = D - A == 0 ? 1 : (D - A == 1 ? J : J * J);  // outer taps
+                float2 o[NO];
+                int cidx[NO];
+                float wo[NO];
+#pragma unroll
+                for (int t = 0; t < NO; ++t) {
+                    int off = inner;
+                    float wt = 1.f;
+                    if (D - A >= 1) {
+                        const int j0 = D - A == 1 ? t : t / J;
+                        const float2 r0 = owi[j0];
+                        off += __float_as_int(r0.x);
+                        wt = r0.y;
                     }
-                } else if (D - A == 1) {
-                    // all reads of this entry first (distinct rows), then the writes
-                    const int stride0 = D == 2 ? pt[1] : pt[1] * pt[2];
-                    float2 o[J];
-                    int cidx[J];
-                    bool ok[J];
-#pragma unroll
-                    for (int j0 = 0; j0 < J; ++j0) {
-                        int l0 = li[0] + j0;
-                        if (l0 >= g.K[0]) l0 -= g.K[0];
-                        ok[j0] = in && l0 < te[0];
-                        cidx[j0] = l0 * stride0 + inner;
-                        if (ok[j0]) o[j0] = accc[cidx[j0]];
+                    if (D - A == 2) {
+                        const int j1 = t % J;
+                        const float2 r1 = owi[J + j1];
+                        off += __float_as_int(r1.x);
+                        wt *= r1.y;
                     }
-#pragma unroll
-                    for (int j0 = 0; j0 < J; ++j0) {
-                        const float w0 = wi[j0];
-                        if (ok[j0]) accc[cidx[j0]] = make_float2(fmaf(w0, v.x, o[j0].x), fmaf(w0, v.y, o[j0].y));
-                    }
-                } else {  // D == 3, A == 1: one row of J cells per j0, reads before writes
-#pragma unroll
-                    for (int j0 = 0; j0 < J; ++j0) {
-                        int l0 = li[0] + j0;
-                        if (l0 >= g.K[0]) l0 -= g.K[0];
-                        const float w0 = wi[j0];
-                        float2 o[J];
-                        int cidx[J];
-                        bool ok[J];
-#pragma unroll
-                        for (int j1 = 0; j1 < J; ++j1) {
-                            int l1 = li[1] + j1;
-                            if (l1 >= g.K[1]) l1 -= g.K[1];
-                            ok[j1] = in && l0 < te[0] && l1 < te[1];
-                            cidx[j1] = (l0 * pt[1] + l1) * pt[2] + inner;
-                            if (ok[j1]) o[j1] = accc[cidx[j1]];
-                        }
-#pragma unroll
-                        for (int j1 = 0; j1 < J; ++j1) {
-                            const float w01 = w0 * wi[J + j1];
-                            if (ok[j1])
-                                accc[cidx[j1]] = make_float2(fmaf(w01, v.x, o[j1].x), fmaf(w01, v.y, o[j1].y));
-                        }
-                    }
+                    cidx[t] = off;
+                    wo[t] = wt;
+                    if (off >= 0) o[t] = accc[off];
                 }
+#pragma unroll
+                for (int t = 0; t < NO; ++t)
+                    if (cidx[t] >= 0)
+                        accc[cidx[t]] = make_float2(fmaf(wo[t], v.x, o[t].x), fmaf(wo[t], v.y, o[t].y));
             }
         }
     }
     __syncthreads();
-    // write the owned tile of every channel in the group
-    for (int c = 0; c < nchg; ++c) {
-        float2 *G = a.grid + (int64_t)(ch0 + c) * a.gsize;
-        const float2 *src = acc + (size_t)c * plane;
-        for (int i = threadIdx.x; i < tsize; i += nthr) {
-            int rem = i;
-            int64_t off = 0, stride = 1;
-            int lo = 0, lstride = 1;
-            for (int d = D - 1; d >= 0; --d) {
-                const int l = rem % te[d];
-                rem /= te[d];
-                off += (int64_t)(a0[d] + l) * stride;
-                stride *= g.K[d];
-                lo += l * lstride;
-                lstride *= pt[d];
-            }
-            G[off] = src[lo];
+    // write the owned tile of every channel in the group: to the grid, or
+    // (tile split into several work items) to this item's partial slot.
+    // Threads cover (channel, row) pairs x last-axis columns; a row is one
+    // index tuple of the leading axes.
+    int nrows = 1;
+    for (int d = 0; d + 1 < D; ++d) nrows *= te[d];
+    const int tl = te[D - 1];
+    int pstride = 1;
+    for (int d = 0; d < D; ++d) pstride *= g.To[d];
+    for (int idx = threadIdx.x; idx < nchg * nrows * tl; idx += nthr) {
+        const int cr = idx / tl;           // (channel, row) pair
+        const int col = idx - cr * tl;
+        const int c = cr / nrows;
+        const int r = cr - c * nrows;
+        int rem = r, lo = col;
+        int64_t goff = 0, gstride = g.K[D - 1];
+        for (int d = D - 2; d >= 0; --d) {
+            const int l = D == 2 ? rem : rem % te[d];
+            rem = D == 2 ? 0 : rem / te[d];
+            lo += l * stride[d];
+            goff += (int64_t)(a0[d] + l) * gstride;
+            gstride *= g.K[d];
         }
+        const float2 v = acc[(size_t)c * plane + lo];
+        if (slot >= 0)
+            a.partial[((int64_t)slot * a.nch + ch0 + c) * pstride + r * tl + col] = v;
+        else
+            a.grid[(int64_t)(ch0 + c) * a.gsize + goff + a0[D - 1] + col] = v;
+    }
+}
+
+// Per-entry records of the owner lists: sorted position, the tap origin
+// relative to the owning tile (in [0, K)) and the window fraction, so that
+// the spread stages entries with one coalesced load round.
+template <int J>
+__global__ void __launch_bounds__(KBN_BLOCK)
+k_spread_records(KbnGeom g, int64_t M, const int *__restrict__ cell, const float *__restrict__ frac,
+                 const int *__restrict__ ooff, const int *__restrict__ oent, int64_t cap,
+                 int *__restrict__ rec_p, int *__restrict__ rec_l, float *__restrict__ rec_f) {
+    const int64_t e = (int64_t)blockIdx.x * KBN_BLOCK + threadIdx.x;
+    if (e >= cap || e >= ooff[g.ntiles_own]) return;
+    // owning tile: last t with ooff[t] <= e
+    int lo = 0, hi = g.ntiles_own - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ooff[mid] <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    int rem = lo;
+    int a0[KBN_MAX_D];
+    for (int d = g.D - 1; d >= 0; --d) {
+        a0[d] = (rem % g.nto[d]) * g.To[d];
+        rem /= g.nto[d];
+    }
+    const int p = oent[e];
+    rec_p[e] = p;
+    for (int d = 0; d < g.D; ++d) {
+        int start;
+        float f;
+        tap_origin(J, cell[d * M + p], frac[d * M + p], start, f);
+        int l = start - a0[d];
+        if (l < 0) l += g.K[d];
+        if (l < 0) l += g.K[d];
+        rec_l[e * g.D + d] = l;
+        rec_f[e * g.D + d] = f;
+    }
+}
+
+// Tiles split into several work items: sum their partial tiles in slot
+// order (deterministic) and write the grid tile.  Block = (channel, tile).
+template <int D>
+__global__ void __launch_bounds__(KBN_BLOCK) k_spread_combine(KbnGeom g, KbnSpreadArgs a) {
+    const int k = blockIdx.y;
+    if (k >= a.scounts[1]) return;
+    const int tile = a.scomb[3 * k], slot0 = a.scomb[3 * k + 1], ns = a.scomb[3 * k + 2];
+    const int ch = blockIdx.x;
+    int a0[KBN_MAX_D], te[KBN_MAX_D];
+    int rem = tile;
+    for (int d = D - 1; d >= 0; --d) {
+        const int tc = rem % g.nto[d];
+        rem /= g.nto[d];
+        a0[d] = tc * g.To[d];
+        te[d] = min(g.To[d], g.K[d] - a0[d]);
+    }
+    int tsize = 1, pstride = 1;
+    for (int d = 0; d < D; ++d) {
+        tsize *= te[d];
+        pstride *= g.To[d];
+    }
+    float2 *G = a.grid + (int64_t)ch * a.gsize;
+    for (int i = threadIdx.x; i < tsize; i += KBN_BLOCK) {
+        float2 sum = make_float2(0.f, 0.f);
+        for (int s = 0; s < ns; ++s) {
+            const float2 v = a.partial[((int64_t)(slot0 + s) * a.nch + ch) * pstride + i];
+            sum.x += v.x;
+            sum.y += v.y;
+        }
+        int r = i;
+        int64_t off = 0, stride = 1;
+        for (int d = D - 1; d >= 0; --d) {
+            const int l = r % te[d];
+            r /= te[d];
+            off += (int64_t)(a0[d] + l) * stride;
+            stride *= g.K[d];
+        }
+        G[off] = sum;
     }
 }
 
@@ -580,7 +656,7 @@ SpreadShape spread_shape(const KbnGeom &g, int nch) {
     const int EB = KBN_SPREAD_EB;
     auto bytes = [&](int nw) {
         const int ng = nw * sh.cw;
-        return sizeof(float2) * (size_t)ng * plane + sizeof(int) * EB * (1 + D) +
+        return sizeof(float2) * (size_t)ng * plane + sizeof(int) * EB * (1 + D * J) +
                sizeof(float) * EB * D * J + sizeof(float2) * (size_t)ng * (EB + 1);
     };
     sh.nwave = 1;
@@ -600,11 +676,13 @@ hipError_t spread_dj(const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s) {
         dim3 pgrid((unsigned)((a.M + KBN_BLOCK - 1) / KBN_BLOCK), (unsigned)a.nch);
         k_permute<<<pgrid, dim3(KBN_BLOCK), 0, s>>>(a.y, a.ys, a.order, a.M);
     }
-    dim3 grid((unsigned)ng, (unsigned)g.ntiles_own);
+    dim3 grid((unsigned)ng, (unsigned)a.nwork_max);
     if (sh.A == 1 || D == 1)
         k_spread<D, J, 1><<<grid, dim3(64 * sh.nwave), sh.lds, s>>>(g, a, sh.cw, sh.nwave);
     else
         k_spread<D, J, (D >= 2 ? 2 : 1)><<<grid, dim3(64 * sh.nwave), sh.lds, s>>>(g, a, sh.cw, sh.nwave);
+    if (a.ncomb_max > 0)
+        k_spread_combine<D><<<dim3((unsigned)a.nch, (unsigned)a.ncomb_max), dim3(KBN_BLOCK), 0, s>>>(g, a);
     return hipGetLastError();
 }
 
@@ -653,3 +731,17 @@ hipError_t kbn_launch_spread(const KbnGeom &g, const KbnSpreadArgs &a, hipStream
 }
 
 
+
+hipError_t kbn_launch_spread_records(const KbnGeom &g, int64_t M, const int *cell, const float *frac,
+                                     const int *ooff, const int *oent, int64_t cap, int *rec_p,
+                                     int *rec_l, float *rec_f, hipStream_t s) {
+    if (M == 0 || cap == 0) return hipSuccess;
+    const dim3 grid((unsigned)((cap + KBN_BLOCK - 1) / KBN_BLOCK));
+    switch (g.J) {
+#define KBN_REC(j) case j: k_spread_records<j><<<grid, dim3(KBN_BLOCK), 0, s>>>(g, M, cell, frac, ooff, oent, cap, rec_p, rec_l, rec_f); break;
+        KBN_REC(2) KBN_REC(3) KBN_REC(4) KBN_REC(5) KBN_REC(6) KBN_REC(7) KBN_REC(8)
+#undef KBN_REC
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}

@@ -15,6 +15,8 @@
 #define KBN_BLOCK 256
 #define KBN_SUB 256        // sorted points per gather subproblem (one per thread)
 #define KBN_SPREAD_EB 64   // list entries staged per spread batch
+#define KBN_SPREAD_SEG 128  // list entries per spread work item (doubled if slots run out)
+#define KBN_SPREAD_SMAX 256 // partial-tile slots for tiles split into several work items
 #define KBN_SPREAD_LDS (64 * 1024)  // LDS budget of one spread workgroup
 
 // kernel classes reported by kbn_timing_read (order of kClassNames)
@@ -72,7 +74,8 @@ hipError_t kbn_launch_owner_lists(int D, int J, int ntiles_sort, const int *K, c
                                   const int *nto, int ntiles_own, int64_t M, int chunk,
                                   int nchunks, const int *cell, const float *frac,
                                   const int *toff, int *counts, int *ooff, int *entries,
-                                  int *otile_order, hipStream_t s);
+                                  int *otile_order, int seg, int smax, int *swork, int *scomb,
+                                  int *scounts, hipStream_t s);
 
 hipError_t kbn_launch_points(int D, int64_t M, const float *omega, const double *scale,
                              const int *K, const int *T, const int *nt, int ntiles,
@@ -177,7 +180,18 @@ struct KbnSpreadArgs {
     const int *ooff;           // owner tile t's entries: oent[ooff[t] .. ooff[t+1])
     const int *oent;           // sorted sample positions, grouped by owner tile
     const int *otile_order;    // owner tiles by decreasing entry count (coarse)
+    const int *swork;          // work items [n][4]: tile, entry begin, entry end, slot (-1: direct)
+    const int *scomb;          // multi-item tiles [n][3]: tile, first slot, slots
+    const int *scounts;        // [0] work items, [1] multi-item tiles
+    float2 *partial;           // [smax][nch][prod To] partial tiles of multi-item tiles
+    const int *rec_p;          // per owner-list entry: sorted sample position
+    const int *rec_l;          // [entries][D] tap origin relative to the owning tile
+    const float *rec_f;        // [entries][D] window fraction
+    int nwork_max, ncomb_max;
 };
 
 hipError_t kbn_launch_gather(const KbnGeom &g, const KbnGatherArgs &a, int mode, hipStream_t s);
 hipError_t kbn_launch_spread(const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s);
+hipError_t kbn_launch_spread_records(const KbnGeom &g, int64_t M, const int *cell, const float *frac,
+                                     const int *ooff, const int *oent, int64_t cap, int *rec_p,
+                                     int *rec_l, float *rec_f, hipStream_t s);

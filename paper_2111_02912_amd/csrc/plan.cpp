@@ -196,6 +196,10 @@ struct kbn_plan_s {
     int64_t counts_cap = 0;
     int *subs = nullptr, *nsub = nullptr;
     int *ooff = nullptr, *oent = nullptr, *otile_order = nullptr;
+    int *swork = nullptr, *scomb = nullptr, *scounts = nullptr;
+    int *rec_p = nullptr, *rec_l = nullptr;
+    float *rec_f = nullptr;
+    int64_t swork_cap = 0;
     // grid workspace
     float2 *ws = nullptr;
     int64_t ws_bytes = 0, max_ws = 0;
@@ -281,6 +285,11 @@ void free_points(kbn_plan p) {
     dev_free(p->counts);
     dev_free(p->subs);
     dev_free(p->oent);
+    dev_free(p->swork);
+    dev_free(p->rec_p);
+    dev_free(p->rec_l);
+    dev_free(p->rec_f);
+    p->swork_cap = 0;
     p->Mcap = 0;
     p->counts_cap = 0;
 }
@@ -302,6 +311,8 @@ void free_plan(kbn_plan p) {
     dev_free(p->nsub);
     dev_free(p->ooff);
     dev_free(p->otile_order);
+    dev_free(p->scomb);
+    dev_free(p->scounts);
     dev_free(p->ws);
     delete p;
 }
@@ -431,13 +442,18 @@ int run_type1(kbn_plan p, int B, int C, const float2 *y, const float2 *smaps, fl
               hipStream_t stream) {
     const int D = p->D;
     const int64_t gsz = p->gsize();
-    const int64_t per_img = (int64_t)C * (gsz * 2 + p->M) * (int64_t)sizeof(float2);
+    int64_t tcells = 1;
+    for (int d = 0; d < D; ++d) tcells *= p->To[d];
+    // per image: two grids, k-space in tile order, partial tiles of split owner tiles
+    const int64_t per_img =
+        (int64_t)C * (gsz * 2 + p->M + KBN_SPREAD_SMAX * tcells) * (int64_t)sizeof(float2);
     int64_t bc = std::max<int64_t>(1, std::min<int64_t>(B, p->max_ws / per_img));
     int rc = ensure_ws(p, bc * per_img, stream);
     if (rc != KBN_OK) return rc;
     float2 *bufA = p->ws;
     float2 *bufB = p->ws + bc * C * gsz;
     float2 *bufY = p->ws + 2 * bc * C * gsz;
+    float2 *bufP = bufY + bc * C * p->M;
     const int64_t R0 = img_rows(p);
     const int Nl = p->N[D - 1];
     const KbnGeom geom = p->geom();
@@ -458,6 +474,15 @@ int run_type1(kbn_plan p, int B, int C, const float2 *y, const float2 *smaps, fl
         sa.ooff = p->ooff;
         sa.oent = p->oent;
         sa.otile_order = p->otile_order;
+        sa.swork = p->swork;
+        sa.scomb = p->scomb;
+        sa.scounts = p->scounts;
+        sa.partial = bufP;
+        sa.rec_p = p->rec_p;
+        sa.rec_l = p->rec_l;
+        sa.rec_f = p->rec_f;
+        sa.nwork_max = (int)p->swork_cap;
+        sa.ncomb_max = std::min<int>(p->ntiles_own, KBN_SPREAD_SMAX / 2);
         KBN_LAUNCH(KBN_CLASS_SPREAD, kbn_launch_spread(geom, sa, stream), "spread");
         float2 *cur = bufA, *nxt = bufB;
         for (int d = 0; d + 1 < D; ++d) {
@@ -573,18 +598,25 @@ int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts
         return fail(KBN_ERR_UNSUPPORTED, "too many tiles; use larger tiles");
     }
     p->ntiles = (int)ntiles;
-    // spread owner tiles: small enough that several channels' accumulators fit in LDS
+    // spread owner tiles: small enough that several channels' accumulators fit
+    // in LDS, large enough that the tile count fits the LDS histogram
     int64_t ntiles_own = 1;
-    const int defown = D == 1 ? 128 : 16;
-    for (int d = 0; d < D; ++d) {
-        const int K = p->K[d];
-        int T = std::max(defown, J);
-        if (T > K) T = K;
-        while (T > J && K % T != 0 && K % T < J) --T;
-        if (K % T != 0 && K % T < J) T = K;
-        p->To[d] = T;
-        p->nto[d] = (K + T - 1) / T;
-        ntiles_own *= p->nto[d];
+    int defown = D == 1 ? 128 : (D == 2 ? 12 : 16);
+    if (const char *e = std::getenv("KBN_OWNER_TILE")) defown = std::max(J, std::atoi(e));
+    for (;;) {
+        ntiles_own = 1;
+        for (int d = 0; d < D; ++d) {
+            const int K = p->K[d];
+            int T = std::max(defown, J);
+            if (T > K) T = K;
+            while (T > J && K % T != 0 && K % T < J) --T;
+            if (K % T != 0 && K % T < J) T = K;
+            p->To[d] = T;
+            p->nto[d] = (K + T - 1) / T;
+            ntiles_own *= p->nto[d];
+        }
+        if (ntiles_own <= KBN_MAX_TILES || defown >= KBN_MAX_K) break;
+        defown += 4;
     }
     if (ntiles_own > KBN_MAX_TILES) {
         free_plan(p);
@@ -628,6 +660,8 @@ int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts
     if (rc == KBN_OK) rc = dev_alloc(&p->nsub, 1);
     if (rc == KBN_OK) rc = dev_alloc(&p->ooff, (int64_t)p->ntiles_own + 1);
     if (rc == KBN_OK) rc = dev_alloc(&p->otile_order, (int64_t)p->ntiles_own);
+    if (rc == KBN_OK) rc = dev_alloc(&p->scomb, 3 * (int64_t)p->ntiles_own);
+    if (rc == KBN_OK) rc = dev_alloc(&p->scounts, 2);
     if (rc != KBN_OK) {
         free_plan(p);
         return rc;
@@ -664,6 +698,11 @@ int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream_) {
         if (rc == KBN_OK) rc = dev_alloc(&p->counts, counts_need);
         if (rc == KBN_OK) rc = dev_alloc(&p->subs, 2 * ((cap + KBN_SUB - 1) / KBN_SUB + nbins));
         if (rc == KBN_OK) rc = dev_alloc(&p->oent, cap << D);
+        p->swork_cap = p->ntiles_own + ((cap << D) + KBN_SPREAD_SEG - 1) / KBN_SPREAD_SEG + 1;
+        if (rc == KBN_OK) rc = dev_alloc(&p->swork, 4 * p->swork_cap);
+        if (rc == KBN_OK) rc = dev_alloc(&p->rec_p, cap << D);
+        if (rc == KBN_OK) rc = dev_alloc(&p->rec_l, (cap << D) * D);
+        if (rc == KBN_OK) rc = dev_alloc(&p->rec_f, (cap << D) * D);
         if (rc != KBN_OK) {
             free_points(p);
             p->M = -1;
@@ -690,8 +729,13 @@ int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream_) {
     KBN_LAUNCH(KBN_CLASS_INDEX,
                kbn_launch_owner_lists(p->D, p->J, p->ntiles, p->K, p->To, p->nto, p->ntiles_own, M,
                                       (int)chunk_o, (int)nchunks_o, p->cell, p->frac, p->toff,
-                                      p->counts, p->ooff, p->oent, p->otile_order, stream),
+                                      p->counts, p->ooff, p->oent, p->otile_order, KBN_SPREAD_SEG,
+                                      KBN_SPREAD_SMAX, p->swork, p->scomb, p->scounts, stream),
                "spread lists");
+    KBN_LAUNCH(KBN_CLASS_INDEX,
+               kbn_launch_spread_records(p->geom(), M, p->cell, p->frac, p->ooff, p->oent, p->Mcap << p->D,
+                                         p->rec_p, p->rec_l, p->rec_f, stream),
+               "spread records");
     p->M = M;
     return KBN_OK;
 }

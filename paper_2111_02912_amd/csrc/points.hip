@@ -347,13 +347,105 @@ k_tile_order(int ntiles, const int *__restrict__ ooff, int *__restrict__ order) 
     }
 }
 
+// Spread work items.  Tile t (taken in hottest-first order) with n entries
+// becomes ceil(n / seg) items of at most seg entries (one item if n == 0, so
+// that every tile is written).  Tiles with several items get consecutive
+// partial slots; seg doubles until the slots fit in `smax`.  Outputs:
+//   work[i] = (tile, first entry, end entry, slot or -1), nwork
+//   comb[k] = (tile, first slot, number of slots), ncomb
+__global__ void __launch_bounds__(1024)
+k_spread_work(int ntiles, int seg, int smax, const int *__restrict__ ooff,
+              const int *__restrict__ order, int *__restrict__ work, int *__restrict__ comb,
+              int *__restrict__ counts2) {
+    __shared__ int part_w[1024], part_s[1024], part_c[1024];
+    __shared__ int seg_s;
+    const int tid = threadIdx.x;
+    const int per = (ntiles + 1023) / 1024;
+    const int beg = tid * per;
+    const int end = min(beg + per, ntiles);
+    if (tid == 0) seg_s = seg;
+    __syncthreads();
+    for (int it = 0; it < 31; ++it) {  // grow seg until the slots fit
+        const int sg = seg_s;
+        int sl = 0;
+        for (int r = beg; r < end; ++r) {
+            const int t = order[r];
+            const int c = ooff[t + 1] - ooff[t];
+            const int ns = c > sg ? (c + sg - 1) / sg : 1;
+            if (ns > 1) sl += ns;
+        }
+        part_s[tid] = sl;
+        __syncthreads();
+        for (int off = 512; off > 0; off >>= 1) {
+            if (tid < off) part_s[tid] += part_s[tid + off];
+            __syncthreads();
+        }
+        const bool fits = part_s[0] <= smax;
+        __syncthreads();
+        if (fits) break;
+        if (tid == 0) seg_s = 2 * sg;
+        __syncthreads();
+    }
+    const int sg = seg_s;
+    int nw = 0, ns_tot = 0, nc = 0;
+    for (int r = beg; r < end; ++r) {
+        const int t = order[r];
+        const int c = ooff[t + 1] - ooff[t];
+        const int ns = c > sg ? (c + sg - 1) / sg : 1;
+        nw += ns;
+        if (ns > 1) {
+            ns_tot += ns;
+            nc += 1;
+        }
+    }
+    part_w[tid] = nw;
+    part_s[tid] = ns_tot;
+    part_c[tid] = nc;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // inclusive scans
+        const int a = tid >= off ? part_w[tid - off] : 0;
+        const int b = tid >= off ? part_s[tid - off] : 0;
+        const int cc = tid >= off ? part_c[tid - off] : 0;
+        __syncthreads();
+        part_w[tid] += a;
+        part_s[tid] += b;
+        part_c[tid] += cc;
+        __syncthreads();
+    }
+    int wi = part_w[tid] - nw, si = part_s[tid] - ns_tot, ci = part_c[tid] - nc;
+    for (int r = beg; r < end; ++r) {
+        const int t = order[r];
+        const int e0 = ooff[t], c = ooff[t + 1] - e0;
+        const int ns = c > sg ? (c + sg - 1) / sg : 1;
+        for (int k = 0; k < ns; ++k) {
+            int *w = work + 4 * wi++;
+            w[0] = t;
+            w[1] = e0 + k * sg;
+            w[2] = min(e0 + (k + 1) * sg, e0 + c);
+            w[3] = ns > 1 ? si + k : -1;
+        }
+        if (ns > 1) {
+            int *cb = comb + 3 * ci++;
+            cb[0] = t;
+            cb[1] = si;
+            cb[2] = ns;
+            si += ns;
+        }
+    }
+    if (tid == 1023) {
+        counts2[0] = part_w[1023];
+        counts2[1] = part_c[1023];
+    }
+}
+
 }  // namespace
 
 hipError_t kbn_launch_owner_lists(int D, int J, int ntiles_sort, const int *K, const int *To,
                                   const int *nto, int ntiles_own, int64_t M, int chunk,
                                   int nchunks, const int *cell, const float *frac,
                                   const int *toff, int *counts, int *ooff, int *entries,
-                                  int *otile_order, hipStream_t s) {
+                                  int *otile_order, int seg, int smax, int *swork, int *scomb,
+                                  int *scounts, hipStream_t s) {
     OwnerGeom o;
     o.D = D;
     o.J = J;
@@ -377,6 +469,8 @@ hipError_t kbn_launch_owner_lists(int D, int J, int ntiles_sort, const int *K, c
             o, M, chunk, nchunks, nbins, nbits, cell, frac, toff, counts, entries);
     }
     k_tile_order<<<dim3(1), dim3(1024), 0, s>>>(nbins, ooff, otile_order);
+    k_spread_work<<<dim3(1), dim3(1024), 0, s>>>(nbins, seg, smax, ooff, otile_order, swork, scomb,
+                                                 scounts);
     return hipGetLastError();
 }
 
