@@ -103,6 +103,23 @@ class KbNufft:
               "kbn_set_points")
         self.M = int(om.shape[0])
         self._omega_keep = om  # keep alive until the stream has consumed it
+        self._points_src = omega
+        self._points_key = self._omega_key(omega)
+        return self
+
+    @staticmethod
+    def _omega_key(omega: torch.Tensor):
+        return (omega.data_ptr(), omega._version, tuple(omega.shape), tuple(omega.stride()))
+
+    def ensure_points(self, omega: torch.Tensor):
+        """set_points(omega) unless this plan's points came from the same,
+        unmodified tensor (the plan keeps a reference to it, so its memory
+        cannot be recycled while the key is held)."""
+        if self.M is None or getattr(self, "_points_src", None) is None \
+                or self._points_key != self._omega_key(omega):
+            self.set_points(omega.detach())
+            self._points_src = omega
+            self._points_key = self._omega_key(omega)
         return self
 
     def forward(self, x: torch.Tensor, smaps: Optional[torch.Tensor] = None) -> torch.Tensor:
