@@ -14,7 +14,13 @@ launch stream over the timed region; the dominant kernel class is reported
 against the HBM peak using the algorithmic bytes of the model below.  The
 CPU baseline times the FP64 oracle on a bounded sample on the host.
 
+Other workloads (one JSON line each, not the default):
+  --workload batch   32 uneven 2D SENSE instances + one 128^3 kooshball, the
+                     same bundle per instance, batched (streams, one graph)
+                     against the same kernels launched per instance/coil/op.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B]
+                       [--workload step|batch]
 """
 from __future__ import annotations
 
@@ -96,6 +102,111 @@ def cpu_baseline(N, om, x, g, images=2):
     }
 
 
+def _wall_ms(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def bench_batch(args):
+    """Multi-instance bundle: per instance forward E x, omega-Jacobian with
+    upstream gradient k, adjoint E^H k (B = 1, all coils)."""
+    import numpy as np
+    import torch
+
+    from paper_2111_02912_amd import batch as KB
+    from paper_2111_02912_amd import workloads as W
+    from paper_2111_02912_amd.autotune import tune_plan
+    from paper_2111_02912_amd.nufft import KbNufft
+
+    dev = torch.device("cuda", 0)
+    insts = W.multi_instance_case()
+    items = []
+    pts = 0
+    t0 = time.perf_counter()
+    choices = {}
+    for i, inst in enumerate(insts):
+        x, smaps, k = W.instance_data(inst, 4500 + 10 * i)
+        N, C, M, D = tuple(inst["N"]), inst["coils"], inst["omega"].shape[0], len(inst["N"])
+        om = torch.from_numpy(inst["omega"]).to(dev)
+        xt = torch.from_numpy(x).to(dev)
+        kt = torch.from_numpy(k).to(dev)
+        st = torch.from_numpy(smaps).to(dev) if smaps is not None else None
+        if args.autotune:
+            plan, info = tune_plan(N, om, C, xt, st, kt)
+            c = info["choice"]
+            key = f"{c['tile'][0]}/{c['spread_tile']}"
+            choices[key] = choices.get(key, 0) + 1
+        else:
+            plan = KbNufft(N, device=dev)
+            plan.set_points(om)
+        items.append(dict(plan=plan, N=N, C=C, M=M, D=D, x=xt, k=kt, s=st,
+                          y=torch.empty((1, C, M), dtype=torch.complex64, device=dev),
+                          dom=torch.empty((M, D), dtype=torch.float32, device=dev),
+                          xa=torch.empty((1,) + N, dtype=torch.complex64, device=dev),
+                          xc=torch.empty((C,) + N, dtype=torch.complex64, device=dev)))
+        pts += C * M
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    batched, percall = [], []
+    for it in items:
+        C, s = it["C"], it["s"]
+        batched += [KB.Task(it["plan"], KB.FORWARD, 1, C, it["x"], it["y"], s),
+                    KB.Task(it["plan"], KB.JAC_OMEGA_FWD, 1, C, it["x"], it["dom"], s, g=it["k"]),
+                    KB.Task(it["plan"], KB.ADJOINT, 1, C, it["k"], it["xa"], s)]
+        for c in range(C):
+            sc = s[c:c + 1] if s is not None else None
+            percall += [KB.Task(it["plan"], KB.FORWARD, 1, 1, it["x"], it["y"][:, c:c + 1], sc),
+                        KB.Task(it["plan"], KB.JAC_OMEGA_FWD, 1, 1, it["x"], it["dom"], sc,
+                                g=it["k"][:, c:c + 1], accumulate=c > 0),
+                        KB.Task(it["plan"], KB.ADJOINT, 1, 1, it["k"][:, c:c + 1], it["xc"][c:c + 1], sc)]
+    modes = {}
+    b = KB.KbnBatch(percall, nstreams=1)
+    modes["per_call"] = _wall_ms(b.run, args.steps, args.warmup)
+    b.close()
+    b = KB.KbnBatch(batched, nstreams=1)
+    modes["per_instance_one_stream"] = _wall_ms(b.run, args.steps, args.warmup)
+    b.close()
+    b = KB.KbnBatch(batched, nstreams=args.streams)
+    modes["streams"] = _wall_ms(b.run, args.steps, args.warmup)
+    b.capture()
+    modes["graph"] = _wall_ms(b.launch, args.steps, args.warmup)
+    b.close()
+    best = min(("streams", "graph"), key=lambda m: modes[m])
+    out = {
+        "metric": "multi-instance bundle nonuniform pts/s (fwd+adj+omega-Jacobian)",
+        "value": pts / (modes[best] * 1e-3),
+        "unit": "pts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": modes[best],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{len(insts) - 1} uneven 2D SENSE instances (N_d 128..384, M 8k..80k, "
+                         "4..8 coils, radial/spiral) + one 128^3 kooshball (M = 1048576, 1 coil): "
+                         "forward + omega-Jacobian + adjoint per instance"),
+            "coil_samples_per_step": pts, "autotune": bool(args.autotune),
+            "tile_choices": choices, "streams": args.streams, "setup_s": setup_s,
+        },
+        "mode_ms": modes,
+        "best_mode": best,
+        "speedup_vs_per_call": modes["per_call"] / modes[best],
+        "speedup_vs_per_instance": modes["per_instance_one_stream"] / modes[best],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +215,10 @@ def main():
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-images", type=int, default=2)
+    ap.add_argument("--workload", choices=("step", "batch"), default="step")
+    ap.add_argument("--streams", type=int, default=4, help="batch workload: streams")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="batch workload: default tiles instead of tuned ones")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="after the run, copy this many bytes device-to-device once (a "
                          "known-size reference dispatch for hardware byte counters)")
@@ -112,6 +227,8 @@ def main():
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); "
               "the path shards by image/coil with no communication, see DESIGN.md", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        return bench_batch(args)
 
     import numpy as np
     import torch

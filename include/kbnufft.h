@@ -67,11 +67,15 @@ typedef struct kbn_plan_s *kbn_plan;
 typedef struct {
     double sigma;            /* grid oversampling factor, >= 1 (default 2.0)        */
     int J;                   /* window width in grid cells, 2..8 (default 6)        */
-    int tile[3];             /* tile edge per axis for sorting and spreading
+    int tile[3];             /* tile edge per axis for sorting the points and for
+                                the interpolation subproblems
                                 (0 = automatic: 1D 256, 2D 32, 3D 16)               */
     int64_t max_workspace;   /* byte cap for the plan's grid workspace; batches
                                 larger than fits are processed in chunks
                                 (0 = 4 GiB)                                          */
+    int spread_tile;         /* edge of the grid tiles that one spreading work
+                                group owns, >= J (0 = automatic: 1D 128, 2D 12,
+                                3D 16; grown until the tile count fits)              */
 } kbn_opts;
 
 /*
@@ -215,8 +219,88 @@ int kbn_timing(kbn_plan p, int enable);
 int kbn_timing_read(kbn_plan p, int cls, int64_t *launches, double *total_ms);
 const char *kbn_timing_name(int cls);
 
-/* Free the plan and its device buffers (synchronises the device). */
+/* Free the plan and its device buffers (synchronises the device).
+ * Errors: INVALID_ARG (null plan, or a captured batch still holds it). */
 int kbn_plan_destroy(kbn_plan p);
+
+/*
+ * Batches: many independent operator calls issued together.
+ *
+ * Not an operation of the paper; an executor for running many SENSE
+ * problems of different shapes (training on several trajectories or
+ * image sizes, serving) without per-call host overhead.  A task is one
+ * of the single-plan calls above with its arguments:
+ *
+ *   op                    a            g          out
+ *   KBN_TASK_FORWARD      x            -          y        (kbn_forward)
+ *   KBN_TASK_ADJOINT      y            -          x        (kbn_adjoint)
+ *   KBN_TASK_JAC_OMEGA_FWD x           g [B][C][M] domega  (kbn_jac_omega_fwd)
+ *   KBN_TASK_JAC_OMEGA_ADJ y           g [B][N..]  domega  (kbn_jac_omega_adj)
+ *   KBN_TASK_JAC_X_FWD    g [B][C][M]  -          E^H g    (kbn_jac_x, FORWARD)
+ *   KBN_TASK_JAC_X_ADJ    g [B][N..]   -          E g      (kbn_jac_x, ADJOINT)
+ *
+ * Tasks of one plan run in list order on one stream (they share the
+ * plan's workspace); tasks of different plans must be independent (no
+ * task may read another plan's task output) and run concurrently on the
+ * batch's own streams: each plan's chain goes to the stream with the
+ * least estimated traffic so far, largest chains first.
+ */
+#define KBN_TASK_FORWARD 0
+#define KBN_TASK_ADJOINT 1
+#define KBN_TASK_JAC_OMEGA_FWD 2
+#define KBN_TASK_JAC_OMEGA_ADJ 3
+#define KBN_TASK_JAC_X_FWD 4
+#define KBN_TASK_JAC_X_ADJ 5
+
+typedef struct {
+    kbn_plan plan;
+    int op;                  /* KBN_TASK_*                                          */
+    int B, C;                /* images and coils, as for the single call            */
+    const void *a;           /* first data argument (table above), device           */
+    const void *smaps;       /* c64 [C][N..] or NULL                                */
+    const void *g;           /* upstream gradient of the JAC_OMEGA tasks, else NULL */
+    void *out;               /* output, device                                      */
+    int accumulate;          /* JAC_OMEGA tasks: add onto out                       */
+} kbn_task;
+
+typedef struct kbn_batch_s *kbn_batch;
+
+/*
+ * Create a batch of `ntasks` tasks (host array, copied) executed on
+ * `nstreams` streams of default priority (0 = 4, at most 16).  The plans
+ * must have their points set and stay alive while the batch exists.
+ * Errors: INVALID_ARG (null/empty arguments, null plan, unknown op), HIP.
+ */
+int kbn_batch_create(kbn_batch *out, int ntasks, const kbn_task *tasks, int nstreams);
+
+/*
+ * Run every task once, asynchronously: the batch's streams wait for the
+ * work already queued on `stream`, and `stream` waits for all of them, so
+ * the results are ordered after later work on `stream`.
+ * Errors: those of the task calls (the first failing task stops the
+ * issue; already-issued tasks still run), HIP.
+ */
+int kbn_batch_run(kbn_batch b, void *stream);
+
+/*
+ * Record the batch into a HIP graph for kbn_batch_launch.  Runs the
+ * batch once first (on `stream`, as kbn_batch_run, and waits for it) so
+ * that every plan workspace has its final size, then captures the same
+ * launches.  The graph holds the task buffers' and plans' addresses: until
+ * the batch is destroyed its plans refuse kbn_set_points, workspace
+ * growth, kbn_timing and kbn_plan_destroy.  Replays read the task inputs
+ * as they are at replay time.
+ * Errors: INVALID_ARG (a plan has timing on), the task calls' errors, HIP.
+ */
+int kbn_batch_capture(kbn_batch b, void *stream);
+
+/* Replay the captured graph on `stream` (asynchronous).
+ * Errors: INVALID_ARG (not captured), HIP. */
+int kbn_batch_launch(kbn_batch b, void *stream);
+
+/* Wait for the batch's streams, free the graph and the streams, and
+ * release the plans.  Errors: INVALID_ARG (null). */
+int kbn_batch_destroy(kbn_batch b);
 
 /* Static description of an error code. */
 const char *kbn_strerror(int code);

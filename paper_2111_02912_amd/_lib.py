@@ -20,12 +20,20 @@ KBN_ERR_NONFINITE = -5
 KBN_ERR_NO_POINTS = -6
 KBN_OP_FORWARD = 0
 KBN_OP_ADJOINT = 1
+KBN_TASK_FORWARD = 0
+KBN_TASK_ADJOINT = 1
+KBN_TASK_JAC_OMEGA_FWD = 2
+KBN_TASK_JAC_OMEGA_ADJ = 3
+KBN_TASK_JAC_X_FWD = 4
+KBN_TASK_JAC_X_ADJ = 5
 
 EXPORTS = (
     "kbn_plan_create", "kbn_set_points", "kbn_forward", "kbn_adjoint",
     "kbn_jac_omega_fwd", "kbn_jac_omega_adj", "kbn_jac_x", "kbn_plan_info",
     "kbn_get_points", "kbn_check_error", "kbn_plan_destroy", "kbn_strerror",
     "kbn_last_error", "kbn_timing", "kbn_timing_read", "kbn_timing_name",
+    "kbn_batch_create", "kbn_batch_run", "kbn_batch_capture", "kbn_batch_launch",
+    "kbn_batch_destroy",
 )
 
 
@@ -35,6 +43,21 @@ class KbnOpts(ctypes.Structure):
         ("J", ctypes.c_int),
         ("tile", ctypes.c_int * 3),
         ("max_workspace", ctypes.c_int64),
+        ("spread_tile", ctypes.c_int),
+    ]
+
+
+class KbnTask(ctypes.Structure):
+    _fields_ = [
+        ("plan", ctypes.c_void_p),
+        ("op", ctypes.c_int),
+        ("B", ctypes.c_int),
+        ("C", ctypes.c_int),
+        ("a", ctypes.c_void_p),
+        ("smaps", ctypes.c_void_p),
+        ("g", ctypes.c_void_p),
+        ("out", ctypes.c_void_p),
+        ("accumulate", ctypes.c_int),
     ]
 
 
@@ -80,6 +103,11 @@ def lib():
     L.kbn_timing_read.argtypes = [vp, ci, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
     L.kbn_timing_name.argtypes = [ci]
     L.kbn_timing_name.restype = ctypes.c_char_p
+    L.kbn_batch_create.argtypes = [ctypes.POINTER(vp), ci, ctypes.POINTER(KbnTask), ci]
+    L.kbn_batch_run.argtypes = [vp, vp]
+    L.kbn_batch_capture.argtypes = [vp, vp]
+    L.kbn_batch_launch.argtypes = [vp, vp]
+    L.kbn_batch_destroy.argtypes = [vp]
     for name in EXPORTS:
         if name not in ("kbn_strerror", "kbn_last_error", "kbn_timing_name"):
             getattr(L, name).restype = ci

@@ -6,6 +6,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "kbnufft.h"
+
 #define KBN_MAX_D 3
 #define KBN_MAX_J 8
 #define KBN_NCOEF 11        // polynomial coefficients per window piece (degree 10)
@@ -195,3 +197,12 @@ hipError_t kbn_launch_spread(const KbnGeom &g, const KbnSpreadArgs &a, hipStream
 hipError_t kbn_launch_spread_records(const KbnGeom &g, int64_t M, const int *cell, const float *frac,
                                      const int *ooff, const int *oent, int64_t cap, int *rec_p,
                                      int *rec_l, float *rec_f, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Plan hooks used by the batch executor (plan.cpp)
+// ---------------------------------------------------------------------------
+bool kbn_internal_timing_on(kbn_plan p);
+void kbn_internal_graph_ref(kbn_plan p, int delta);  // captured graphs holding p
+int kbn_internal_fail(int code, const char *msg);    // sets the thread's last error
+// estimated bytes moved by one call (jac: D channels per coil; type1: adjoint type)
+double kbn_internal_cost(kbn_plan p, int B, int C, int jac, int type1);

@@ -203,6 +203,9 @@ struct kbn_plan_s {
     // grid workspace
     float2 *ws = nullptr;
     int64_t ws_bytes = 0, max_ws = 0;
+    // captured batch graphs that hold this plan's buffer addresses; while
+    // non-zero the plan refuses anything that would move or resize them
+    int graph_refs = 0;
     // per-kernel-class event timing (kbn_timing)
     struct Timed {
         int cls;
@@ -319,6 +322,8 @@ void free_plan(kbn_plan p) {
 
 int ensure_ws(kbn_plan p, int64_t bytes, hipStream_t stream) {
     if (bytes <= p->ws_bytes) return KBN_OK;
+    if (p->graph_refs > 0)
+        return fail(KBN_ERR_UNSUPPORTED, "workspace growth on a plan held by a captured batch");
     KBN_HIP(hipStreamSynchronize(stream));
     dev_free(p->ws);
     p->ws_bytes = 0;
@@ -540,6 +545,20 @@ int run_jac(kbn_plan p, int B, int C, const float2 *img, const float2 *smaps, co
 
 }  // namespace
 
+// Hooks for the batch executor (batch.cpp).
+bool kbn_internal_timing_on(kbn_plan p) { return p->timing; }
+void kbn_internal_graph_ref(kbn_plan p, int delta) { p->graph_refs += delta; }
+int kbn_internal_fail(int code, const char *msg) { return fail(code, msg); }
+double kbn_internal_cost(kbn_plan p, int B, int C, int jac, int type1) {
+    // bytes the call moves under the kernel byte model: D + 1 grid sweeps
+    // per channel (D channels per coil for an omega-Jacobian) plus the
+    // k-space and image traffic
+    const double g = (double)p->gsize() * 8.0 * (p->D + 1) * (jac && !type1 ? p->D : 1);
+    double n = 1.0;
+    for (int d = 0; d < p->D; ++d) n *= p->N[d];
+    return (double)B * C * (g + 8.0 * (double)std::max<int64_t>(p->M, 0) + 8.0 * n);
+}
+
 extern "C" {
 
 int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts) {
@@ -601,8 +620,9 @@ int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts
     // spread owner tiles: small enough that several channels' accumulators fit
     // in LDS, large enough that the tile count fits the LDS histogram
     int64_t ntiles_own = 1;
-    int defown = D == 1 ? 128 : (D == 2 ? 12 : 16);
-    if (const char *e = std::getenv("KBN_OWNER_TILE")) defown = std::max(J, std::atoi(e));
+    int defown = o.spread_tile > 0 ? std::max(J, o.spread_tile) : (D == 1 ? 128 : (D == 2 ? 12 : 16));
+    if (o.spread_tile <= 0)
+        if (const char *e = std::getenv("KBN_OWNER_TILE")) defown = std::max(J, std::atoi(e));
     for (;;) {
         ntiles_own = 1;
         for (int d = 0; d < D; ++d) {
@@ -673,6 +693,8 @@ int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts
 int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream_) {
     hipStream_t stream = (hipStream_t)stream_;
     if (!p) return fail(KBN_ERR_INVALID_ARG, "null plan");
+    if (p->graph_refs > 0)
+        return fail(KBN_ERR_UNSUPPORTED, "kbn_set_points on a plan held by a captured batch");
     if (M < 0 || M > 2147483647LL) return fail(KBN_ERR_INVALID_ARG, "M out of range");
     if (M > 0 && !omega) return fail(KBN_ERR_INVALID_ARG, "null omega");
     const int nbins = p->ntiles + 1;
@@ -826,6 +848,8 @@ int kbn_check_error(kbn_plan p, void *stream) {
 
 int kbn_plan_destroy(kbn_plan p) {
     if (!p) return fail(KBN_ERR_INVALID_ARG, "null plan");
+    if (p->graph_refs > 0)
+        return fail(KBN_ERR_INVALID_ARG, "plan is held by a captured batch; destroy the batch first");
     (void)hipDeviceSynchronize();
     free_plan(p);
     return KBN_OK;
@@ -833,6 +857,8 @@ int kbn_plan_destroy(kbn_plan p) {
 
 int kbn_timing(kbn_plan p, int enable) {
     if (!p) return fail(KBN_ERR_INVALID_ARG, "null plan");
+    if (enable && p->graph_refs > 0)
+        return fail(KBN_ERR_UNSUPPORTED, "timing on a plan held by a captured batch");
     if (enable) {
         for (auto &t : p->pending) {
             p->pool.push_back(t.e0);

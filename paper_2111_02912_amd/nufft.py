@@ -32,7 +32,7 @@ class KbNufft:
 
     def __init__(self, N: Sequence[int], sigma: float = 2.0, J: int = 6,
                  tile: Optional[Sequence[int]] = None, max_workspace: int = 0,
-                 device=None):
+                 spread_tile: int = 0, device=None):
         self.N = tuple(int(n) for n in N)
         self.D = len(self.N)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -44,6 +44,9 @@ class KbNufft:
             for d, t in enumerate(tile):
                 opts.tile[d] = int(t)
         opts.max_workspace = int(max_workspace)
+        opts.spread_tile = int(spread_tile)
+        self.opts = {"sigma": float(sigma), "J": int(J), "tile": tuple(tile) if tile else None,
+                     "spread_tile": int(spread_tile)}
         arr = (ctypes.c_int64 * self.D)(*self.N)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):

@@ -139,3 +139,46 @@ def spiral_sense_case(batch: int = 8, coils: int = 8, seed: int = 3001):
     x = complex_normal((batch,) + N, seed)
     smaps = sense_maps(coils, N)
     return N, om, x, smaps
+
+
+def multi_instance_case(n2d: int = 32, seed: int = 4001, n_range=(128, 384),
+                        m_range=(8000, 80000), coil_range=(4, 8),
+                        shape3d=(128, 128, 128), spokes3d: int = 4096, samples3d: int = 256):
+    """Uneven SENSE problems sharing one GPU.
+
+    n2d 2D instances with N_d drawn independently per axis from n_range,
+    M from m_range and the coil count from coil_range (all inclusive);
+    even-numbered instances use golden-angle radial spokes of 2 max(N)
+    samples, odd-numbered ones 16 spiral interleaves, truncated to M
+    samples.  Then one 3D kooshball instance of shape3d with one coil
+    (spokes3d x samples3d samples), unless shape3d is None.
+    Returns a list of dicts with keys N, omega, coils, kind.
+    """
+    g = rng(seed)
+    out = []
+    for i in range(n2d):
+        N = tuple(int(v) for v in g.integers(n_range[0], n_range[1] + 1, size=2))
+        M = int(g.integers(m_range[0], m_range[1] + 1))
+        C = int(g.integers(coil_range[0], coil_range[1] + 1))
+        if i % 2 == 0:
+            R = 2 * max(N)
+            om = radial_2d(-(-M // R), R)[:M]
+            kind = "radial"
+        else:
+            om = spiral_2d(16, -(-M // 16))[:M]
+            kind = "spiral"
+        out.append({"N": N, "omega": np.ascontiguousarray(om), "coils": C, "kind": kind})
+    if shape3d is not None:
+        out.append({"N": tuple(shape3d), "omega": kooshball_3d(spokes3d, samples3d), "coils": 1,
+                    "kind": "kooshball"})
+    return out
+
+
+def instance_data(inst: dict, seed: int):
+    """Image [1, *N], coil maps [C, *N] (None for one coil) and a k-space
+    array [1, C, M] (upstream gradient or data) for one instance."""
+    N, C, M = inst["N"], inst["coils"], inst["omega"].shape[0]
+    x = complex_normal((1,) + tuple(N), seed)
+    smaps = sense_maps(C, N) if C > 1 else None
+    k = complex_normal((1, C, M), seed + 1)
+    return x, smaps, k
