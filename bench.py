@@ -18,9 +18,13 @@ Other workloads (one JSON line each, not the default):
   --workload batch   32 uneven 2D SENSE instances + one 128^3 kooshball, the
                      same bundle per instance, batched (streams, one graph)
                      against the same kernels launched per instance/coil/op.
+  --workload serve   CG-SENSE requests (10 iterations, lambda 1e-3, 8 coils)
+                     arriving as a Poisson process at 50/s: 80% 2D spiral
+                     (N 192..384, M 20k..60k), 20% 96^3 kooshball; latency
+                     p50/p99 of a continuous-batching server.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B]
-                       [--workload step|batch]
+                       [--workload step|batch|serve]
 """
 from __future__ import annotations
 
@@ -207,6 +211,115 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def serve_pool(dev, n2d, n3d, coils=8, seed=5001):
+    """Resident problems: square 2D spirals and 96^3 kooshballs with
+    Gaussian-bump maps and noiseless data y = E x_true."""
+    import numpy as np
+    import torch
+
+    from paper_2111_02912_amd import workloads as W
+    from paper_2111_02912_amd.nufft import KbNufft
+    from paper_2111_02912_amd.serve import Problem
+
+    g = W.rng(seed)
+    specs = []
+    for i in range(n2d):
+        n = int(g.integers(192, 385))
+        M = int(g.integers(20000, 60001))
+        specs.append(((n, n), W.spiral_2d(16, -(-M // 16))[:M], "2d"))
+    koosh = W.kooshball_3d(4096, 256)
+    for i in range(n3d):
+        specs.append(((96, 96, 96), koosh, "3d"))
+    probs = []
+    for pid, (N, om, kind) in enumerate(specs):
+        om_t = torch.from_numpy(np.ascontiguousarray(om)).to(dev)
+        sm = torch.from_numpy(W.sense_maps(coils, N)).to(dev)
+        xt = torch.from_numpy(W.complex_normal((1,) + N, seed + 100 + pid)).to(dev)
+        plan = KbNufft(N, device=dev)
+        plan.set_points(om_t)
+        y = plan.forward(xt, sm)[0].contiguous()
+        plan.close()
+        probs.append(Problem(pid, N, coils, om.shape[0], kind, {"omega": om_t, "smaps": sm, "y": y}))
+    torch.cuda.synchronize()
+    return probs
+
+
+def bench_serve(args):
+    import numpy as np
+    import torch
+
+    from paper_2111_02912_amd.serve import (GpuExecutor, Request, Server, latency_stats,
+                                            poisson_arrivals)
+
+    dev = torch.device("cuda", 0)
+    t0 = time.perf_counter()
+    probs = serve_pool(dev, args.pool_2d, args.pool_3d)
+    p2 = [p for p in probs if p.kind == "2d"]
+    p3 = [p for p in probs if p.kind == "3d"]
+    print(f"# pool ready: {len(p2)} 2D + {len(p3)} 3D problems in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    n = args.warm_requests + args.requests
+    arr = poisson_arrivals(n, args.rate, seed=5101)
+    g = np.random.default_rng(5102)
+    reqs = []
+    for i, t in enumerate(arr):
+        pool = p3 if g.random() < args.frac_3d else p2
+        reqs.append(Request(i, float(t), pool[int(g.integers(len(pool)))], iters=args.cg_iters))
+    ex = GpuExecutor(dev, lanes=args.lanes, lam=1e-3)
+    srv = Server(ex, hbm_budget=int(args.hbm_gb * (1 << 30)), lanes=args.lanes, chunk=args.chunk,
+                 depth=2, max_active=64)
+    t1 = time.perf_counter()
+    done = srv.run(reqs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    done.sort(key=lambda r: r.rid)
+    meas = done[args.warm_requests:]
+    rel = np.array([float(r.result["rel"].item()) for r in meas])
+    st = latency_stats(meas)
+    per = {k: latency_stats([r for r in meas if r.problem.kind == k]) for k in ("2d", "3d")}
+    # unloaded latency of one request of each class
+    solo = {}
+    for k, pool in (("2d", p2), ("3d", p3)):
+        ex1 = GpuExecutor(dev, lanes=1, lam=1e-3)
+        r1 = Server(ex1, hbm_budget=int(args.hbm_gb * (1 << 30)), lanes=1).run(
+            [Request(0, 0.0, pool[0], iters=args.cg_iters)])
+        r2 = Server(ex1, hbm_budget=int(args.hbm_gb * (1 << 30)), lanes=1).run(
+            [Request(0, 0.0, pool[0], iters=args.cg_iters)])
+        solo[k] = {"N": list(pool[0].N), "M": pool[0].M, "cold_ms": r1[0].latency * 1e3,
+                   "resident_ms": r2[0].latency * 1e3}
+        ex1.close()
+    out = {
+        "metric": "served CG-SENSE recon latency p50 (p99 alongside)",
+        "value": st["p50_ms"],
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.requests,
+        "warmup": args.warm_requests,
+        "ms_per_step": st["mean_ms"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"CG-SENSE serving: Poisson {args.rate}/s, {int(100 * (1 - args.frac_3d))}% "
+                         "2D spiral N 192..384 M 20k..60k, "
+                         f"{int(100 * args.frac_3d)}% 96^3 kooshball M 1048576, 8 coils, "
+                         f"{args.cg_iters} CG iterations, lambda 1e-3"),
+            "pool": {"2d": len(p2), "3d": len(p3)}, "lanes": args.lanes, "chunk": args.chunk,
+            "hbm_budget_gb": args.hbm_gb,
+        },
+        "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "max_ms": st["max_ms"],
+        "per_class": per, "unloaded": solo,
+        "requests_per_s": len(meas) / (max(r.t_done for r in meas) - min(r.arrival for r in meas)),
+        "wall_s": wall, "plans_created": ex.plans_created, "resident_plan_hits": ex.plan_hits,
+        "peak_active": srv.peak_active, "peak_bytes_gb": srv.peak_bytes / 2 ** 30,
+        "residual_median": float(np.median(rel)), "residual_max": float(rel.max()),
+    }
+    ex.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,7 +328,17 @@ def main():
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-images", type=int, default=2)
-    ap.add_argument("--workload", choices=("step", "batch"), default="step")
+    ap.add_argument("--workload", choices=("step", "batch", "serve"), default="step")
+    ap.add_argument("--requests", type=int, default=2000, help="serve workload: measured requests")
+    ap.add_argument("--warm-requests", type=int, default=100, help="serve workload: unmeasured first requests")
+    ap.add_argument("--rate", type=float, default=50.0, help="serve workload: arrivals per second")
+    ap.add_argument("--frac-3d", type=float, default=0.2)
+    ap.add_argument("--pool-2d", type=int, default=24)
+    ap.add_argument("--pool-3d", type=int, default=4)
+    ap.add_argument("--lanes", type=int, default=4)
+    ap.add_argument("--chunk", type=int, default=1, help="serve workload: CG iterations per issue")
+    ap.add_argument("--cg-iters", type=int, default=10)
+    ap.add_argument("--hbm-gb", type=float, default=64.0)
     ap.add_argument("--streams", type=int, default=4, help="batch workload: streams")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="batch workload: default tiles instead of tuned ones")
@@ -229,6 +352,8 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     import numpy as np
     import torch

@@ -224,6 +224,37 @@ const char *kbn_timing_name(int cls);
 int kbn_plan_destroy(kbn_plan p);
 
 /*
+ * CG-SENSE reconstruction (Sec. IV-B: the quadratic reconstruction
+ * x = (E^H E + lambda T^H T)^{-1} E^H y with T = I, solved by conjugate
+ * gradients; residual ||r|| / ||b|| as in Sec. IV-A), one image, C coils.
+ *
+ * Plain CG from x0 = 0 (Shewchuk): r = b = E^H y, p = r; per iteration
+ * q = E^H E p + lambda p, alpha = r'r / p'q, x += alpha p, r -= alpha q,
+ * beta = r'r(new) / r'r(old), p = r + beta p.  Exactly `iters` iterations
+ * (no early stop); if p'q or r'r is not positive the step is zero.  Image
+ * vectors and arithmetic are FP32; inner products are summed in FP64 with
+ * a fixed reduction order, and the scalars stay on the device, so a solve
+ * needs no host synchronisation and its result does not depend on other
+ * work running on the GPU.
+ *
+ * work: a caller-owned device buffer of kbn_cg_work_bytes bytes holding
+ * the solver state between calls; its first doubles are
+ *   [0] r'r  [1] b'b  [2] p'q  [3] alpha  [4] beta
+ *   [5] ||r|| / ||b|| (0 if b = 0)  [6] iterations done
+ * kbn_cg_begin sets x = 0 and the state for y; kbn_cg_step runs `iters`
+ * more iterations (calls may be split, e.g. one iteration at a time).
+ * x: c64 [N..]; y: c64 [C][M]; smaps: c64 [C][N..] or NULL (C = 1).
+ * The same plan's points must stay set between begin and the last step.
+ * Errors: INVALID_ARG (null pointers, C < 1, iters < 0, lambda < 0 or
+ * not finite), NO_POINTS, OOM/HIP (workspace growth, launches).
+ */
+int kbn_cg_work_bytes(kbn_plan p, int C, int64_t *bytes);
+int kbn_cg_begin(kbn_plan p, int C, const void *smaps, const void *y, void *x, void *work,
+                 void *stream);
+int kbn_cg_step(kbn_plan p, int C, const void *smaps, double lambda, int iters, void *x,
+                void *work, void *stream);
+
+/*
  * Batches: many independent operator calls issued together.
  *
  * Not an operation of the paper; an executor for running many SENSE

@@ -206,3 +206,25 @@ void kbn_internal_graph_ref(kbn_plan p, int delta);  // captured graphs holding 
 int kbn_internal_fail(int code, const char *msg);    // sets the thread's last error
 // estimated bytes moved by one call (jac: D channels per coil; type1: adjoint type)
 double kbn_internal_cost(kbn_plan p, int B, int C, int jac, int type1);
+
+// ---------------------------------------------------------------------------
+// CG-SENSE vector kernels (cg.hip)
+// ---------------------------------------------------------------------------
+// scalar slots (doubles) at the start of a CG work buffer
+#define KBN_CG_RR 0
+#define KBN_CG_BB 1
+#define KBN_CG_PQ 2
+#define KBN_CG_ALPHA 3
+#define KBN_CG_BETA 4
+#define KBN_CG_REL 5
+#define KBN_CG_ITERS 6
+#define KBN_CG_NSCAL 32
+#define KBN_CG_MAXPARTS 1024
+// kernel groups of one CG step
+#define KBN_CGK_INIT 0  // x = 0, p = r, rr = bb = |r|^2
+#define KBN_CGK_Q 1     // q += lambda p, alpha = rr / <p, q>
+#define KBN_CGK_XR 2    // x += alpha p, r -= alpha q, beta, rr, rel
+#define KBN_CGK_P 3     // p = r + beta p
+int kbn_cg_nparts(int64_t n);
+hipError_t kbn_launch_cg(int kind, int64_t n, float2 *x, float2 *r, float2 *p, float2 *q, float lam,
+                         double *scal, double *part, hipStream_t s);

@@ -324,7 +324,7 @@ int ensure_ws(kbn_plan p, int64_t bytes, hipStream_t stream) {
     if (bytes <= p->ws_bytes) return KBN_OK;
     if (p->graph_refs > 0)
         return fail(KBN_ERR_UNSUPPORTED, "workspace growth on a plan held by a captured batch");
-    KBN_HIP(hipStreamSynchronize(stream));
+    if (p->ws) KBN_HIP(hipStreamSynchronize(stream));  // the old buffer may still be in use
     dev_free(p->ws);
     p->ws_bytes = 0;
     int rc = dev_alloc((char **)&p->ws, bytes);
@@ -707,7 +707,7 @@ int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream_) {
     const int64_t nchunks_o = M > 0 ? (M + chunk_o - 1) / chunk_o : 0;
     const int64_t counts_need = std::max<int64_t>(std::max(nchunks * nbins, nchunks_o * nbins_o), 1);
     if (M > p->Mcap || counts_need > p->counts_cap) {
-        KBN_HIP(hipStreamSynchronize(stream));
+        if (p->Mcap > 0 || p->counts_cap > 0) KBN_HIP(hipStreamSynchronize(stream));
         free_points(p);
         const int64_t cap = std::max<int64_t>(M, 1);
         const int D = p->D;
@@ -800,6 +800,92 @@ int kbn_jac_x(kbn_plan p, int op, int B, int C, const void *g, const void *smaps
     if (op == KBN_OP_FORWARD) return kbn_adjoint(p, B, C, g, smaps, out, stream);
     if (op == KBN_OP_ADJOINT) return kbn_forward(p, B, C, g, smaps, out, stream);
     return fail(KBN_ERR_INVALID_ARG, "unknown op");
+}
+
+// CG work buffer: scalars, block partials, r, p, q (images), E p (k-space)
+struct CgBufs {
+    double *scal, *part;
+    float2 *r, *p, *q, *ytmp;
+};
+
+static int64_t cg_align(int64_t b) { return (b + 255) / 256 * 256; }
+
+static int64_t cg_bytes(kbn_plan p, int C, CgBufs *b, void *work) {
+    int64_t npix = 1;
+    for (int d = 0; d < p->D; ++d) npix *= p->N[d];
+    const int64_t o_part = cg_align(KBN_CG_NSCAL * 8);
+    const int64_t o_r = o_part + cg_align(KBN_CG_MAXPARTS * 8);
+    const int64_t img = cg_align(npix * 8);
+    const int64_t o_y = o_r + 3 * img;
+    const int64_t total = o_y + cg_align(std::max<int64_t>(p->M, 0) * C * 8);
+    if (b) {
+        char *w = (char *)work;
+        b->scal = (double *)w;
+        b->part = (double *)(w + o_part);
+        b->r = (float2 *)(w + o_r);
+        b->p = (float2 *)(w + o_r + img);
+        b->q = (float2 *)(w + o_r + 2 * img);
+        b->ytmp = (float2 *)(w + o_y);
+    }
+    return total;
+}
+
+static int cg_launch(int kind, int64_t n, float2 *x, const CgBufs &b, float lam, hipStream_t s) {
+    return launched(kbn_launch_cg(kind, n, x, b.r, b.p, b.q, lam, b.scal, b.part, s), "cg vector kernel",
+                    s);
+}
+
+int kbn_cg_work_bytes(kbn_plan p, int C, int64_t *bytes) {
+    if (!p || !bytes) return fail(KBN_ERR_INVALID_ARG, "null argument");
+    if (p->M < 0) return fail(KBN_ERR_NO_POINTS, "kbn_set_points has not been called");
+    if (C < 1) return fail(KBN_ERR_INVALID_ARG, "C must be >= 1");
+    *bytes = cg_bytes(p, C, nullptr, nullptr);
+    return KBN_OK;
+}
+
+int kbn_cg_begin(kbn_plan p, int C, const void *smaps, const void *y, void *x, void *work,
+                 void *stream_) {
+    int rc = check_common(p, 1, C, x, smaps, y);
+    if (rc != KBN_OK) return rc;
+    if (!work) return fail(KBN_ERR_INVALID_ARG, "null work buffer");
+    hipStream_t stream = (hipStream_t)stream_;
+    CgBufs b;
+    cg_bytes(p, C, &b, work);
+    int64_t npix = 1;
+    for (int d = 0; d < p->D; ++d) npix *= p->N[d];
+    // r = b = E^H y (x0 = 0), p = r
+    rc = run_type1(p, 1, C, (const float2 *)y, (const float2 *)smaps, b.r, stream);
+    if (rc != KBN_OK) return rc;
+    return cg_launch(KBN_CGK_INIT, npix, (float2 *)x, b, 0.f, stream);
+}
+
+int kbn_cg_step(kbn_plan p, int C, const void *smaps, double lambda, int iters, void *x, void *work,
+                void *stream_) {
+    int rc = check_common(p, 1, C, x, smaps, work);
+    if (rc != KBN_OK) return rc;
+    if (!work) return fail(KBN_ERR_INVALID_ARG, "null work buffer");
+    if (iters < 0) return fail(KBN_ERR_INVALID_ARG, "iters must be >= 0");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(KBN_ERR_INVALID_ARG, "lambda must be finite and >= 0");
+    hipStream_t stream = (hipStream_t)stream_;
+    CgBufs b;
+    cg_bytes(p, C, &b, work);
+    int64_t npix = 1;
+    for (int d = 0; d < p->D; ++d) npix *= p->N[d];
+    for (int it = 0; it < iters; ++it) {
+        // q = E^H E p (+ lambda p in the vector kernel)
+        if (p->M > 0) {
+            rc = run_type2(p, 1, C, 1, 0, b.p, (const float2 *)smaps, 0, b.ytmp, nullptr, nullptr, 0,
+                           stream);
+            if (rc != KBN_OK) return rc;
+        }
+        rc = run_type1(p, 1, C, b.ytmp, (const float2 *)smaps, b.q, stream);
+        if (rc != KBN_OK) return rc;
+        rc = cg_launch(KBN_CGK_Q, npix, (float2 *)x, b, (float)lambda, stream);
+        if (rc == KBN_OK) rc = cg_launch(KBN_CGK_XR, npix, (float2 *)x, b, 0.f, stream);
+        if (rc == KBN_OK) rc = cg_launch(KBN_CGK_P, npix, (float2 *)x, b, 0.f, stream);
+        if (rc != KBN_OK) return rc;
+    }
+    return KBN_OK;
 }
 
 int kbn_plan_info(kbn_plan p, int64_t *K, int *tile, int *ntiles, double *beta, int64_t *M,
