@@ -74,8 +74,8 @@ typedef struct {
                                 larger than fits are processed in chunks
                                 (0 = 4 GiB)                                          */
     int spread_tile;         /* edge of the grid tiles that one spreading work
-                                group owns, >= J (0 = automatic: 1D 128, 2D 12,
-                                3D 16; grown until the tile count fits)              */
+                                group owns, >= J (0 = automatic: 1D 128, 2D 8,
+                                3D 8; grown until the tile count fits)               */
 } kbn_opts;
 
 /*

@@ -22,6 +22,7 @@
 #include "kbn_internal.h"
 
 #include <algorithm>
+#include <cstdlib>
 
 namespace {
 
@@ -486,6 +487,120 @@ __global__ void __launch_bounds__(KBN_BLOCK) k_spread(KbnGeom g, KbnSpreadArgs a
     }
 }
 
+// Output-stationary spread.  Workgroup = (work item of one owner tile,
+// group of CPT channels); one thread per cell of the tile (To^D threads), which
+// keeps the CPT channel sums of its cell in registers.  The work item's list
+// entries are staged in batches: per entry the tap origin relative to the
+// tile, the window weights of each axis (evaluated once per entry) and the
+// k-space values of the channel group.  Then every thread walks the batch: its
+// tap index per axis is its cell minus the entry's origin (mod K), its weight
+// the product of the axis weights (zero outside the J^D footprint), and it adds
+// weight * y into its sums.  No thread ever writes another thread's cell, so
+// there are no atomics and no read-modify-write of shared memory, and the sum
+// order (list order) is fixed.  The tile is written once at the end, to the
+// grid or to the work item's partial slot.
+template <int D, int J, int CPT>
+__global__ void __launch_bounds__(512) k_spread_os(KbnGeom g, KbnSpreadArgs a) {
+    constexpr int EB = 32;
+    __shared__ float2 s_y[EB][CPT];
+    __shared__ float s_w[EB][D][J];
+    __shared__ int s_l[EB][D];
+    __shared__ int s_p[EB];
+    const int wk = blockIdx.y;
+    if (wk >= a.scounts[0]) return;
+    const int tile = a.swork[4 * wk];
+    const int slot = a.swork[4 * wk + 3];
+    const int ch0 = blockIdx.x * CPT;
+    const int nchg = min(CPT, a.nch - ch0);
+    int a0[D], te[D], c[D];
+    {
+        int rem = tile;
+#pragma unroll
+        for (int d = D - 1; d >= 0; --d) {
+            const int tc = rem % g.nto[d];
+            rem /= g.nto[d];
+            a0[d] = tc * g.To[d];
+            te[d] = min(g.To[d], g.K[d] - a0[d]);
+        }
+        int t = threadIdx.x;
+#pragma unroll
+        for (int d = D - 1; d >= 0; --d) {
+            c[d] = t % g.To[d];
+            t /= g.To[d];
+        }
+    }
+    bool active = true;
+#pragma unroll
+    for (int d = 0; d < D; ++d) active = active && c[d] < te[d];
+    float2 acc[CPT];
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) acc[k] = make_float2(0.f, 0.f);
+    const int nthr = blockDim.x;
+    const int e0 = a.swork[4 * wk + 1], e1 = a.swork[4 * wk + 2];
+    for (int eb = e0; eb < e1; eb += EB) {
+        const int n = min(EB, e1 - eb);
+        __syncthreads();  // previous batch consumed
+        if ((int)threadIdx.x < n) {
+            const int t = threadIdx.x;
+            const int e = eb + t;
+            s_p[t] = a.rec_p[e];
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                s_l[t][d] = a.rec_l[(int64_t)e * D + d];
+                float w[J];
+                kb_weights<J>(a.rec_f[(int64_t)e * D + d], g.coef, w);
+#pragma unroll
+                for (int j = 0; j < J; ++j) s_w[t][d][j] = w[j];
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < EB * CPT; i += nthr) {
+            const int t = i % EB;
+            const int k = i / EB;
+            if (t < n && k < nchg) s_y[t][k] = a.ys[(int64_t)(ch0 + k) * a.M + s_p[t]];
+        }
+        __syncthreads();
+        for (int i = 0; i < n; ++i) {
+            bool in = active;
+            float w = 1.f;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                int j = c[d] - s_l[i][d];
+                if (j < 0) j += g.K[d];
+                in = in && j < J;
+                w *= s_w[i][d][j < J ? j : J - 1];
+            }
+            w = in ? w : 0.f;
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) {
+                const float2 y = s_y[i][k];
+                acc[k].x = fmaf(w, y.x, acc[k].x);
+                acc[k].y = fmaf(w, y.y, acc[k].y);
+            }
+        }
+    }
+    if (!active) return;
+    int pstride = 1, loc = 0, lstride = 1;
+    int64_t goff = 0, gstride = 1;
+#pragma unroll
+    for (int d = D - 1; d >= 0; --d) {
+        pstride *= g.To[d];
+        loc += c[d] * lstride;
+        lstride *= te[d];
+        goff += (int64_t)(a0[d] + c[d]) * gstride;
+        gstride *= g.K[d];
+    }
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+        if (k < nchg) {
+            if (slot >= 0)
+                a.partial[((int64_t)slot * a.nch + ch0 + k) * pstride + loc] = acc[k];
+            else
+                a.grid[(int64_t)(ch0 + k) * a.gsize + goff] = acc[k];
+        }
+    }
+}
+
 // Per-entry records of the owner lists: sorted position, the tap origin
 // relative to the owning tile (in [0, K)) and the window fraction, so that
 // the spread stages entries with one coalesced load round.
@@ -675,6 +790,30 @@ hipError_t spread_dj(const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s) {
     if (a.M > 0) {
         dim3 pgrid((unsigned)((a.M + KBN_BLOCK - 1) / KBN_BLOCK), (unsigned)a.nch);
         k_permute<<<pgrid, dim3(KBN_BLOCK), 0, s>>>(a.y, a.ys, a.order, a.M);
+    }
+    int tcells = 1;
+    for (int d = 0; d < D; ++d) tcells *= g.To[d];
+    static const bool os_on = [] {
+        const char *e = std::getenv("KBN_SPREAD_OS");
+        return !(e && e[0] == '0');
+    }();
+    if (D >= 2 && tcells <= 512 && os_on) {
+        const int want = std::min(a.nch, 32);
+        int cpt = 1;
+        while (cpt < want) cpt *= 2;
+        dim3 grid_os((unsigned)((a.nch + cpt - 1) / cpt), (unsigned)a.nwork_max);
+        dim3 blk((unsigned)tcells);
+        switch (cpt) {
+            case 1: k_spread_os<D, J, 1><<<grid_os, blk, 0, s>>>(g, a); break;
+            case 2: k_spread_os<D, J, 2><<<grid_os, blk, 0, s>>>(g, a); break;
+            case 4: k_spread_os<D, J, 4><<<grid_os, blk, 0, s>>>(g, a); break;
+            case 8: k_spread_os<D, J, 8><<<grid_os, blk, 0, s>>>(g, a); break;
+            case 16: k_spread_os<D, J, 16><<<grid_os, blk, 0, s>>>(g, a); break;
+            default: k_spread_os<D, J, 32><<<grid_os, blk, 0, s>>>(g, a); break;
+        }
+        if (a.ncomb_max > 0)
+            k_spread_combine<D><<<dim3((unsigned)a.nch, (unsigned)a.ncomb_max), dim3(KBN_BLOCK), 0, s>>>(g, a);
+        return hipGetLastError();
     }
     dim3 grid((unsigned)ng, (unsigned)a.nwork_max);
     if (sh.A == 1 || D == 1)

@@ -620,7 +620,7 @@ int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts
     // spread owner tiles: small enough that several channels' accumulators fit
     // in LDS, large enough that the tile count fits the LDS histogram
     int64_t ntiles_own = 1;
-    int defown = o.spread_tile > 0 ? std::max(J, o.spread_tile) : (D == 1 ? 128 : (D == 2 ? 12 : 16));
+    int defown = o.spread_tile > 0 ? std::max(J, o.spread_tile) : (D == 1 ? 128 : 8);
     if (o.spread_tile <= 0)
         if (const char *e = std::getenv("KBN_OWNER_TILE")) defown = std::max(J, std::atoi(e));
     for (;;) {
@@ -698,14 +698,18 @@ int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream_) {
     if (M < 0 || M > 2147483647LL) return fail(KBN_ERR_INVALID_ARG, "M out of range");
     if (M > 0 && !omega) return fail(KBN_ERR_INVALID_ARG, "null omega");
     const int nbins = p->ntiles + 1;
-    int64_t chunk = std::max<int64_t>(1024, (M * nbins + (1 << 17) - 1) >> 17);
+    // histogram chunks: about a thousand of at least 256 points, so that the
+    // counting and scattering kernels fill the GPU; the bin-major count matrix
+    // (bins x chunks) is scanned by a multi-block scan
+    int64_t chunk = std::max<int64_t>(256, (M + 1023) / 1024);
     chunk = (chunk + 63) / 64 * 64;
     const int64_t nchunks = M > 0 ? (M + chunk - 1) / chunk : 0;
     const int nbins_o = p->ntiles_own;
-    int64_t chunk_o = std::max<int64_t>(1024, (M * nbins_o + (1 << 17) - 1) >> 17);
-    chunk_o = (chunk_o + 63) / 64 * 64;
-    const int64_t nchunks_o = M > 0 ? (M + chunk_o - 1) / chunk_o : 0;
-    const int64_t counts_need = std::max<int64_t>(std::max(nchunks * nbins, nchunks_o * nbins_o), 1);
+    const int64_t chunk_o = chunk;
+    const int64_t nchunks_o = nchunks;
+    const int64_t S_max = std::max(nchunks * nbins, nchunks_o * nbins_o);
+    // counts, then the scan's span sums (one per 8192 counts, plus the total)
+    const int64_t counts_need = std::max<int64_t>(S_max + S_max / 8192 + 2, 1);
     if (M > p->Mcap || counts_need > p->counts_cap) {
         if (p->Mcap > 0 || p->counts_cap > 0) KBN_HIP(hipStreamSynchronize(stream));
         free_points(p);

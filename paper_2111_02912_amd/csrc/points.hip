@@ -80,47 +80,98 @@ k_tile_hist(int64_t M, int chunk, int nchunks, int nbins, const int *__restrict_
     for (int i = threadIdx.x; i < nbins; i += 64) counts[(int64_t)i * nchunks + ch] = hist[i];
 }
 
-// Single-workgroup exclusive scan of the bin-major count matrix (S entries,
-// in place), 4096 entries per round with coalesced loads, wave shuffles and
-// one LDS exchange per 1024-entry slab.  Also emits toff[b] = first position
-// of bin b and toff[nbins] = total count.
-__global__ void __launch_bounds__(1024)
-k_scan(int64_t S, int nchunks, int nbins, int *__restrict__ counts, int *__restrict__ toff) {
-    __shared__ int wsum[16];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wid = tid >> 6;
-    int run = 0;  // identical in every thread
-    for (int64_t base = 0; base < S; base += 4096) {
-        int v[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int64_t i = base + (int64_t)k * 1024 + tid;
-            v[k] = i < S ? counts[i] : 0;
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            int x = v[k];
-            for (int o = 1; o < 64; o <<= 1) {  // inclusive wave scan
-                const int y = __shfl_up(x, o, 64);
-                if (lane >= o) x += y;
-            }
-            if (lane == 63) wsum[wid] = x;
-            __syncthreads();
-            int wpre = 0, slab = 0;
-            for (int w = 0; w < 16; ++w) {
-                const int ws = wsum[w];
-                if (w < wid) wpre += ws;
-                slab += ws;
-            }
-            __syncthreads();
-            const int64_t i = base + (int64_t)k * 1024 + tid;
-            if (i < S) counts[i] = run + wpre + x - v[k];
-            run += slab;
-        }
+// Exclusive scan of the per-(bin, chunk) counts, in bin-major order, in
+// place: counts[b * nchunks + c] becomes the first output position of chunk c's
+// points of bin b; toff[b] = start of bin b and toff[nbins] = total count.
+// Three phases over spans of KBN_SCAN_SPAN counts: span sums, an exclusive
+// scan of the span sums (one workgroup), then each span rescanned with its
+// offset.  Integer sums, so the order of additions does not matter.
+#define KBN_SCAN_SPAN 8192
+
+__device__ __forceinline__ int block_scan_1024(int x, int *wsum, int &total) {
+    // inclusive scan over a 1024-thread block; returns the exclusive prefix
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    int inc = x;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    int wpre = 0, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+        const int ws = wsum[w];
+        if (w < wid) wpre += ws;
+        tot += ws;
     }
     __syncthreads();
-    for (int b = tid; b < nbins; b += 1024) toff[b] = S > 0 ? counts[(int64_t)b * nchunks] : 0;
-    if (tid == 0) toff[nbins] = run;
+    total = tot;
+    return wpre + inc - x;
+}
+
+__global__ void __launch_bounds__(1024)
+k_scan_sums(int64_t S, const int *__restrict__ counts, int *__restrict__ bsum) {
+    __shared__ int wsum[16];
+    const int64_t base = (int64_t)blockIdx.x * KBN_SCAN_SPAN;
+    int acc = 0;
+    for (int k = 0; k < KBN_SCAN_SPAN / 1024; ++k) {
+        const int64_t i = base + (int64_t)k * 1024 + threadIdx.x;
+        acc += i < S ? counts[i] : 0;
+    }
+    int tot;
+    (void)block_scan_1024(acc, wsum, tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// exclusive scan of nb span sums in place; bsum[nb] = total
+__global__ void __launch_bounds__(1024) k_scan_top(int nb, int *__restrict__ bsum) {
+    __shared__ int wsum[16];
+    int run = 0;
+    for (int base = 0; base < nb; base += 1024) {
+        const int i = base + (int)threadIdx.x;
+        const int v = i < nb ? bsum[i] : 0;
+        int tot;
+        const int ex = block_scan_1024(v, wsum, tot);
+        if (i < nb) bsum[i] = run + ex;
+        run += tot;
+    }
+    if (threadIdx.x == 0) bsum[nb] = run;
+}
+
+__global__ void __launch_bounds__(1024)
+k_scan_apply(int64_t S, int *__restrict__ counts, const int *__restrict__ bsum) {
+    __shared__ int wsum[16];
+    const int64_t base = (int64_t)blockIdx.x * KBN_SCAN_SPAN;
+    int run = bsum[blockIdx.x];
+    for (int k = 0; k < KBN_SCAN_SPAN / 1024; ++k) {
+        const int64_t i = base + (int64_t)k * 1024 + threadIdx.x;
+        const int v = i < S ? counts[i] : 0;
+        int tot;
+        const int ex = block_scan_1024(v, wsum, tot);
+        if (i < S) counts[i] = run + ex;
+        run += tot;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_scan_offsets(int64_t S, int nchunks, int nbins, const int *__restrict__ counts,
+               const int *__restrict__ bsum, int nb, int *__restrict__ toff) {
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b < nbins) toff[b] = S > 0 ? counts[(int64_t)b * nchunks] : 0;
+    if (b == 0) toff[nbins] = S > 0 ? bsum[nb] : 0;
+}
+
+hipError_t scan_counts(int64_t S, int nchunks, int nbins, int *counts, int *bsum, int *toff,
+                       hipStream_t s) {
+    const int nb = (int)((S + KBN_SCAN_SPAN - 1) / KBN_SCAN_SPAN);
+    if (nb > 0) {
+        k_scan_sums<<<dim3(nb), dim3(1024), 0, s>>>(S, counts, bsum);
+        k_scan_top<<<dim3(1), dim3(1024), 0, s>>>(nb, bsum);
+        k_scan_apply<<<dim3(nb), dim3(1024), 0, s>>>(S, counts, bsum);
+    }
+    k_scan_offsets<<<dim3((nbins + 256) / 256), dim3(256), 0, s>>>(S, nchunks, nbins, counts, bsum, nb,
+                                                                   toff);
+    return hipGetLastError();
 }
 
 // One wavefront per chunk: stable scatter.  Lanes with equal tile ids are
@@ -461,7 +512,7 @@ hipError_t kbn_launch_owner_lists(int D, int J, int ntiles_sort, const int *K, c
             o, M, chunk, nchunks, nbins, cell, frac, toff, counts);
     const int64_t S = (int64_t)nbins * (M > 0 ? nchunks : 0);
     // ooff[nbins] receives the total entry count
-    k_scan<<<dim3(1), dim3(1024), 0, s>>>(S, M > 0 ? nchunks : 1, nbins, counts, ooff);
+    scan_counts(S, M > 0 ? nchunks : 1, nbins, counts, counts + S, ooff, s);
     if (M > 0) {
         int nbits = 0;
         while ((1 << nbits) < nbins) ++nbits;
@@ -488,7 +539,7 @@ hipError_t kbn_launch_points(int D, int64_t M, const float *omega, const double 
                                                                           b.tile, b.counts);
     }
     const int64_t S = (int64_t)nbins * (M > 0 ? nchunks : 0);
-    k_scan<<<dim3(1), dim3(1024), 0, s>>>(S, M > 0 ? nchunks : 1, nbins, b.counts, b.toff);
+    scan_counts(S, M > 0 ? nchunks : 1, nbins, b.counts, b.counts + S, b.toff, s);
     if (M > 0) {
         int nbits = 0;
         while ((1 << nbits) < nbins) ++nbits;
