@@ -69,7 +69,8 @@ typedef struct {
     int J;                   /* window width in grid cells, 2..8 (default 6)        */
     int tile[3];             /* tile edge per axis for sorting the points and for
                                 the interpolation subproblems
-                                (0 = automatic: 1D 256, 2D 32, 3D 16)               */
+                                (0 = automatic: 1D 256, 2D 32, 3D 8, grown until
+                                the tile count fits)                                 */
     int64_t max_workspace;   /* byte cap for the plan's grid workspace; batches
                                 larger than fits are processed in chunks
                                 (0 = 4 GiB)                                          */

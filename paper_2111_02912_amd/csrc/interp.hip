@@ -499,29 +499,16 @@ __global__ void __launch_bounds__(KBN_BLOCK) k_spread(KbnGeom g, KbnSpreadArgs a
 // there are no atomics and no read-modify-write of shared memory, and the sum
 // order (list order) is fixed.  The tile is written once at the end, to the
 // grid or to the work item's partial slot.
-template <int D, int J, int CPT>
+template <int D, int J, int CPT, int EB>
 __global__ void __launch_bounds__(512) k_spread_os(KbnGeom g, KbnSpreadArgs a) {
-    constexpr int EB = 32;
     __shared__ float2 s_y[EB][CPT];
     __shared__ float s_w[EB][D][J];
     __shared__ int s_l[EB][D];
     __shared__ int s_p[EB];
-    const int wk = blockIdx.y;
-    if (wk >= a.scounts[0]) return;
-    const int tile = a.swork[4 * wk];
-    const int slot = a.swork[4 * wk + 3];
-    const int ch0 = blockIdx.x * CPT;
-    const int nchg = min(CPT, a.nch - ch0);
-    int a0[D], te[D], c[D];
+    const int nwork = a.scounts[0];
+    const int nthr = blockDim.x;
+    int c[D];
     {
-        int rem = tile;
-#pragma unroll
-        for (int d = D - 1; d >= 0; --d) {
-            const int tc = rem % g.nto[d];
-            rem /= g.nto[d];
-            a0[d] = tc * g.To[d];
-            te[d] = min(g.To[d], g.K[d] - a0[d]);
-        }
         int t = threadIdx.x;
 #pragma unroll
         for (int d = D - 1; d >= 0; --d) {
@@ -529,74 +516,100 @@ __global__ void __launch_bounds__(512) k_spread_os(KbnGeom g, KbnSpreadArgs a) {
             t /= g.To[d];
         }
     }
-    bool active = true;
+    const int ch0 = blockIdx.x * CPT;
+    const int nchg = min(CPT, a.nch - ch0);
+    // work items in dispatch order (hottest tiles first); a grid smaller
+    // than the work list strides over it
+    for (int wk = blockIdx.y; wk < nwork; wk += gridDim.y) {
+        const int tile = a.swork[4 * wk];
+        const int slot = a.swork[4 * wk + 3];
+        int a0[D], te[D];
+        {
+            int rem = tile;
 #pragma unroll
-    for (int d = 0; d < D; ++d) active = active && c[d] < te[d];
-    float2 acc[CPT];
-#pragma unroll
-    for (int k = 0; k < CPT; ++k) acc[k] = make_float2(0.f, 0.f);
-    const int nthr = blockDim.x;
-    const int e0 = a.swork[4 * wk + 1], e1 = a.swork[4 * wk + 2];
-    for (int eb = e0; eb < e1; eb += EB) {
-        const int n = min(EB, e1 - eb);
-        __syncthreads();  // previous batch consumed
-        if ((int)threadIdx.x < n) {
-            const int t = threadIdx.x;
-            const int e = eb + t;
-            s_p[t] = a.rec_p[e];
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                s_l[t][d] = a.rec_l[(int64_t)e * D + d];
-                float w[J];
-                kb_weights<J>(a.rec_f[(int64_t)e * D + d], g.coef, w);
-#pragma unroll
-                for (int j = 0; j < J; ++j) s_w[t][d][j] = w[j];
+            for (int d = D - 1; d >= 0; --d) {
+                const int tc = rem % g.nto[d];
+                rem /= g.nto[d];
+                a0[d] = tc * g.To[d];
+                te[d] = min(g.To[d], g.K[d] - a0[d]);
             }
         }
-        __syncthreads();
-        for (int i = threadIdx.x; i < EB * CPT; i += nthr) {
-            const int t = i % EB;
-            const int k = i / EB;
-            if (t < n && k < nchg) s_y[t][k] = a.ys[(int64_t)(ch0 + k) * a.M + s_p[t]];
-        }
-        __syncthreads();
-        for (int i = 0; i < n; ++i) {
-            bool in = active;
-            float w = 1.f;
+        bool active = true;
 #pragma unroll
-            for (int d = 0; d < D; ++d) {
-                int j = c[d] - s_l[i][d];
-                if (j < 0) j += g.K[d];
-                in = in && j < J;
-                w *= s_w[i][d][j < J ? j : J - 1];
+        for (int d = 0; d < D; ++d) active = active && c[d] < te[d];
+        float2 acc[CPT];
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) acc[k] = make_float2(0.f, 0.f);
+        const int e0 = a.swork[4 * wk + 1], e1 = a.swork[4 * wk + 2];
+        for (int eb = e0; eb < e1; eb += EB) {
+            const int n = min(EB, e1 - eb);
+            __syncthreads();  // previous batch (or work item) consumed
+            for (int t = threadIdx.x; t < n; t += nthr) {
+                const int e = eb + t;
+                s_p[t] = a.rec_p[e];
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    s_l[t][d] = a.rec_l[(int64_t)e * D + d];
+                    float w[J];
+                    kb_weights<J>(a.rec_f[(int64_t)e * D + d], g.coef, w);
+#pragma unroll
+                    for (int j = 0; j < J; ++j) s_w[t][d][j] = w[j];
+                }
             }
-            w = in ? w : 0.f;
+            __syncthreads();
+            for (int i = threadIdx.x; i < EB * CPT; i += nthr) {
+                const int t = i % EB;
+                const int k = i / EB;
+                if (t < n && k < nchg) s_y[t][k] = a.ys[(int64_t)(ch0 + k) * a.M + s_p[t]];
+            }
+            __syncthreads();
+            for (int i = 0; i < n; ++i) {
+                if (D == 3) {
+                    // with 8 x 8 cells per x-slice a wave holds one slice, so
+                    // this skip is taken by whole waves when the footprint
+                    // misses the slice
+                    int j = c[0] - s_l[i][0];
+                    if (j < 0) j += g.K[0];
+                    if (j >= J) continue;
+                }
+                bool in = active;
+                float w = 1.f;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    int j = c[d] - s_l[i][d];
+                    if (j < 0) j += g.K[d];
+                    in = in && j < J;
+                    w *= s_w[i][d][j < J ? j : J - 1];
+                }
+                w = in ? w : 0.f;
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) {
+                    const float2 y = s_y[i][k];
+                    acc[k].x = fmaf(w, y.x, acc[k].x);
+                    acc[k].y = fmaf(w, y.y, acc[k].y);
+                }
+            }
+        }
+        if (active) {
+            int pstride = 1, loc = 0, lstride = 1;
+            int64_t goff = 0, gstride = 1;
+#pragma unroll
+            for (int d = D - 1; d >= 0; --d) {
+                pstride *= g.To[d];
+                loc += c[d] * lstride;
+                lstride *= te[d];
+                goff += (int64_t)(a0[d] + c[d]) * gstride;
+                gstride *= g.K[d];
+            }
 #pragma unroll
             for (int k = 0; k < CPT; ++k) {
-                const float2 y = s_y[i][k];
-                acc[k].x = fmaf(w, y.x, acc[k].x);
-                acc[k].y = fmaf(w, y.y, acc[k].y);
+                if (k < nchg) {
+                    if (slot >= 0)
+                        a.partial[((int64_t)slot * a.nch + ch0 + k) * pstride + loc] = acc[k];
+                    else
+                        a.grid[(int64_t)(ch0 + k) * a.gsize + goff] = acc[k];
+                }
             }
-        }
-    }
-    if (!active) return;
-    int pstride = 1, loc = 0, lstride = 1;
-    int64_t goff = 0, gstride = 1;
-#pragma unroll
-    for (int d = D - 1; d >= 0; --d) {
-        pstride *= g.To[d];
-        loc += c[d] * lstride;
-        lstride *= te[d];
-        goff += (int64_t)(a0[d] + c[d]) * gstride;
-        gstride *= g.K[d];
-    }
-#pragma unroll
-    for (int k = 0; k < CPT; ++k) {
-        if (k < nchg) {
-            if (slot >= 0)
-                a.partial[((int64_t)slot * a.nch + ch0 + k) * pstride + loc] = acc[k];
-            else
-                a.grid[(int64_t)(ch0 + k) * a.gsize + goff] = acc[k];
         }
     }
 }
@@ -642,40 +655,41 @@ k_spread_records(KbnGeom g, int64_t M, const int *__restrict__ cell, const float
 // order (deterministic) and write the grid tile.  Block = (channel, tile).
 template <int D>
 __global__ void __launch_bounds__(KBN_BLOCK) k_spread_combine(KbnGeom g, KbnSpreadArgs a) {
-    const int k = blockIdx.y;
-    if (k >= a.scounts[1]) return;
-    const int tile = a.scomb[3 * k], slot0 = a.scomb[3 * k + 1], ns = a.scomb[3 * k + 2];
+    const int ncomb = a.scounts[1];
     const int ch = blockIdx.x;
-    int a0[KBN_MAX_D], te[KBN_MAX_D];
-    int rem = tile;
-    for (int d = D - 1; d >= 0; --d) {
-        const int tc = rem % g.nto[d];
-        rem /= g.nto[d];
-        a0[d] = tc * g.To[d];
-        te[d] = min(g.To[d], g.K[d] - a0[d]);
-    }
-    int tsize = 1, pstride = 1;
-    for (int d = 0; d < D; ++d) {
-        tsize *= te[d];
-        pstride *= g.To[d];
-    }
     float2 *G = a.grid + (int64_t)ch * a.gsize;
-    for (int i = threadIdx.x; i < tsize; i += KBN_BLOCK) {
-        float2 sum = make_float2(0.f, 0.f);
-        for (int s = 0; s < ns; ++s) {
-            const float2 v = a.partial[((int64_t)(slot0 + s) * a.nch + ch) * pstride + i];
-            sum.x += v.x;
-            sum.y += v.y;
-        }
-        int r = i;
-        int64_t off = 0, stride = 1;
+    for (int k = blockIdx.y; k < ncomb; k += gridDim.y) {
+        const int tile = a.scomb[3 * k], slot0 = a.scomb[3 * k + 1], ns = a.scomb[3 * k + 2];
+        int a0[KBN_MAX_D], te[KBN_MAX_D];
+        int rem = tile;
         for (int d = D - 1; d >= 0; --d) {
-            const int l = r % te[d];
-            r /= te[d];
-            off += (int64_t)(a0[d] + l) * stride;
-            stride *= g.K[d];
+            const int tc = rem % g.nto[d];
+            rem /= g.nto[d];
+            a0[d] = tc * g.To[d];
+            te[d] = min(g.To[d], g.K[d] - a0[d]);
         }
-        G[off] = sum;
+        int tsize = 1, pstride = 1;
+        for (int d = 0; d < D; ++d) {
+            tsize *= te[d];
+            pstride *= g.To[d];
+        }
+        for (int i = threadIdx.x; i < tsize; i += blockDim.x) {
+            float2 sum = make_float2(0.f, 0.f);
+            for (int s = 0; s < ns; ++s) {
+                const float2 v = a.partial[((int64_t)(slot0 + s) * a.nch + ch) * pstride + i];
+                sum.x += v.x;
+                sum.y += v.y;
+            }
+            int r = i;
+            int64_t off = 0, stride = 1;
+            for (int d = D - 1; d >= 0; --d) {
+                const int l = r % te[d];
+                r /= te[d];
+                off += (int64_t)(a0[d] + l) * stride;
+                stride *= g.K[d];
+            }
+            G[off] = sum;
+        }
     }
 }
 
@@ -801,18 +815,33 @@ hipError_t spread_dj(const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s) {
         const int want = std::min(a.nch, 32);
         int cpt = 1;
         while (cpt < want) cpt *= 2;
-        dim3 grid_os((unsigned)((a.nch + cpt - 1) / cpt), (unsigned)a.nwork_max);
+        const int ngr = (a.nch + cpt - 1) / cpt;
+        dim3 grid_os((unsigned)ngr, (unsigned)a.nwork_max);
         dim3 blk((unsigned)tcells);
-        switch (cpt) {
-            case 1: k_spread_os<D, J, 1><<<grid_os, blk, 0, s>>>(g, a); break;
-            case 2: k_spread_os<D, J, 2><<<grid_os, blk, 0, s>>>(g, a); break;
-            case 4: k_spread_os<D, J, 4><<<grid_os, blk, 0, s>>>(g, a); break;
-            case 8: k_spread_os<D, J, 8><<<grid_os, blk, 0, s>>>(g, a); break;
-            case 16: k_spread_os<D, J, 16><<<grid_os, blk, 0, s>>>(g, a); break;
-            default: k_spread_os<D, J, 32><<<grid_os, blk, 0, s>>>(g, a); break;
+        if (D == 3) {
+            switch (cpt) {
+                case 1: k_spread_os<D, J, 1, 64><<<grid_os, blk, 0, s>>>(g, a); break;
+                case 2: k_spread_os<D, J, 2, 64><<<grid_os, blk, 0, s>>>(g, a); break;
+                case 4: k_spread_os<D, J, 4, 64><<<grid_os, blk, 0, s>>>(g, a); break;
+                case 8: k_spread_os<D, J, 8, 64><<<grid_os, blk, 0, s>>>(g, a); break;
+                case 16: k_spread_os<D, J, 16, 64><<<grid_os, blk, 0, s>>>(g, a); break;
+                default: k_spread_os<D, J, 32, 32><<<grid_os, blk, 0, s>>>(g, a); break;
+            }
+        } else {
+            switch (cpt) {
+                case 1: k_spread_os<D, J, 1, 32><<<grid_os, blk, 0, s>>>(g, a); break;
+                case 2: k_spread_os<D, J, 2, 32><<<grid_os, blk, 0, s>>>(g, a); break;
+                case 4: k_spread_os<D, J, 4, 32><<<grid_os, blk, 0, s>>>(g, a); break;
+                case 8: k_spread_os<D, J, 8, 32><<<grid_os, blk, 0, s>>>(g, a); break;
+                case 16: k_spread_os<D, J, 16, 32><<<grid_os, blk, 0, s>>>(g, a); break;
+                default: k_spread_os<D, J, 32, 32><<<grid_os, blk, 0, s>>>(g, a); break;
+            }
         }
-        if (a.ncomb_max > 0)
-            k_spread_combine<D><<<dim3((unsigned)a.nch, (unsigned)a.ncomb_max), dim3(KBN_BLOCK), 0, s>>>(g, a);
+        if (a.ncomb_max > 0) {
+            const int cb = std::min(KBN_BLOCK, (tcells + 63) / 64 * 64);
+            const int ny = std::max(1, std::min(a.ncomb_max, 8 * 256 * 4 / a.nch + 1));
+            k_spread_combine<D><<<dim3((unsigned)a.nch, (unsigned)ny), dim3(cb), 0, s>>>(g, a);
+        }
         return hipGetLastError();
     }
     dim3 grid((unsigned)ng, (unsigned)a.nwork_max);
