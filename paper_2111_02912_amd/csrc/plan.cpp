@@ -545,6 +545,22 @@ int run_jac(kbn_plan p, int B, int C, const float2 *img, const float2 *smaps, co
     return run_type2(p, B, C, p->D, 1, img, smaps, 1, nullptr, v, dom, accumulate, stream);
 }
 
+// Tile edge nearest to `want` (searching down and up, at least J) whose last
+// partial tile is empty or at least J cells wide, so that a J-tap footprint
+// meets at most two tiles per axis; the whole axis if none exists.
+int pick_tile(int K, int want, int J) {
+    want = std::max(J, std::min(want, K));
+    for (int dlt = 0; dlt <= K; ++dlt) {
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+            const int T = want + sgn * dlt;
+            if (T < J || T > K) continue;
+            if (K % T == 0 || K % T >= J) return T;
+            if (dlt == 0) break;
+        }
+    }
+    return K;
+}
+
 }  // namespace
 
 // Hooks for the batch executor (batch.cpp).
@@ -613,11 +629,7 @@ int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts
         ntiles = 1;
         for (int d = 0; d < D; ++d) {
             const int K = p->K[d];
-            int T = o.tile[d] > 0 ? o.tile[d] : dt;
-            if (T < J) T = J;
-            if (T > K) T = K;
-            while (T > J && K % T != 0 && K % T < J) --T;
-            if (K % T != 0 && K % T < J) T = K;
+            const int T = pick_tile(K, o.tile[d] > 0 ? o.tile[d] : dt, J);
             p->T[d] = T;
             p->nt[d] = (K + T - 1) / T;
             ntiles *= p->nt[d];
@@ -639,10 +651,7 @@ int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts
         ntiles_own = 1;
         for (int d = 0; d < D; ++d) {
             const int K = p->K[d];
-            int T = std::max(defown, J);
-            if (T > K) T = K;
-            while (T > J && K % T != 0 && K % T < J) --T;
-            if (K % T != 0 && K % T < J) T = K;
+            const int T = pick_tile(K, defown, J);
             p->To[d] = T;
             p->nto[d] = (K + T - 1) / T;
             ntiles_own *= p->nto[d];

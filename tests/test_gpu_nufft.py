@@ -267,3 +267,24 @@ def test_specialised_fft_matches_generic(N, dev, monkeypatch):
     ref = nufft_ref.Params(N, 2.0, 6)
     assert ndft.rel_l2(outs[0][0][:, 0], nufft_ref.forward(ref, om, x)) < TOL_STEPS
     assert ndft.rel_l2(outs[0][1], nufft_ref.adjoint(ref, om, g[:, 0])) < TOL_STEPS
+
+
+def test_grid_sizes_without_a_near_tile_divisor(dev):
+    """N = 302 x 362 gives K = 625 x 729 (powers of 5 and 3): no tile edge
+    near the preferred one divides K or leaves a last tile of at least J
+    cells below it, so the tile search must also look upward."""
+    N = (302, 362)
+    _say(f"awkward grid N={N}")
+    om = W.uniform_random(3000, 2, seed=9101)
+    x = W.complex_normal((1,) + N, 9102)
+    smaps = W.sense_maps(2, N).astype(np.complex64)
+    p = _plan(N, dev)
+    assert p.K == (625, 729)
+    p.set_points(_f(om, dev))
+    y = p.forward(_c(x, dev), _c(smaps, dev))
+    g = W.complex_normal((1, 2, om.shape[0]), 9103)
+    xa = p.adjoint(_c(g, dev), _c(smaps, dev))
+    e_f = ndft.rel_l2(_np(y), ndft.sense_forward(om, x, N, smaps))
+    e_a = ndft.rel_l2(_np(xa), ndft.sense_adjoint(om, g, N, smaps))
+    _say(f"  fwd {e_f:.2e} adj {e_a:.2e}")
+    assert e_f < TOL_NUFFT and e_a < TOL_NUFFT
