@@ -42,6 +42,25 @@ if ROOT not in sys.path:
 METRIC = "nonuniform pts/s (fwd+adj+ω-Jacobian), % HBM peak; served recon p50/p99 ms"
 HBM_PEAK_GBPS = 8000.0
 C8 = 8  # bytes per complex64
+# hardware-counter traffic of this workload's kernels (rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, calibrated against a device copy of known size); used only while
+# its source hash matches the kernels being run
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_2d256_M32768_B256.json")
+
+
+def measured_traffic(cls: str, launches_per_step: float):
+    """HBM bytes per launch of kernel class `cls` from the counter summary,
+    or None when there is none or the kernels changed since it was taken."""
+    from paper_2111_02912_amd.profsummary import sources_hash
+    try:
+        with open(PMC_SUMMARY) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    c = d.get("classes", {}).get(cls)
+    if d.get("sources") != sources_hash() or c is None or launches_per_step <= 0:
+        return None
+    return (c["fetch_per_step"] + c["write_per_step"]) / launches_per_step
 
 
 def algorithmic_bytes(N, K, M, B, D):
@@ -409,7 +428,8 @@ def main():
     per_launch_bytes = alg[dom_name] * args.steps / dk["launches"]
     achieved = per_launch_bytes / (dk["avg_ms"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                "traffic": measured_traffic(dom_name, dk["launches"] / args.steps),
                 "alg_bytes_per_launch": per_launch_bytes, "avg_launch_ms": dk["avg_ms"]}
     total_alg = sum(alg.values())
 

@@ -23,15 +23,32 @@ import sys
 
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
-# kernel symbol fragment -> timing class of the library
+# kernel symbol fragment -> timing class of the library (first match wins,
+# so the index-pass kernels named k_spread_* come before the spread itself)
 CLASSES = [
-    ("k_first_pass", "fft_first"),
+    ("k_spread_records", "index"), ("k_spread_work", "index"), ("k_points_cells", "index"),
+    ("k_tile_hist", "index"), ("k_tile_scatter", "index"), ("k_scan", "index"),
+    ("k_subproblems", "index"), ("k_owner_", "index"), ("k_tile_order", "index"),
+    ("k_first_pass", "fft_first"), ("k_rows_first", "fft_first"),
     ("k_mid_pass<16, false>", "fft_mid_fwd"), ("k_mid_pass<32, false>", "fft_mid_fwd"),
     ("k_mid_pass<16, true>", "fft_mid_inv"), ("k_mid_pass<32, true>", "fft_mid_inv"),
-    ("k_last_adj", "fft_last_adj"),
-    ("k_gather_staged<2, 6, 0>", "gather"), ("k_gather_staged<2, 6, 1>", "gather_jac"),
+    ("false>", "fft_mid_fwd"), ("true>", "fft_mid_inv"),  # k_cols<L, E, INV>
+    ("k_last_adj", "fft_last_adj"), ("k_rows_last_adj", "fft_last_adj"),
+    ("k_gather_staged<2, 6, 0>", "gather"), ("k_gather_staged<3, 6, 0>", "gather"),
+    ("k_gather<", "gather"),
+    ("k_gather_staged<2, 6, 1>", "gather_jac"), ("k_gather_staged<3, 6, 1>", "gather_jac"),
+    ("k_reduce_parts", "gather_jac"),
     ("k_spread", "spread"), ("k_permute", "spread"),
 ]
+
+
+def kernel_class(name: str):
+    for frag, cls in CLASSES:
+        if frag in name:
+            if frag in ("false>", "true>") and "k_cols" not in name:
+                continue
+            return cls
+    return None
 
 
 def sources_hash() -> str:
@@ -69,7 +86,7 @@ def _per_kernel(path):
     return agg
 
 
-def pmc(fetch_csv, write_csv, calib_bytes, cmd_f, cmd_w, json_out=None) -> str:
+def pmc(fetch_csv, write_csv, calib_bytes, cmd_f, cmd_w, json_out=None, steps=1) -> str:
     fa = _per_kernel(fetch_csv)
     wa = _per_kernel(write_csv)
 
@@ -96,14 +113,19 @@ def pmc(fetch_csv, write_csv, calib_bytes, cmd_f, cmd_w, json_out=None) -> str:
         f = sum(fa.get(name, [0])) / max(len(fa.get(name, [])), 1) * 1024.0 * sf
         w = sum(wa.get(name, [0])) / max(len(wa.get(name, [])), 1) * 1024.0 * sw
         out.append(f"{short(name)[:58]:58s} {len(fa.get(name, [])):4d} {f / 1e6:10.2f} {w / 1e6:10.2f}")
-        for frag, cls in CLASSES:
-            if frag in name:
-                c = classes.setdefault(cls, {"fetch": 0.0, "write": 0.0})
-                c["fetch"] += f
-                c["write"] += w
+        cls = kernel_class(name)
+        if cls is not None:
+            # totals over all dispatches of the run, divided per step below
+            c = classes.setdefault(cls, {"fetch_per_step": 0.0, "write_per_step": 0.0})
+            c["fetch_per_step"] += sum(fa.get(name, [])) * 1024.0 * sf / steps
+            c["write_per_step"] += sum(wa.get(name, [])) * 1024.0 * sw / steps
+    out.append("")
+    out.append(f"per step ({steps} steps in the run), by kernel class:")
+    for cls, c in sorted(classes.items()):
+        out.append(f"  {cls:14s} fetch {c['fetch_per_step'] / 1e6:10.2f} MB  write {c['write_per_step'] / 1e6:10.2f} MB")
     if json_out:
         with open(json_out, "w") as fh:
-            json.dump({"sources": sources_hash(), "calib_bytes": calib_bytes,
+            json.dump({"sources": sources_hash(), "calib_bytes": calib_bytes, "steps": steps,
                        "classes": classes}, fh, indent=1)
     return "\n".join(out) + "\n"
 
@@ -121,11 +143,13 @@ def main():
     p.add_argument("--cmd-fetch", required=True)
     p.add_argument("--cmd-write", required=True)
     p.add_argument("--json")
+    p.add_argument("--steps", type=int, default=1, help="steps (incl. warm-up) in the counted run")
     a = ap.parse_args()
     if a.mode == "stats":
         sys.stdout.write(stats(a.csv, a.cmd))
     else:
-        sys.stdout.write(pmc(a.fetch_csv, a.write_csv, a.calib_bytes, a.cmd_fetch, a.cmd_write, a.json))
+        sys.stdout.write(pmc(a.fetch_csv, a.write_csv, a.calib_bytes, a.cmd_fetch, a.cmd_write, a.json,
+                             a.steps))
 
 
 if __name__ == "__main__":
