@@ -433,6 +433,22 @@ def main():
                 "alg_bytes_per_launch": per_launch_bytes, "avg_launch_ms": dk["avg_ms"]}
     total_alg = sum(alg.values())
 
+    # achievable HBM bandwidth: a 1 GiB device-to-device copy (read + write),
+    # larger than the 256 MB Infinity Cache, best of 5
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    copy_ms = []
+    for _ in range(6):
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        copy_ms.append(e0.elapsed_time(e1))
+    copy_gbps = 2 * src.numel() * 8 / (min(copy_ms[1:]) * 1e-3) / 1e9
+    del src, dst
+    roofline["achievable_copy_GBps"] = copy_gbps
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(N, om, x, g, images=min(args.cpu_images, B))
