@@ -512,7 +512,8 @@ hipError_t kbn_launch_owner_lists(int D, int J, int ntiles_sort, const int *K, c
             o, M, chunk, nchunks, nbins, cell, frac, toff, counts);
     const int64_t S = (int64_t)nbins * (M > 0 ? nchunks : 0);
     // ooff[nbins] receives the total entry count
-    scan_counts(S, M > 0 ? nchunks : 1, nbins, counts, counts + S, ooff, s);
+    const hipError_t es = scan_counts(S, M > 0 ? nchunks : 1, nbins, counts, counts + S, ooff, s);
+    if (es != hipSuccess) return es;
     if (M > 0) {
         int nbits = 0;
         while ((1 << nbits) < nbins) ++nbits;
@@ -539,7 +540,8 @@ hipError_t kbn_launch_points(int D, int64_t M, const float *omega, const double 
                                                                           b.tile, b.counts);
     }
     const int64_t S = (int64_t)nbins * (M > 0 ? nchunks : 0);
-    scan_counts(S, M > 0 ? nchunks : 1, nbins, b.counts, b.counts + S, b.toff, s);
+    const hipError_t es = scan_counts(S, M > 0 ? nchunks : 1, nbins, b.counts, b.counts + S, b.toff, s);
+    if (es != hipSuccess) return es;
     if (M > 0) {
         int nbits = 0;
         while ((1 << nbits) < nbins) ++nbits;

@@ -245,7 +245,7 @@ def test_throughput_shape_sampled(dev):
     assert ndft.rel_l2(dom[rows], exact_j) < TOL_JAC
 
 
-@pytest.mark.parametrize("N", [(64, 96), (160, 128), (48, 40, 64)])
+@pytest.mark.parametrize("N", [(64, 96), (160, 128), (48, 40, 64), (256, 130)])
 def test_specialised_fft_matches_generic(N, dev, monkeypatch):
     """The compile-time specialised FFT passes and the generic ones agree, and
     both match the oracle (K = 128, 192, 320->generic, 256, 96->generic...)."""
