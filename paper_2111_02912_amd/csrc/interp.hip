@@ -15,52 +15,17 @@
 // Im{z conj(v_{b,c,m})} and summed over the channels in registers.
 //
 // spread (type 1, adjoint operator): each workgroup owns one tile of the
-// grid for a group of channels, accumulates every sample whose taps reach
-// the tile into an LDS copy of the tile (LDS float atomics), then writes the
-// tile with plain stores: every grid cell is written exactly once, so the
-// grid needs neither zero-initialisation nor global atomics.
+// grid for a group of channels and sums every sample whose taps reach the
+// tile (see k_spread_os), then writes the tile with plain stores: every grid
+// cell is written exactly once, so the grid needs neither zero-initialisation
+// nor atomics.
 #include "kbn_internal.h"
+#include "kbn_window.h"
 
 #include <algorithm>
 #include <cstdlib>
 
 namespace {
-
-__device__ __forceinline__ void tap_origin(int J, int cell, float frac, int &start, float &f) {
-    if ((J & 1) == 0) {
-        start = cell - J / 2 + 1;
-        f = frac;
-    } else if (frac >= 0.5f) {
-        start = cell - J / 2 + 1;
-        f = frac - 0.5f;
-    } else {
-        start = cell - J / 2;
-        f = frac + 0.5f;
-    }
-}
-
-template <int J>
-__device__ __forceinline__ void kb_weights(float f, const float *__restrict__ coef, float *w) {
-    const float x = 2.f * f - 1.f;
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        float acc = coef[j * KBN_NCOEF + KBN_NCOEF - 1];
-#pragma unroll
-        for (int k = KBN_NCOEF - 2; k >= 0; --k) acc = fmaf(acc, x, coef[j * KBN_NCOEF + k]);
-        w[j] = acc;
-    }
-}
-
-__device__ __forceinline__ int wrapk(int i, int K) {  // i in [-K, 2K)
-    return i < 0 ? i + K : (i >= K ? i - K : i);
-}
-
-// Tap reach of a point in cell c: taps lie in [c - LO, c + HI].
-template <int J>
-struct Reach {
-    static constexpr int LO = (J & 1) ? J / 2 : J / 2 - 1;
-    static constexpr int HI = (J & 1) ? J / 2 + 1 : J / 2;
-};
 
 // Staged gather: one workgroup per subproblem (<= KBN_SUB sorted points of
 // one tile).  For each channel the tile's grid region (tile plus the tap

@@ -81,7 +81,7 @@ hipError_t kbn_launch_owner_lists(int D, int J, int ntiles_sort, const int *K, c
 
 hipError_t kbn_launch_points(int D, int64_t M, const float *omega, const double *scale,
                              const int *K, const int *T, const int *nt, int ntiles,
-                             int chunk, int nchunks, const KbnPointsBufs &b, hipStream_t s);
+                             int chunk, int nchunks, int sub, const KbnPointsBufs &b, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // FFT passes (fft.hip)

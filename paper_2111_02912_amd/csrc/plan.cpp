@@ -208,6 +208,7 @@ struct kbn_plan_s {
     int graph_refs = 0;
     // partial-tile slots for owner tiles split into several spread work items
     int smax = KBN_SPREAD_SMAX;
+    int sub = KBN_SUB;  // samples per gather subproblem
     // per-kernel-class event timing (kbn_timing)
     struct Timed {
         int cls;
@@ -363,8 +364,12 @@ int run_type2(kbn_plan p, int B, int C, int nw, int weighted, const float2 *x,
     int64_t bc = std::max<int64_t>(1, std::min<int64_t>(B, p->max_ws / per_img));
     const KbnGeom geom0 = p->geom();
     // per-group partial omega-gradients (mode 1), sized for the largest chunk
-    const KbnGatherShape sh = kbn_gather_shape(geom0, p->M, (int)(bc * C * nw), nw);
-    const int64_t part_bytes = mode == 1 ? (int64_t)sh.groups * p->M * D * (int64_t)sizeof(float) : 0;
+    // channel groups of any chunk are at most min(images x coils of the
+    // largest chunk, ceil(2048 / blocks)) (a smaller last chunk can have
+    // more groups than the largest one)
+    const int64_t blocks0 = kbn_gather_shape(geom0, p->M, (int)(bc * C * nw), nw).blocks;
+    const int64_t groups_max = std::max<int64_t>(1, std::min<int64_t>(bc * C, (2048 + blocks0 - 1) / blocks0));
+    const int64_t part_bytes = mode == 1 ? (int64_t)groups_max * p->M * D * (int64_t)sizeof(float) : 0;
     int rc = ensure_ws(p, bc * per_img + part_bytes, stream);
     if (rc != KBN_OK) return rc;
     float2 *bufA = p->ws;
@@ -775,7 +780,7 @@ int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream_) {
     b.subs = p->subs;
     b.nsub = p->nsub;
     KBN_LAUNCH(KBN_CLASS_INDEX, kbn_launch_points(p->D, M, omega, p->scale, p->K, p->T, p->nt, p->ntiles,
-                                 (int)chunk, (int)nchunks, b, stream),
+                                 (int)chunk, (int)nchunks, p->sub, b, stream),
                "index pass");
     KBN_LAUNCH(KBN_CLASS_INDEX,
                kbn_launch_owner_lists(p->D, p->J, p->ntiles, p->K, p->To, p->nto, p->ntiles_own, M,

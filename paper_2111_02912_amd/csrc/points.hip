@@ -528,7 +528,7 @@ hipError_t kbn_launch_owner_lists(int D, int J, int ntiles_sort, const int *K, c
 
 hipError_t kbn_launch_points(int D, int64_t M, const float *omega, const double *scale,
                              const int *K, const int *T, const int *nt, int ntiles,
-                             int chunk, int nchunks, const KbnPointsBufs &b, hipStream_t s) {
+                             int chunk, int nchunks, int sub, const KbnPointsBufs &b, hipStream_t s) {
     const int nbins = ntiles + 1;
     if (M > 0) {
         const int64_t blocks = (M + KBN_BLOCK - 1) / KBN_BLOCK;
@@ -549,6 +549,6 @@ hipError_t kbn_launch_points(int D, int64_t M, const float *omega, const double 
             D, M, chunk, nchunks, nbins, nbits, b.tile, b.counts, b.cell_tmp, b.frac_tmp, b.order,
             b.cell, b.frac);
     }
-    k_subproblems<<<dim3(1), dim3(1024), 0, s>>>(nbins, KBN_SUB, b.toff, b.subs, b.nsub);
+    k_subproblems<<<dim3(1), dim3(1024), 0, s>>>(nbins, sub, b.toff, b.subs, b.nsub);
     return hipGetLastError();
 }

@@ -224,6 +224,31 @@ def test_chunked_batches_match_single_pass(dev):
     assert ndft.rel_l2(c[1], c[0]) < 1e-6
 
 
+def test_chunked_jacobian_last_chunk_with_more_groups(dev):
+    """omega-Jacobian in image chunks of 7 and 6 where the smaller last chunk
+    splits into more channel groups than the first (about 2048 / blocks = 6
+    groups at most): the per-group gradient buffer must hold the larger
+    count.  Compared with the single-pass result and the exact gradient on
+    sampled rows."""
+    N = (48, 48)
+    M = 85000
+    _say(f"chunked jacobian N={N} M={M} B=13")
+    om = W.uniform_random(M, 2, seed=41)
+    x = W.complex_normal((13,) + N, 42)
+    g = W.complex_normal((13, 1, M), 43)
+    p1 = _plan(N, dev)
+    per_img = p1.K[0] * p1.K[1] * 8 * 2 * 2  # two grids x D weight channels
+    p2 = _plan(N, dev, max_workspace=7 * per_img + 1024)
+    outs = []
+    for p in (p1, p2):
+        p.set_points(_f(om, dev))
+        outs.append(_np(p.jac_omega_fwd(_c(x, dev), _c(g, dev))))
+    assert ndft.rel_l2(outs[1], outs[0]) < 1e-6
+    rows = np.sort(W.rng(44).choice(M, 64, replace=False))
+    ex = ndft.jac_omega_fwd(om, x, g, N, rows=rows)
+    assert ndft.rel_l2(outs[1][rows], ex) < 1e-4
+
+
 def test_throughput_shape_sampled(dev):
     """256x256, 64 spokes x 512 samples + jitter, sigma 2, J 6: sampled rows/pixels."""
     _say("256x256 M=32768 sampled parity")
