@@ -18,13 +18,17 @@ Other workloads (one JSON line each, not the default):
   --workload batch   32 uneven 2D SENSE instances + one 128^3 kooshball, the
                      same bundle per instance, batched (streams, one graph)
                      against the same kernels launched per instance/coil/op.
+  --workload train   SENSE trajectory-learning step through the autograd
+                     layer: 320x320, 8 images x 8 coils, 16 x 1280 spiral;
+                     forward, loss, backward (x and omega gradients), SGD on
+                     omega (so every step re-sorts the points).
   --workload serve   CG-SENSE requests (10 iterations, lambda 1e-3, 8 coils)
                      arriving as a Poisson process at 50/s: 80% 2D spiral
                      (N 192..384, M 20k..60k), 20% 96^3 kooshball; latency
                      p50/p99 of a continuous-batching server.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B]
-                       [--workload step|batch|serve]
+                       [--workload step|batch|train|serve]
 """
 from __future__ import annotations
 
@@ -230,6 +234,59 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_train(args):
+    import numpy as np
+    import torch
+
+    from paper_2111_02912_amd import workloads as W
+    from paper_2111_02912_amd.autograd import nufft
+    from paper_2111_02912_amd.nufft import KbNufft
+
+    dev = torch.device("cuda", 0)
+    N, om, x, smaps = W.spiral_sense_case()
+    B, C, M = x.shape[0], smaps.shape[0], om.shape[0]
+    plan = KbNufft(N, device=dev)
+    xt = torch.from_numpy(x).to(dev).requires_grad_(True)
+    st = torch.from_numpy(smaps).to(dev)
+    omt = torch.from_numpy(om).to(dev).requires_grad_(True)
+    # data from a perturbed trajectory, as when learning a trajectory
+    with torch.no_grad():
+        delta = torch.from_numpy(W.rng(3004).normal(0.0, 0.1, om.shape).astype(np.float32)).to(dev)
+        plan.set_points(omt + delta)
+        yt = plan.forward(xt, st)
+    opt = torch.optim.SGD([omt], lr=1e-9)
+
+    def step():
+        opt.zero_grad(set_to_none=False)
+        loss = (nufft(xt, omt, plan, st) - yt).abs().pow(2).sum()
+        loss.backward()
+        opt.step()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.timing(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.timing(False)
+    kt = {k: round(ms / args.steps, 4) for k, (n, ms) in plan.timing_read().items() if n}
+    ms = (t1 - t0) * 1e3 / args.steps
+    out = {
+        "metric": "SENSE training step nonuniform pts/s (forward + x/omega gradients + index pass)",
+        "value": B * C * M / (ms * 1e-3), "unit": "pts/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": (f"SENSE trajectory learning: {N[0]}x{N[1]}, {B} images x {C} coils, "
+                                f"16 x 1280 spiral (M = {M}), loss |E(omega) x - y|^2, autograd "
+                                "backward to x and omega, SGD on omega")},
+        "kernel_ms_per_step": kt,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def serve_pool(dev, n2d, n3d, coils=8, seed=5001):
     """Resident problems: square 2D spirals and 96^3 kooshballs with
     Gaussian-bump maps and noiseless data y = E x_true."""
@@ -347,7 +404,7 @@ def main():
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-images", type=int, default=2)
-    ap.add_argument("--workload", choices=("step", "batch", "serve"), default="step")
+    ap.add_argument("--workload", choices=("step", "batch", "train", "serve"), default="step")
     ap.add_argument("--requests", type=int, default=2000, help="serve workload: measured requests")
     ap.add_argument("--warm-requests", type=int, default=100, help="serve workload: unmeasured first requests")
     ap.add_argument("--rate", type=float, default=50.0, help="serve workload: arrivals per second")
@@ -373,6 +430,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "train":
+        return bench_train(args)
 
     import numpy as np
     import torch
