@@ -424,7 +424,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); "
-              "the path shards by image/coil with no communication, see DESIGN.md", file=sys.stderr)
+              "the path shards by image, coil and instance with no communication", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":
         return bench_batch(args)

@@ -28,13 +28,14 @@
 namespace {
 
 // Staged gather: one workgroup per subproblem (<= KBN_SUB sorted points of
-// one tile).  For each channel the tile's grid region (tile plus the tap
-// reach) is loaded into LDS with coalesced reads, then every thread
-// interpolates its point from LDS.  Subproblems of the extra tile id ntiles
-// hold the flagged points, whose outputs are NaN.
+// one tile).  Channels are taken in pairs: the two channels' grid regions
+// (tile plus the tap reach) are loaded into LDS interleaved, with coalesced
+// reads, and every thread interpolates its point for both channels from LDS,
+// one 16-byte read per tap.  Subproblems of the extra tile id ntiles hold the
+// flagged points, whose outputs are NaN.
 template <int D, int J, int MODE>
 __global__ void __launch_bounds__(KBN_BLOCK) k_gather_staged(KbnGeom g, KbnGatherArgs a, int cg) {
-    extern __shared__ float2 reg[];
+    extern __shared__ float4 reg2[];
     const int s = blockIdx.x;
     if (s >= *a.nsub) return;
     const int tile = a.subs[2 * s];
@@ -92,10 +93,10 @@ __global__ void __launch_bounds__(KBN_BLOCK) k_gather_staged(KbnGeom g, KbnGathe
         }
     }
     float jac[KBN_MAX_D] = {0.f, 0.f, 0.f};
-    for (int ch = ch0; ch < ch1; ++ch) {
-        float2 vv = make_float2(0.f, 0.f);
-        if (MODE == 1 && act) vv = a.v[(int64_t)(ch / a.nw) * a.M + q];
-        const float2 *G = a.grid + (int64_t)ch * a.gsize;
+    for (int ch = ch0; ch < ch1; ch += 2) {
+        const bool two = ch + 1 < ch1;
+        const float2 *G0 = a.grid + (int64_t)ch * a.gsize;
+        const float2 *G1 = two ? G0 + a.gsize : G0;
         for (int i = threadIdx.x; i < R; i += KBN_BLOCK) {
             int rem = i;
             int64_t gi = 0, gstride = 1;
@@ -106,61 +107,90 @@ __global__ void __launch_bounds__(KBN_BLOCK) k_gather_staged(KbnGeom g, KbnGathe
                 gi += (int64_t)wrapk(o[d] + e, g.K[d]) * gstride;
                 gstride *= g.K[d];
             }
-            reg[i] = G[gi];
+            const float2 v0 = G0[gi];
+            const float2 v1 = two ? G1[gi] : make_float2(0.f, 0.f);
+            reg2[i] = make_float4(v0.x, v0.y, v1.x, v1.y);
         }
         __syncthreads();
         if (act) {
-            float2 acc = make_float2(0.f, 0.f);
+            float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);  // (channel ch, channel ch + 1)
             if (D == 1) {
 #pragma unroll
                 for (int j0 = 0; j0 < J; ++j0) {
-                    const float2 v = reg[base + j0];
-                    acc.x = fmaf(w[0][j0], v.x, acc.x);
-                    acc.y = fmaf(w[0][j0], v.y, acc.y);
+                    const float4 v = reg2[base + j0];
+                    const float w0 = w[0][j0];
+                    acc.x = fmaf(w0, v.x, acc.x);
+                    acc.y = fmaf(w0, v.y, acc.y);
+                    acc.z = fmaf(w0, v.z, acc.z);
+                    acc.w = fmaf(w0, v.w, acc.w);
                 }
             } else if (D == 2) {
-#pragma unroll
+                // rows one at a time: only one row's taps live in registers
+#pragma unroll 1
                 for (int j0 = 0; j0 < J; ++j0) {
-                    const float2 *row = reg + base + j0 * E[D - 1];
-                    float2 t = make_float2(0.f, 0.f);
+                    const float4 *row = reg2 + base + j0 * E[D - 1];
+                    float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
                     for (int j1 = 0; j1 < J; ++j1) {
-                        const float2 v = row[j1];
-                        t.x = fmaf(w[1][j1], v.x, t.x);
-                        t.y = fmaf(w[1][j1], v.y, t.y);
+                        const float4 v = row[j1];
+                        const float w1 = w[1][j1];
+                        t.x = fmaf(w1, v.x, t.x);
+                        t.y = fmaf(w1, v.y, t.y);
+                        t.z = fmaf(w1, v.z, t.z);
+                        t.w = fmaf(w1, v.w, t.w);
                     }
-                    acc.x = fmaf(w[0][j0], t.x, acc.x);
-                    acc.y = fmaf(w[0][j0], t.y, acc.y);
+                    const float w0 = w[0][j0];
+                    acc.x = fmaf(w0, t.x, acc.x);
+                    acc.y = fmaf(w0, t.y, acc.y);
+                    acc.z = fmaf(w0, t.z, acc.z);
+                    acc.w = fmaf(w0, t.w, acc.w);
                 }
             } else {
-#pragma unroll
+#pragma unroll 1
                 for (int j0 = 0; j0 < J; ++j0) {
-                    float2 t1 = make_float2(0.f, 0.f);
+                    float4 t1 = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
                     for (int j1 = 0; j1 < J; ++j1) {
-                        const float2 *row = reg + base + (j0 * E[1] + j1) * E[2];
-                        float2 t = make_float2(0.f, 0.f);
+                        const float4 *row = reg2 + base + (j0 * E[1] + j1) * E[2];
+                        float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
                         for (int j2 = 0; j2 < J; ++j2) {
-                            const float2 v = row[j2];
-                            t.x = fmaf(w[2][j2], v.x, t.x);
-                            t.y = fmaf(w[2][j2], v.y, t.y);
+                            const float4 v = row[j2];
+                            const float w2 = w[2][j2];
+                            t.x = fmaf(w2, v.x, t.x);
+                            t.y = fmaf(w2, v.y, t.y);
+                            t.z = fmaf(w2, v.z, t.z);
+                            t.w = fmaf(w2, v.w, t.w);
                         }
-                        t1.x = fmaf(w[1][j1], t.x, t1.x);
-                        t1.y = fmaf(w[1][j1], t.y, t1.y);
+                        const float w1 = w[1][j1];
+                        t1.x = fmaf(w1, t.x, t1.x);
+                        t1.y = fmaf(w1, t.y, t1.y);
+                        t1.z = fmaf(w1, t.z, t1.z);
+                        t1.w = fmaf(w1, t.w, t1.w);
                     }
-                    acc.x = fmaf(w[0][j0], t1.x, acc.x);
-                    acc.y = fmaf(w[0][j0], t1.y, acc.y);
+                    const float w0 = w[0][j0];
+                    acc.x = fmaf(w0, t1.x, acc.x);
+                    acc.y = fmaf(w0, t1.y, acc.y);
+                    acc.z = fmaf(w0, t1.z, acc.z);
+                    acc.w = fmaf(w0, t1.w, acc.w);
                 }
             }
             if (MODE == 0) {
-                a.y[(int64_t)ch * a.M + q] = acc;
+                a.y[(int64_t)ch * a.M + q] = make_float2(acc.x, acc.y);
+                if (two) a.y[(int64_t)(ch + 1) * a.M + q] = make_float2(acc.z, acc.w);
             } else {
-                const int wd = ch % a.nw;
-                const float im = acc.y * vv.x - acc.x * vv.y;  // Im{acc conj(v)}
 #pragma unroll
-                for (int d = 0; d < D; ++d)
-                    if (wd == d) jac[d] += im;
+                for (int k = 0; k < 2; ++k) {
+                    if (k == 1 && !two) break;
+                    const int c = ch + k;
+                    const float2 vv = a.v[(int64_t)(c / a.nw) * a.M + q];
+                    const float ax = k == 0 ? acc.x : acc.z, ay = k == 0 ? acc.y : acc.w;
+                    const float im = ay * vv.x - ax * vv.y;  // Im{acc conj(v)}
+                    const int wd = c % a.nw;
+#pragma unroll
+                    for (int d = 0; d < D; ++d)
+                        if (wd == d) jac[d] += im;
+                }
             }
         }
         __syncthreads();
@@ -690,7 +720,7 @@ KbnGatherShape kbn_gather_shape(const KbnGeom &g, int64_t M, int nch, int nw) {
     const int hi = (g.J & 1) ? g.J / 2 + 1 : g.J / 2;
     int64_t region = 1;
     for (int d = 0; d < g.D; ++d) region *= (int64_t)std::min(g.T[d], g.K[d]) + lo + hi;
-    sh.lds = sizeof(float2) * (size_t)region;
+    sh.lds = 2 * sizeof(float2) * (size_t)region;  // two channels interleaved
     sh.staged = sh.lds <= 48 * 1024;
     const int64_t nbc = std::max(1, nch / nw);
     int64_t blocks;
