@@ -28,14 +28,15 @@
 namespace {
 
 // Staged gather: one workgroup per subproblem (<= KBN_SUB sorted points of
-// one tile).  Channels are taken in pairs: the two channels' grid regions
-// (tile plus the tap reach) are loaded into LDS interleaved, with coalesced
-// reads, and every thread interpolates its point for both channels from LDS,
-// one 16-byte read per tap.  Subproblems of the extra tile id ntiles hold the
-// flagged points, whose outputs are NaN.
-template <int D, int J, int MODE>
+// one tile).  Channels are taken CP at a time (CP = 2 or 4): their grid
+// regions (tile plus the tap reach) are loaded into LDS interleaved, with
+// coalesced reads, and every thread interpolates its point for all CP
+// channels from LDS, one 16-byte read per tap and channel pair.  Subproblems
+// of the extra tile id ntiles hold the flagged points, whose outputs are NaN.
+template <int D, int J, int MODE, int CP>
 __global__ void __launch_bounds__(KBN_BLOCK) k_gather_staged(KbnGeom g, KbnGatherArgs a, int cg) {
-    extern __shared__ float4 reg2[];
+    constexpr int H = CP / 2;  // float4 (channel pairs) per region cell
+    extern __shared__ float4 reg4[];
     const int s = blockIdx.x;
     if (s >= *a.nsub) return;
     const int tile = a.subs[2 * s];
@@ -93,10 +94,8 @@ __global__ void __launch_bounds__(KBN_BLOCK) k_gather_staged(KbnGeom g, KbnGathe
         }
     }
     float jac[KBN_MAX_D] = {0.f, 0.f, 0.f};
-    for (int ch = ch0; ch < ch1; ch += 2) {
-        const bool two = ch + 1 < ch1;
-        const float2 *G0 = a.grid + (int64_t)ch * a.gsize;
-        const float2 *G1 = two ? G0 + a.gsize : G0;
+    for (int ch = ch0; ch < ch1; ch += CP) {
+        const int nc = min(CP, ch1 - ch);
         for (int i = threadIdx.x; i < R; i += KBN_BLOCK) {
             int rem = i;
             int64_t gi = 0, gstride = 1;
@@ -107,84 +106,114 @@ __global__ void __launch_bounds__(KBN_BLOCK) k_gather_staged(KbnGeom g, KbnGathe
                 gi += (int64_t)wrapk(o[d] + e, g.K[d]) * gstride;
                 gstride *= g.K[d];
             }
-            const float2 v0 = G0[gi];
-            const float2 v1 = two ? G1[gi] : make_float2(0.f, 0.f);
-            reg2[i] = make_float4(v0.x, v0.y, v1.x, v1.y);
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const float2 v0 = 2 * h < nc ? a.grid[(int64_t)(ch + 2 * h) * a.gsize + gi] : make_float2(0.f, 0.f);
+                const float2 v1 =
+                    2 * h + 1 < nc ? a.grid[(int64_t)(ch + 2 * h + 1) * a.gsize + gi] : make_float2(0.f, 0.f);
+                reg4[i * H + h] = make_float4(v0.x, v0.y, v1.x, v1.y);
+            }
         }
         __syncthreads();
         if (act) {
-            float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);  // (channel ch, channel ch + 1)
+            float4 acc[H];
+#pragma unroll
+            for (int h = 0; h < H; ++h) acc[h] = make_float4(0.f, 0.f, 0.f, 0.f);
             if (D == 1) {
 #pragma unroll
                 for (int j0 = 0; j0 < J; ++j0) {
-                    const float4 v = reg2[base + j0];
                     const float w0 = w[0][j0];
-                    acc.x = fmaf(w0, v.x, acc.x);
-                    acc.y = fmaf(w0, v.y, acc.y);
-                    acc.z = fmaf(w0, v.z, acc.z);
-                    acc.w = fmaf(w0, v.w, acc.w);
+#pragma unroll
+                    for (int h = 0; h < H; ++h) {
+                        const float4 v = reg4[(base + j0) * H + h];
+                        acc[h].x = fmaf(w0, v.x, acc[h].x);
+                        acc[h].y = fmaf(w0, v.y, acc[h].y);
+                        acc[h].z = fmaf(w0, v.z, acc[h].z);
+                        acc[h].w = fmaf(w0, v.w, acc[h].w);
+                    }
                 }
             } else if (D == 2) {
                 // rows one at a time: only one row's taps live in registers
 #pragma unroll 1
                 for (int j0 = 0; j0 < J; ++j0) {
-                    const float4 *row = reg2 + base + j0 * E[D - 1];
-                    float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+                    const float4 *row = reg4 + (base + j0 * E[D - 1]) * H;
+                    float4 t[H];
+#pragma unroll
+                    for (int h = 0; h < H; ++h) t[h] = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
                     for (int j1 = 0; j1 < J; ++j1) {
-                        const float4 v = row[j1];
                         const float w1 = w[1][j1];
-                        t.x = fmaf(w1, v.x, t.x);
-                        t.y = fmaf(w1, v.y, t.y);
-                        t.z = fmaf(w1, v.z, t.z);
-                        t.w = fmaf(w1, v.w, t.w);
+#pragma unroll
+                        for (int h = 0; h < H; ++h) {
+                            const float4 v = row[j1 * H + h];
+                            t[h].x = fmaf(w1, v.x, t[h].x);
+                            t[h].y = fmaf(w1, v.y, t[h].y);
+                            t[h].z = fmaf(w1, v.z, t[h].z);
+                            t[h].w = fmaf(w1, v.w, t[h].w);
+                        }
                     }
                     const float w0 = w[0][j0];
-                    acc.x = fmaf(w0, t.x, acc.x);
-                    acc.y = fmaf(w0, t.y, acc.y);
-                    acc.z = fmaf(w0, t.z, acc.z);
-                    acc.w = fmaf(w0, t.w, acc.w);
+#pragma unroll
+                    for (int h = 0; h < H; ++h) {
+                        acc[h].x = fmaf(w0, t[h].x, acc[h].x);
+                        acc[h].y = fmaf(w0, t[h].y, acc[h].y);
+                        acc[h].z = fmaf(w0, t[h].z, acc[h].z);
+                        acc[h].w = fmaf(w0, t[h].w, acc[h].w);
+                    }
                 }
             } else {
 #pragma unroll 1
                 for (int j0 = 0; j0 < J; ++j0) {
-                    float4 t1 = make_float4(0.f, 0.f, 0.f, 0.f);
+                    float4 t1[H];
+#pragma unroll
+                    for (int h = 0; h < H; ++h) t1[h] = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
                     for (int j1 = 0; j1 < J; ++j1) {
-                        const float4 *row = reg2 + base + (j0 * E[1] + j1) * E[2];
-                        float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+                        const float4 *row = reg4 + (base + (j0 * E[1] + j1) * E[2]) * H;
+                        float4 t[H];
+#pragma unroll
+                        for (int h = 0; h < H; ++h) t[h] = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
                         for (int j2 = 0; j2 < J; ++j2) {
-                            const float4 v = row[j2];
                             const float w2 = w[2][j2];
-                            t.x = fmaf(w2, v.x, t.x);
-                            t.y = fmaf(w2, v.y, t.y);
-                            t.z = fmaf(w2, v.z, t.z);
-                            t.w = fmaf(w2, v.w, t.w);
+#pragma unroll
+                            for (int h = 0; h < H; ++h) {
+                                const float4 v = row[j2 * H + h];
+                                t[h].x = fmaf(w2, v.x, t[h].x);
+                                t[h].y = fmaf(w2, v.y, t[h].y);
+                                t[h].z = fmaf(w2, v.z, t[h].z);
+                                t[h].w = fmaf(w2, v.w, t[h].w);
+                            }
                         }
                         const float w1 = w[1][j1];
-                        t1.x = fmaf(w1, t.x, t1.x);
-                        t1.y = fmaf(w1, t.y, t1.y);
-                        t1.z = fmaf(w1, t.z, t1.z);
-                        t1.w = fmaf(w1, t.w, t1.w);
+#pragma unroll
+                        for (int h = 0; h < H; ++h) {
+                            t1[h].x = fmaf(w1, t[h].x, t1[h].x);
+                            t1[h].y = fmaf(w1, t[h].y, t1[h].y);
+                            t1[h].z = fmaf(w1, t[h].z, t1[h].z);
+                            t1[h].w = fmaf(w1, t[h].w, t1[h].w);
+                        }
                     }
                     const float w0 = w[0][j0];
-                    acc.x = fmaf(w0, t1.x, acc.x);
-                    acc.y = fmaf(w0, t1.y, acc.y);
-                    acc.z = fmaf(w0, t1.z, acc.z);
-                    acc.w = fmaf(w0, t1.w, acc.w);
+#pragma unroll
+                    for (int h = 0; h < H; ++h) {
+                        acc[h].x = fmaf(w0, t1[h].x, acc[h].x);
+                        acc[h].y = fmaf(w0, t1[h].y, acc[h].y);
+                        acc[h].z = fmaf(w0, t1[h].z, acc[h].z);
+                        acc[h].w = fmaf(w0, t1[h].w, acc[h].w);
+                    }
                 }
             }
-            if (MODE == 0) {
-                a.y[(int64_t)ch * a.M + q] = make_float2(acc.x, acc.y);
-                if (two) a.y[(int64_t)(ch + 1) * a.M + q] = make_float2(acc.z, acc.w);
-            } else {
 #pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    if (k == 1 && !two) break;
-                    const int c = ch + k;
+            for (int k = 0; k < CP; ++k) {
+                if (k >= nc) break;
+                const int c = ch + k;
+                const float ax = (k & 1) ? acc[k / 2].z : acc[k / 2].x;
+                const float ay = (k & 1) ? acc[k / 2].w : acc[k / 2].y;
+                if (MODE == 0) {
+                    a.y[(int64_t)c * a.M + q] = make_float2(ax, ay);
+                } else {
                     const float2 vv = a.v[(int64_t)(c / a.nw) * a.M + q];
-                    const float ax = k == 0 ? acc.x : acc.z, ay = k == 0 ? acc.y : acc.w;
                     const float im = ay * vv.x - ax * vv.y;  // Im{acc conj(v)}
                     const int wd = c % a.nw;
 #pragma unroll
@@ -720,7 +749,10 @@ KbnGatherShape kbn_gather_shape(const KbnGeom &g, int64_t M, int nch, int nw) {
     const int hi = (g.J & 1) ? g.J / 2 + 1 : g.J / 2;
     int64_t region = 1;
     for (int d = 0; d < g.D; ++d) region *= (int64_t)std::min(g.T[d], g.K[d]) + lo + hi;
-    sh.lds = 2 * sizeof(float2) * (size_t)region;  // two channels interleaved
+    // channels interpolated per pass: pairs (4 at a time measured slower: the
+    // larger region allows fewer workgroups per CU)
+    sh.cp = 2;
+    sh.lds = sh.cp * sizeof(float2) * (size_t)region;
     sh.staged = sh.lds <= 48 * 1024;
     const int64_t nbc = std::max(1, nch / nw);
     int64_t blocks;
@@ -745,9 +777,9 @@ hipError_t gather_dj(const KbnGeom &g, const KbnGatherArgs &a, int mode, hipStre
     dim3 grid((unsigned)sh.blocks, (unsigned)sh.groups);
     if (sh.staged) {
         if (mode == 0)
-            k_gather_staged<D, J, 0><<<grid, dim3(KBN_BLOCK), sh.lds, s>>>(g, a, sh.cg);
+            k_gather_staged<D, J, 0, 2><<<grid, dim3(KBN_BLOCK), sh.lds, s>>>(g, a, sh.cg);
         else
-            k_gather_staged<D, J, 1><<<grid, dim3(KBN_BLOCK), sh.lds, s>>>(g, a, sh.cg);
+            k_gather_staged<D, J, 1, 2><<<grid, dim3(KBN_BLOCK), sh.lds, s>>>(g, a, sh.cg);
     } else {
         if (mode == 0)
             k_gather<D, J, 0><<<grid, dim3(KBN_BLOCK), 0, s>>>(g, a, sh.cg);

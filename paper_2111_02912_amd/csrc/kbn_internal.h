@@ -162,6 +162,7 @@ struct KbnGatherArgs {
 
 struct KbnGatherShape {
     bool staged;
+    int cp;                    // channels interpolated per pass (staged)
     size_t lds;
     int64_t blocks;
     int cg, groups;
