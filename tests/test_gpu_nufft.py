@@ -270,6 +270,35 @@ def test_throughput_shape_sampled(dev):
     assert ndft.rel_l2(dom[rows], exact_j) < TOL_JAC
 
 
+def test_bench_configuration_sampled(dev):
+    """The benchmarked step at its full size and launch shape: 256 images of
+    256x256, M = 32768 (64 spokes x 512 samples with jitter): forward rows
+    and adjoint pixels of images in different channel groups, and the
+    omega-gradient (summed over all 256 images) on sampled rows."""
+    B = 256
+    _say(f"bench configuration B={B}")
+    N, om, x = W.throughput_case(batch=B)
+    M = om.shape[0]
+    g = W.complex_normal((B, 1, M), 2101)
+    p = _plan(N, dev)
+    xt, gt = _c(x, dev), _c(g, dev)
+    p.set_points(_f(om, dev))
+    y = p.forward(xt)
+    dom = p.jac_omega_fwd(xt, gt)
+    xa = p.adjoint(gt)
+    imgs = [0, 43, 130, 255]
+    rows = np.sort(W.rng(2102).choice(M, 128, replace=False))
+    pix = np.sort(W.rng(2103).choice(N[0] * N[1], 96, replace=False))
+    y_ex = ndft.forward(om, x[imgs], N, rows=rows)
+    e_f = ndft.rel_l2(_np(y)[imgs, 0][:, rows], y_ex)
+    xa_ex = ndft.adjoint(om, g[imgs, 0], N, pix=pix)
+    e_a = ndft.rel_l2(_np(xa).reshape(B, -1)[imgs][:, pix], xa_ex)
+    dom_ex = ndft.jac_omega_fwd(om, x, g, N, rows=rows)
+    e_j = ndft.rel_l2(_np(dom)[rows], dom_ex)
+    _say(f"  fwd {e_f:.2e} adj {e_a:.2e} jac {e_j:.2e}")
+    assert e_f < TOL_NUFFT and e_a < TOL_NUFFT and e_j < TOL_JAC
+
+
 @pytest.mark.parametrize("N", [(64, 96), (160, 128), (48, 40, 64), (256, 130)])
 def test_specialised_fft_matches_generic(N, dev, monkeypatch):
     """The compile-time specialised FFT passes and the generic ones agree, and
