@@ -23,31 +23,39 @@ import sys
 
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
-# kernel symbol fragment -> timing class of the library (first match wins,
-# so the index-pass kernels named k_spread_* come before the spread itself)
-CLASSES = [
-    ("k_spread_records", "index"), ("k_spread_work", "index"), ("k_points_cells", "index"),
-    ("k_tile_hist", "index"), ("k_tile_scatter", "index"), ("k_scan", "index"),
-    ("k_subproblems", "index"), ("k_owner_", "index"), ("k_tile_order", "index"),
-    ("k_first_pass", "fft_first"), ("k_rows_first", "fft_first"),
-    ("k_mid_pass<16, false>", "fft_mid_fwd"), ("k_mid_pass<32, false>", "fft_mid_fwd"),
-    ("k_mid_pass<16, true>", "fft_mid_inv"), ("k_mid_pass<32, true>", "fft_mid_inv"),
-    ("false>", "fft_mid_fwd"), ("true>", "fft_mid_inv"),  # k_cols<L, E, INV>
-    ("k_last_adj", "fft_last_adj"), ("k_rows_last_adj", "fft_last_adj"),
-    ("k_gather_staged<2, 6, 0>", "gather"), ("k_gather_staged<3, 6, 0>", "gather"),
-    ("k_gather<", "gather"),
-    ("k_gather_staged<2, 6, 1>", "gather_jac"), ("k_gather_staged<3, 6, 1>", "gather_jac"),
-    ("k_reduce_parts", "gather_jac"),
-    ("k_spread", "spread"), ("k_permute", "spread"),
-]
+# kernel name -> timing class of the library
+_INDEX = ("k_spread_records", "k_spread_work", "k_points_cells", "k_tile_hist", "k_tile_scatter",
+          "k_scan", "k_subproblems", "k_owner_", "k_tile_order")
+
+
+def _targs(name: str):
+    """Template arguments of a kernel symbol, e.g. 'k_cols<512, 16, false, 512>'."""
+    if "<" not in name:
+        return []
+    inner = name[name.index("<") + 1:name.rindex(">")] if ">" in name else ""
+    return [t.strip() for t in inner.split(",")]
 
 
 def kernel_class(name: str):
-    for frag, cls in CLASSES:
-        if frag in name:
-            if frag in ("false>", "true>") and "k_cols" not in name:
-                continue
-            return cls
+    base = name.split("<")[0].split("::")[-1].strip()
+    if any(base.startswith(k) for k in _INDEX):
+        return "index"
+    ta = _targs(name)
+    if base in ("k_first_pass", "k_rows_first"):
+        return "fft_first"
+    if base in ("k_last_adj", "k_rows_last_adj"):
+        return "fft_last_adj"
+    if base in ("k_cols", "k_mid_pass"):
+        # k_cols<L, E, INV, NT>, k_mid_pass<MAXE, INV>
+        inv = ta[2] if base == "k_cols" and len(ta) > 2 else (ta[1] if len(ta) > 1 else "false")
+        return "fft_mid_inv" if inv == "true" else "fft_mid_fwd"
+    if base in ("k_gather_staged", "k_gather"):
+        # <D, J, MODE, ...>
+        return "gather_jac" if len(ta) > 2 and ta[2] == "1" else "gather"
+    if base == "k_reduce_parts":
+        return "gather_jac"
+    if base.startswith("k_spread") or base == "k_permute":
+        return "spread"
     return None
 
 
