@@ -570,7 +570,7 @@ __global__ void __launch_bounds__(512) k_spread_os(KbnGeom g, KbnSpreadArgs a) {
             __syncthreads();  // previous batch (or work item) consumed
             for (int t = threadIdx.x; t < n; t += nthr) {
                 const int e = eb + t;
-                s_p[t] = a.rec_p[e];
+                s_p[t] = a.order[a.rec_p[e]];  // the sample's index in the caller's order
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
                     s_l[t][d] = a.rec_l[(int64_t)e * D + d];
@@ -584,7 +584,7 @@ __global__ void __launch_bounds__(512) k_spread_os(KbnGeom g, KbnSpreadArgs a) {
             for (int i = threadIdx.x; i < EB * CPT; i += nthr) {
                 const int t = i % EB;
                 const int k = i / EB;
-                if (t < n && k < nchg) s_y[t][k] = a.ys[(int64_t)(ch0 + k) * a.M + s_p[t]];
+                if (t < n && k < nchg) s_y[t][k] = a.y[(int64_t)(ch0 + k) * a.M + s_p[t]];
             }
             __syncthreads();
             for (int i = 0; i < n; ++i) {
@@ -828,10 +828,6 @@ hipError_t spread_dj(const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s) {
     const SpreadShape sh = spread_shape(g, a.nch);
     const int ngroup = sh.nwave * sh.cw;
     const int ng = (a.nch + ngroup - 1) / ngroup;
-    if (a.M > 0) {
-        dim3 pgrid((unsigned)((a.M + KBN_BLOCK - 1) / KBN_BLOCK), (unsigned)a.nch);
-        k_permute<<<pgrid, dim3(KBN_BLOCK), 0, s>>>(a.y, a.ys, a.order, a.M);
-    }
     int tcells = 1;
     for (int d = 0; d < D; ++d) tcells *= g.To[d];
     static const bool os_on = [] {
@@ -870,6 +866,10 @@ hipError_t spread_dj(const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s) {
             k_spread_combine<D><<<dim3((unsigned)a.nch, (unsigned)ny), dim3(cb), 0, s>>>(g, a);
         }
         return hipGetLastError();
+    }
+    if (a.M > 0) {  // the scatter kernel reads k-space values in tile order
+        dim3 pgrid((unsigned)((a.M + KBN_BLOCK - 1) / KBN_BLOCK), (unsigned)a.nch);
+        k_permute<<<pgrid, dim3(KBN_BLOCK), 0, s>>>(a.y, a.ys, a.order, a.M);
     }
     dim3 grid((unsigned)ng, (unsigned)a.nwork_max);
     if (sh.A == 1 || D == 1)

@@ -728,10 +728,10 @@ int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream_) {
     if (M < 0 || M > 2147483647LL) return fail(KBN_ERR_INVALID_ARG, "M out of range");
     if (M > 0 && !omega) return fail(KBN_ERR_INVALID_ARG, "null omega");
     const int nbins = p->ntiles + 1;
-    // histogram chunks: about a thousand of at least 256 points, so that the
+    // histogram chunks: about a thousand of at least 64 points, so that the
     // counting and scattering kernels fill the GPU; the bin-major count matrix
     // (bins x chunks) is scanned by a multi-block scan
-    int64_t chunk = std::max<int64_t>(256, (M + 1023) / 1024);
+    int64_t chunk = std::max<int64_t>(64, (M + 1023) / 1024);
     chunk = (chunk + 63) / 64 * 64;
     const int64_t nchunks = M > 0 ? (M + chunk - 1) / chunk : 0;
     const int nbins_o = p->ntiles_own;
