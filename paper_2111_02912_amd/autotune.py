@@ -23,8 +23,8 @@ CANDIDATES = {
     1: [dict(tile=(256,), spread_tile=128), dict(tile=(128,), spread_tile=64)],
     2: [dict(tile=(32, 32), spread_tile=12), dict(tile=(16, 16), spread_tile=12),
         dict(tile=(32, 32), spread_tile=8), dict(tile=(32, 32), spread_tile=16)],
-    3: [dict(tile=(16, 16, 16), spread_tile=16), dict(tile=(8, 8, 8), spread_tile=16),
-        dict(tile=(16, 16, 16), spread_tile=12)],
+    3: [dict(tile=(8, 8, 8), spread_tile=8), dict(tile=(16, 16, 16), spread_tile=8),
+        dict(tile=(8, 8, 8), spread_tile=16)],
 }
 
 _cache: Dict[tuple, dict] = {}

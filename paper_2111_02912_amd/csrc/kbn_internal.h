@@ -13,7 +13,7 @@
 #define KBN_NCOEF 11        // polynomial coefficients per window piece (degree 10)
 #define KBN_MAX_STAGES 24
 #define KBN_MAX_K 1024      // largest oversampled grid edge handled by the LDS FFT
-#define KBN_MAX_TILES 16383 // tile histogram lives in LDS (ntiles + 1 counters)
+#define KBN_MAX_TILES 40959 // tile histograms live in LDS (ntiles + 1 counters, at most 160 KiB)
 #define KBN_BLOCK 256
 #define KBN_SUB 256        // sorted points per gather subproblem (one per thread)
 #define KBN_SPREAD_EB 64   // list entries staged per spread batch

@@ -491,6 +491,23 @@ k_spread_work(int ntiles, int seg, int smax, const int *__restrict__ ooff,
 
 }  // namespace
 
+// Histograms of more than 16384 bins need more than the default 64 KiB of
+// dynamic LDS per workgroup; gfx950 allows up to 160 KiB once a kernel opts in.
+hipError_t allow_large_lds(size_t bytes) {
+    if (bytes <= 64 * 1024) return hipSuccess;
+    static const hipError_t once = [] {
+        const void *ks[] = {(const void *)k_tile_hist, (const void *)k_tile_scatter,
+                            (const void *)k_owner_hist, (const void *)k_owner_scatter};
+        hipError_t r = hipSuccess;
+        for (const void *k : ks) {
+            const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            if (e != hipSuccess) r = e;
+        }
+        return r;
+    }();
+    return once;
+}
+
 hipError_t kbn_launch_owner_lists(int D, int J, int ntiles_sort, const int *K, const int *To,
                                   const int *nto, int ntiles_own, int64_t M, int chunk,
                                   int nchunks, const int *cell, const float *frac,
@@ -507,6 +524,10 @@ hipError_t kbn_launch_owner_lists(int D, int J, int ntiles_sort, const int *K, c
         o.nto[d] = d < D ? nto[d] : 1;
     }
     const int nbins = ntiles_own;
+    {
+        const hipError_t e = allow_large_lds(sizeof(int) * (size_t)nbins);
+        if (e != hipSuccess) return e;
+    }
     if (M > 0)
         k_owner_hist<<<dim3(nchunks), dim3(64), sizeof(int) * nbins, s>>>(
             o, M, chunk, nchunks, nbins, cell, frac, toff, counts);
@@ -530,6 +551,10 @@ hipError_t kbn_launch_points(int D, int64_t M, const float *omega, const double 
                              const int *K, const int *T, const int *nt, int ntiles,
                              int chunk, int nchunks, int sub, const KbnPointsBufs &b, hipStream_t s) {
     const int nbins = ntiles + 1;
+    {
+        const hipError_t e = allow_large_lds(sizeof(int) * (size_t)nbins);
+        if (e != hipSuccess) return e;
+    }
     if (M > 0) {
         const int64_t blocks = (M + KBN_BLOCK - 1) / KBN_BLOCK;
         k_points_cells<<<dim3((unsigned)blocks), dim3(KBN_BLOCK), 0, s>>>(
