@@ -45,5 +45,9 @@ def test_error_strings_without_gpu():
     assert L.kbn_plan_create(ctypes.byref(h), 2, N, ctypes.byref(o)) == _lib.KBN_ERR_INVALID_ARG
     big = (ctypes.c_int64 * 2)(600, 64)  # K = 1200 > 1024
     assert L.kbn_plan_create(ctypes.byref(h), 2, big, None) == _lib.KBN_ERR_UNSUPPORTED
+    small = (ctypes.c_int64 * 2)(3, 64)  # K = 6 < 2 J: the window does not fit the grid
+    assert L.kbn_plan_create(ctypes.byref(h), 2, small, None) == _lib.KBN_ERR_UNSUPPORTED
+    zero = (ctypes.c_int64 * 2)(0, 64)
+    assert L.kbn_plan_create(ctypes.byref(h), 2, zero, None) == _lib.KBN_ERR_INVALID_ARG
     assert L.kbn_set_points(None, 1, None, None) == _lib.KBN_ERR_INVALID_ARG
     assert L.kbn_forward(None, 1, 1, None, None, None, None) == _lib.KBN_ERR_INVALID_ARG

@@ -342,3 +342,26 @@ def test_grid_sizes_without_a_near_tile_divisor(dev):
     e_a = ndft.rel_l2(_np(xa), ndft.sense_adjoint(om, g, N, smaps))
     _say(f"  fwd {e_f:.2e} adj {e_a:.2e}")
     assert e_f < TOL_NUFFT and e_a < TOL_NUFFT
+
+
+def test_largest_grid_and_clustered_samples(dev):
+    """The largest supported grid (512 x 512 images, K = 1024 per axis) with
+    5000 samples at one location among uniform ones: hot tiles are split
+    into many gather subproblems and spread work items."""
+    N = (512, 512)
+    _say(f"largest grid N={N} with clustered samples")
+    hot = np.tile(np.array([[0.3, -1.1]], dtype=np.float32), (5000, 1))
+    om = np.concatenate([W.uniform_random(3000, 2, seed=9301), hot]).astype(np.float32)
+    x = W.complex_normal((1,) + N, 9302)
+    g = W.complex_normal((1, 1, om.shape[0]), 9303)
+    p = _plan(N, dev)
+    assert p.K == (1024, 1024)
+    p.set_points(_f(om, dev))
+    y = _np(p.forward(_c(x, dev)))
+    xa = _np(p.adjoint(_c(g, dev)))
+    rows = np.concatenate([np.arange(0, 3000, 37), np.arange(3000, 8000, 500)])
+    e_f = ndft.rel_l2(y[0, 0, rows], ndft.forward(om, x, N, rows=rows)[0])
+    pix = np.sort(W.rng(9304).choice(N[0] * N[1], 200, replace=False))
+    e_a = ndft.rel_l2(xa.reshape(-1)[pix], ndft.adjoint(om, g[0, 0], N, pix=pix))
+    _say(f"  fwd {e_f:.2e} adj {e_a:.2e}")
+    assert e_f < TOL_NUFFT and e_a < TOL_NUFFT
