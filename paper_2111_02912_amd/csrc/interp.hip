@@ -526,11 +526,20 @@ __global__ void __launch_bounds__(KBN_BLOCK) k_spread(KbnGeom g, KbnSpreadArgs a
 template <int D, int J, int CPT, int EB>
 __global__ void __launch_bounds__(512) k_spread_os(KbnGeom g, KbnSpreadArgs a) {
     __shared__ float2 s_y[EB][CPT];
-    __shared__ float s_w[EB][D][J];
-    __shared__ int s_l[EB][D];
     __shared__ int s_p[EB];
+    // 2D: per staged entry the tap origin relative to the tile and the J
+    // window weights of each axis.  3D: per staged entry and axis, the
+    // window weight seen by each cell coordinate of the tile along that axis
+    // (zero outside the footprint), so that a thread's weight is a product
+    // of table reads (measured faster in 3D, slower in 2D).
+    __shared__ float s_w[D == 2 ? EB : 1][D][J];
+    __shared__ int s_l[D == 2 ? EB : 1][D];
+    extern __shared__ float s_t[];  // 3D: [EB][D][To_max]
     const int nwork = a.scounts[0];
     const int nthr = blockDim.x;
+    int tmax = 1;
+#pragma unroll
+    for (int d = 0; d < D; ++d) tmax = max(tmax, g.To[d]);
     int c[D];
     {
         int t = threadIdx.x;
@@ -569,16 +578,37 @@ __global__ void __launch_bounds__(512) k_spread_os(KbnGeom g, KbnSpreadArgs a) {
             const int n = min(EB, e1 - eb);
             __syncthreads();  // previous batch (or work item) consumed
             for (int t = threadIdx.x; t < n; t += nthr) {
-                const int e = eb + t;
-                s_p[t] = a.order[a.rec_p[e]];  // the sample's index in the caller's order
+                s_p[t] = a.order[a.rec_p[eb + t]];
+                if (D == 2) {
 #pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    s_l[t][d] = a.rec_l[(int64_t)e * D + d];
-                    float w[J];
-                    kb_weights<J>(a.rec_f[(int64_t)e * D + d], g.coef, w);
+                    for (int d = 0; d < D; ++d) {
+                        s_l[t][d] = a.rec_l[(int64_t)(eb + t) * D + d];
+                        float w[J];
+                        kb_weights<J>(a.rec_f[(int64_t)(eb + t) * D + d], g.coef, w);
 #pragma unroll
-                    for (int j = 0; j < J; ++j) s_w[t][d][j] = w[j];
+                        for (int j = 0; j < J; ++j) s_w[t][d][j] = w[j];
+                    }
                 }
+            }
+            // 3D weight tables: entry t, axis d, cell coordinate cc
+            for (int idx = threadIdx.x; D == 3 && idx < n * D * tmax; idx += nthr) {
+                const int cc = idx % tmax;
+                const int td = idx / tmax;
+                const int d = td % D;
+                const int t = td / D;
+                const int64_t e = eb + t;
+                int j = cc - a.rec_l[e * D + d];
+                if (j < 0) j += g.K[d];
+                float wv = 0.f;
+                if (j < J) {
+                    const float x = 2.f * a.rec_f[e * D + d] - 1.f;
+                    const float *cf = g.coef + j * KBN_NCOEF;
+                    float acc_w = cf[KBN_NCOEF - 1];
+#pragma unroll
+                    for (int k = KBN_NCOEF - 2; k >= 0; --k) acc_w = fmaf(acc_w, x, cf[k]);
+                    wv = acc_w;
+                }
+                s_t[idx] = wv;
             }
             __syncthreads();
             for (int i = threadIdx.x; i < EB * CPT; i += nthr) {
@@ -588,24 +618,28 @@ __global__ void __launch_bounds__(512) k_spread_os(KbnGeom g, KbnSpreadArgs a) {
             }
             __syncthreads();
             for (int i = 0; i < n; ++i) {
+                float w;
                 if (D == 3) {
+                    const float *ti = s_t + i * D * tmax;
+                    w = ti[c[0]];
                     // with 8 x 8 cells per x-slice a wave holds one slice, so
                     // this skip is taken by whole waves when the footprint
                     // misses the slice
-                    int j = c[0] - s_l[i][0];
-                    if (j < 0) j += g.K[0];
-                    if (j >= J) continue;
-                }
-                bool in = active;
-                float w = 1.f;
+                    if (w == 0.f) continue;
 #pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    int j = c[d] - s_l[i][d];
-                    if (j < 0) j += g.K[d];
-                    in = in && j < J;
-                    w *= s_w[i][d][j < J ? j : J - 1];
+                    for (int d = 1; d < D; ++d) w *= ti[d * tmax + c[d]];
+                } else {
+                    bool in = true;
+                    w = 1.f;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        int j = c[d] - s_l[i][d];
+                        if (j < 0) j += g.K[d];
+                        in = in && j < J;
+                        w *= s_w[i][d][j < J ? j : J - 1];
+                    }
+                    w = in ? w : 0.f;
                 }
-                w = in ? w : 0.f;
 #pragma unroll
                 for (int k = 0; k < CPT; ++k) {
                     const float2 y = s_y[i][k];
@@ -841,23 +875,27 @@ hipError_t spread_dj(const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s) {
         const int ngr = (a.nch + cpt - 1) / cpt;
         dim3 grid_os((unsigned)ngr, (unsigned)a.nwork_max);
         dim3 blk((unsigned)tcells);
+        int tmax = 1;
+        for (int d = 0; d < D; ++d) tmax = std::max(tmax, g.To[d]);
+        const int ebv = D == 3 ? (cpt <= 16 ? 64 : 32) : 32;  // entries per batch of the chosen kernel
+        const size_t tlds = D == 3 ? sizeof(float) * (size_t)ebv * D * tmax : 0;
         if (D == 3) {
             switch (cpt) {
-                case 1: k_spread_os<D, J, 1, 64><<<grid_os, blk, 0, s>>>(g, a); break;
-                case 2: k_spread_os<D, J, 2, 64><<<grid_os, blk, 0, s>>>(g, a); break;
-                case 4: k_spread_os<D, J, 4, 64><<<grid_os, blk, 0, s>>>(g, a); break;
-                case 8: k_spread_os<D, J, 8, 64><<<grid_os, blk, 0, s>>>(g, a); break;
-                case 16: k_spread_os<D, J, 16, 64><<<grid_os, blk, 0, s>>>(g, a); break;
-                default: k_spread_os<D, J, 32, 32><<<grid_os, blk, 0, s>>>(g, a); break;
+                case 1: k_spread_os<D, J, 1, 64><<<grid_os, blk, tlds, s>>>(g, a); break;
+                case 2: k_spread_os<D, J, 2, 64><<<grid_os, blk, tlds, s>>>(g, a); break;
+                case 4: k_spread_os<D, J, 4, 64><<<grid_os, blk, tlds, s>>>(g, a); break;
+                case 8: k_spread_os<D, J, 8, 64><<<grid_os, blk, tlds, s>>>(g, a); break;
+                case 16: k_spread_os<D, J, 16, 64><<<grid_os, blk, tlds, s>>>(g, a); break;
+                default: k_spread_os<D, J, 32, 32><<<grid_os, blk, tlds, s>>>(g, a); break;
             }
         } else {
             switch (cpt) {
-                case 1: k_spread_os<D, J, 1, 32><<<grid_os, blk, 0, s>>>(g, a); break;
-                case 2: k_spread_os<D, J, 2, 32><<<grid_os, blk, 0, s>>>(g, a); break;
-                case 4: k_spread_os<D, J, 4, 32><<<grid_os, blk, 0, s>>>(g, a); break;
-                case 8: k_spread_os<D, J, 8, 32><<<grid_os, blk, 0, s>>>(g, a); break;
-                case 16: k_spread_os<D, J, 16, 32><<<grid_os, blk, 0, s>>>(g, a); break;
-                default: k_spread_os<D, J, 32, 32><<<grid_os, blk, 0, s>>>(g, a); break;
+                case 1: k_spread_os<D, J, 1, 32><<<grid_os, blk, tlds, s>>>(g, a); break;
+                case 2: k_spread_os<D, J, 2, 32><<<grid_os, blk, tlds, s>>>(g, a); break;
+                case 4: k_spread_os<D, J, 4, 32><<<grid_os, blk, tlds, s>>>(g, a); break;
+                case 8: k_spread_os<D, J, 8, 32><<<grid_os, blk, tlds, s>>>(g, a); break;
+                case 16: k_spread_os<D, J, 16, 32><<<grid_os, blk, tlds, s>>>(g, a); break;
+                default: k_spread_os<D, J, 32, 32><<<grid_os, blk, tlds, s>>>(g, a); break;
             }
         }
         if (a.ncomb_max > 0) {
