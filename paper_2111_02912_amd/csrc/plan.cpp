@@ -650,8 +650,6 @@ int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts
     // in LDS, large enough that the tile count fits the LDS histogram
     int64_t ntiles_own = 1;
     int defown = o.spread_tile > 0 ? std::max(J, o.spread_tile) : (D == 1 ? 128 : 8);
-    if (o.spread_tile <= 0)
-        if (const char *e = std::getenv("KBN_OWNER_TILE")) defown = std::max(J, std::atoi(e));
     for (;;) {
         ntiles_own = 1;
         for (int d = 0; d < D; ++d) {

@@ -365,3 +365,25 @@ def test_largest_grid_and_clustered_samples(dev):
     e_a = ndft.rel_l2(xa.reshape(-1)[pix], ndft.adjoint(om, g[0, 0], N, pix=pix))
     _say(f"  fwd {e_f:.2e} adj {e_a:.2e}")
     assert e_f < TOL_NUFFT and e_a < TOL_NUFFT
+
+
+@pytest.mark.parametrize("N,st", [((60, 52), 24), ((20, 22, 18), 10)])
+def test_scatter_spread_path(N, st, dev):
+    """Owner tiles of more than 512 cells use the scatter spread kernel
+    (lanes own (tap, channel) pairs; the path of 1D plans): adjoint and
+    adjoint-operator Jacobian against the exact NUDFT, with coil maps."""
+    D = len(N)
+    _say(f"scatter spread N={N} spread_tile={st}")
+    om = W.uniform_random(2500, D, seed=9401)
+    C = 3
+    smaps = W.sense_maps(C, N).astype(np.complex64)
+    y = W.complex_normal((2, C, om.shape[0]), 9402)
+    gi = W.complex_normal((2,) + N, 9403)
+    p = _plan(N, dev, spread_tile=st)
+    p.set_points(_f(om, dev))
+    xa = _np(p.adjoint(_c(y, dev), _c(smaps, dev)))
+    e_a = ndft.rel_l2(xa, ndft.sense_adjoint(om, y, N, smaps))
+    dom = _np(p.jac_omega_adj(_c(y, dev), _c(gi, dev), _c(smaps, dev)))
+    e_j = ndft.rel_l2(dom, ndft.jac_omega_adj(om, y, gi, N, smaps))
+    _say(f"  adj {e_a:.2e} jac_adj {e_j:.2e}")
+    assert e_a < TOL_NUFFT and e_j < TOL_JAC
