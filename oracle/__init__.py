@@ -14,4 +14,6 @@ Contents
   points_ref the per-point grid offsets, fractions, tile ids and the stable
              tile order that the index pass must reproduce bit for bit.
   cg         FP64 conjugate-gradient CG-SENSE reconstruction.
+  inverse    the regularised inverse (E^H E + lambda I)^{-1} by dense FP64 solves,
+             and the gradients of the Gram and inverse operators (Sec. II-E).
 """

@@ -209,3 +209,32 @@ def rel_l2(a, b) -> float:
     b = np.asarray(b)
     nb = np.linalg.norm(b.ravel())
     return float(np.linalg.norm((a - b).ravel()) / (nb if nb > 0 else 1.0))
+
+
+# ---------------------------------------------------------------------------
+# Gram and regularised-inverse operators (Sec. II-E)
+# ---------------------------------------------------------------------------
+
+def gram_vjp(omega, x, g, N, smaps=None):
+    """Gradients of a real loss through z = E^H E x (E = SENSE model).
+
+    With the JVP rule (e,jac,Ax,v) applied to both factors of the Gram
+    operator (Sec. II-E: the Jacobian of A'A x w.r.t. omega^[d] has one
+    term from A and one from A'):
+      dL/domega[m, d] = Im{ [E(g r^[d])]_m conj([E x]_m) }
+                      + Im{ [E(x r^[d])]_m conj([E g]_m) }   (summed over coils)
+      dL/dx           = E^H E g   (the Gram operator is Hermitian)
+    x, g: [B, *N]; returns (domega [M, D], dx [B, *N]).
+    """
+    N = tuple(int(n) for n in N)
+    ex = sense_forward(omega, x, N, smaps)
+    eg = sense_forward(omega, g, N, smaps)
+    dom = jac_omega_fwd(omega, g, ex, N, smaps) + jac_omega_fwd(omega, x, eg, N, smaps)
+    dx = sense_adjoint(omega, eg, N, smaps)
+    return dom, dx
+
+
+def gram(omega, x, N, smaps=None):
+    """z = E^H E x for images x [B, *N]."""
+    N = tuple(int(n) for n in N)
+    return sense_adjoint(omega, sense_forward(omega, x, N, smaps), N, smaps)
