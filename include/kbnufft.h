@@ -256,6 +256,14 @@ int kbn_cg_step(kbn_plan p, int C, const void *smaps, double lambda, int iters, 
                 void *work, void *stream);
 
 /*
+ * Start a solve of (E^H E + lambda I) x = b for an image right-hand side b
+ * (c64 [N..], device) instead of b = E^H y: x = 0, r = p = b.  Used to apply
+ * the regularised inverse of Sec. II-E to an image (and to its upstream
+ * gradient).  Continue with kbn_cg_step.  Errors as kbn_cg_begin.
+ */
+int kbn_cg_begin_image(kbn_plan p, int C, const void *b, void *x, void *work, void *stream);
+
+/*
  * Batches: many independent operator calls issued together.
  *
  * Not an operation of the paper; an executor for running many SENSE

@@ -34,6 +34,7 @@ EXPORTS = (
     "kbn_last_error", "kbn_timing", "kbn_timing_read", "kbn_timing_name",
     "kbn_batch_create", "kbn_batch_run", "kbn_batch_capture", "kbn_batch_launch",
     "kbn_batch_destroy", "kbn_cg_work_bytes", "kbn_cg_begin", "kbn_cg_step",
+    "kbn_cg_begin_image",
 )
 
 
@@ -111,6 +112,7 @@ def lib():
     L.kbn_cg_work_bytes.argtypes = [vp, ci, ctypes.POINTER(i64)]
     L.kbn_cg_begin.argtypes = [vp, ci, vp, vp, vp, vp, vp]
     L.kbn_cg_step.argtypes = [vp, ci, vp, ctypes.c_double, ci, vp, vp, vp]
+    L.kbn_cg_begin_image.argtypes = [vp, ci, vp, vp, vp, vp]
     for name in EXPORTS:
         if name not in ("kbn_strerror", "kbn_last_error", "kbn_timing_name"):
             getattr(L, name).restype = ci

@@ -123,3 +123,105 @@ class KbNufftLayer(torch.nn.Module):
 
     def adjoint(self, y, omega, smaps=None):
         return nufft_adjoint(y, omega, self.plan(y.device), smaps)
+
+
+# ---------------------------------------------------------------------------
+# Gram and regularised-inverse operators (Sec. II-E)
+# ---------------------------------------------------------------------------
+
+def _gram_vjp(plan: KbNufft, x, g, smaps, need_x: bool, need_om: bool):
+    """(dx, domega) for z = E^H E x with upstream g: the omega-gradient has
+    one term from each factor of the Gram operator,
+    Im{E(g r) conj(E x)} + Im{E(x r) conj(E g)} summed over coils, and
+    dx = E^H E g."""
+    eg = plan.forward(g, smaps)
+    gx = gom = None
+    if need_x:
+        gx = plan.adjoint(eg, smaps)
+    if need_om:
+        ex = plan.forward(x, smaps)
+        gom = plan.jac_omega_fwd(g, ex, smaps)
+        plan.jac_omega_fwd(x, eg, smaps, out=gom, accumulate=True)
+    return gx, gom
+
+
+class _GramOp(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, omega, smaps, plan):
+        _no_map_grad(smaps)
+        plan.ensure_points(omega)
+        z = plan.adjoint(plan.forward(x, smaps), smaps).reshape(x.shape)
+        ctx.plan = plan
+        ctx.xshape = x.shape
+        ctx.save_for_backward(x, omega, smaps)
+        return z
+
+    @staticmethod
+    @once_differentiable
+    def backward(ctx, g):
+        x, omega, smaps = ctx.saved_tensors
+        plan = ctx.plan
+        plan.ensure_points(omega)
+        gx, gom = _gram_vjp(plan, x, g.contiguous().reshape(ctx.xshape), smaps,
+                            ctx.needs_input_grad[0], ctx.needs_input_grad[1])
+        if gx is not None:
+            gx = gx.reshape(ctx.xshape)
+        return gx, gom, None, None
+
+
+def _cg_solve(plan: KbNufft, x, smaps, lam: float, iters: int):
+    """F^{-1} x image by image with the library's CG (F = E^H E + lam I),
+    starting from the right-hand side x itself (CG-SENSE in the library takes
+    E^H y; here the right-hand side is an image, so y is not formed: the
+    solve runs on E^H E + lam I with b = x)."""
+    from .cg import CgSense
+    C = 1 if smaps is None else int(smaps.shape[0])
+    out = torch.empty_like(x)
+    s = CgSense(plan, C)
+    for b in range(x.shape[0]):
+        s.begin_rhs(x[b], smaps).step(iters, lam)
+        out[b].copy_(s.x)
+    return out
+
+
+class _InverseOp(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, omega, smaps, plan, lam, iters):
+        _no_map_grad(smaps)
+        plan.ensure_points(omega)
+        xb = x.reshape((-1,) + plan.N).contiguous()
+        z = _cg_solve(plan, xb, smaps, lam, iters)
+        ctx.plan = plan
+        ctx.xshape = x.shape
+        ctx.lam, ctx.iters = lam, iters
+        ctx.save_for_backward(z, omega, smaps)
+        return z.reshape(x.shape)
+
+    @staticmethod
+    @once_differentiable
+    def backward(ctx, g):
+        z, omega, smaps = ctx.saved_tensors
+        plan = ctx.plan
+        plan.ensure_points(omega)
+        w = _cg_solve(plan, g.contiguous().reshape(z.shape), smaps, ctx.lam, ctx.iters)
+        gom = None
+        if ctx.needs_input_grad[1]:
+            _, gom = _gram_vjp(plan, z, w, smaps, False, True)
+            gom = -gom
+        gx = w.reshape(ctx.xshape) if ctx.needs_input_grad[0] else None
+        return gx, gom, None, None, None, None
+
+
+def gram(x: torch.Tensor, omega: torch.Tensor, plan: KbNufft,
+         smaps: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """z = E(omega)^H E(omega) x: x [B, *N] complex64 -> [B, *N]."""
+    return _GramOp.apply(x, omega, smaps, plan)
+
+
+def inverse(x: torch.Tensor, omega: torch.Tensor, plan: KbNufft,
+            smaps: Optional[torch.Tensor] = None, lam: float = 1e-3,
+            iters: int = 20) -> torch.Tensor:
+    """z = (E^H E + lam I)^{-1} x by `iters` CG iterations per image; the
+    backward solves with the same operator (the paper's approach of treating
+    the solve as exact and differentiating the exact inverse)."""
+    return _InverseOp.apply(x, omega, smaps, plan, float(lam), int(iters))

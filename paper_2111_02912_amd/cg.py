@@ -43,6 +43,19 @@ class CgSense:
                                       _stream(p.device)), "kbn_cg_begin")
         return self
 
+    def begin_rhs(self, b: torch.Tensor, smaps: Optional[torch.Tensor] = None):
+        """x = 0, r = p = b for an image right-hand side b [*N] (solving
+        (E^H E + lam I) x = b)."""
+        p = self.plan
+        s, C = p._maps(smaps)
+        if C != self.C:
+            raise ValueError(f"smaps has {C} coils, solver was made for {self.C}")
+        bb = p._img(b, "b").reshape(p.N)
+        self._keep = (bb, s)
+        check(_lib.lib().kbn_cg_begin_image(p._h, C, _ptr(bb), _ptr(self.x), _ptr(self.work),
+                                            _stream(p.device)), "kbn_cg_begin_image")
+        return self
+
     def step(self, iters: int, lam: float = 1e-3):
         p = self.plan
         s = self._keep[1]

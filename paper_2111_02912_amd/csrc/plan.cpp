@@ -891,6 +891,21 @@ int kbn_cg_begin(kbn_plan p, int C, const void *smaps, const void *y, void *x, v
     return cg_launch(KBN_CGK_INIT, npix, (float2 *)x, b, 0.f, stream);
 }
 
+int kbn_cg_begin_image(kbn_plan p, int C, const void *b, void *x, void *work, void *stream_) {
+    if (!p) return fail(KBN_ERR_INVALID_ARG, "null plan");
+    if (p->M < 0) return fail(KBN_ERR_NO_POINTS, "kbn_set_points has not been called");
+    if (C < 1) return fail(KBN_ERR_INVALID_ARG, "C must be >= 1");
+    if (!b || !x || !work) return fail(KBN_ERR_INVALID_ARG, "null pointer");
+    hipStream_t stream = (hipStream_t)stream_;
+    CgBufs cb;
+    cg_bytes(p, C, &cb, work);
+    int64_t npix = 1;
+    for (int d = 0; d < p->D; ++d) npix *= p->N[d];
+    // r = b (x0 = 0), p = r
+    KBN_HIP(hipMemcpyAsync(cb.r, b, sizeof(float2) * npix, hipMemcpyDeviceToDevice, stream));
+    return cg_launch(KBN_CGK_INIT, npix, (float2 *)x, cb, 0.f, stream);
+}
+
 int kbn_cg_step(kbn_plan p, int C, const void *smaps, double lambda, int iters, void *x, void *work,
                 void *stream_) {
     int rc = check_common(p, 1, C, x, smaps, work);

@@ -1,0 +1,147 @@
+"""Gram and regularised-inverse layers (Sec. II-E) on the GPU against the
+FP64 oracle.
+
+Gram operator z = E^H E x: the forward and dL/dx are two NUFFTs in a row,
+so they are compared at twice the single-NUFFT tolerance (4e-5, relative
+L2); dL/domega is four NUFFT-sized products (two Jacobian NUFFTs, two
+forward NUFFTs) and is compared at the Jacobian tolerance 1e-4.
+
+Inverse z = (E^H E + lam I)^{-1} x by CG on the GPU against dense FP64
+solves of the exact normal matrix.  The problems have condition number
+~35-40 (uniform random sampling, M = 3 n), 50 CG iterations take the
+Krylov error below 1e-6, and what remains is the Gram operator's error
+amplified by the condition number: 40 x 4e-5 = 1.6e-3, so 2e-3 for z,
+dL/dx and dL/domega.  A sign error in dL/domega, or a dropped term of the
+Gram gradient, moves it by O(1).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import inverse as inv_ref
+from oracle import ndft
+from paper_2111_02912_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_GRAM = 4e-5
+TOL_JAC = 1e-4
+TOL_INV = 2e-3
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch.device("cuda", 0)
+
+
+def _c(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex64)).to(dev)
+
+
+def _f(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+GRAM_CASES = [((48, 40), 2, 3), ((300,), 2, 1), ((12, 10, 14), 1, 2), ((37, 29), 1, 4)]
+
+
+@pytest.mark.parametrize("N,B,C", GRAM_CASES)
+def test_gram_forward_and_gradients(N, B, C, dev):
+    from paper_2111_02912_amd.autograd import gram
+    from paper_2111_02912_amd.nufft import KbNufft
+    _say(f"gram N={N} B={B} C={C}")
+    D = len(N)
+    if D == 2:
+        om = W.radial_2d(24, 2 * max(N), jitter=np.pi / max(N), seed=6101)
+    elif D == 1:
+        om = W.uniform_random(700, 1, seed=6101)
+    else:
+        om = W.kooshball_3d(64, 2 * max(N))
+    om = om.astype(np.float32)
+    x = W.complex_normal((B,) + tuple(N), 6102).astype(np.complex64)
+    g = W.complex_normal((B,) + tuple(N), 6103).astype(np.complex64)
+    smaps = W.sense_maps(C, N).astype(np.complex64) if C > 1 else None
+
+    plan = KbNufft(N, device=dev)
+    xt = _c(x, dev).requires_grad_(True)
+    omt = _f(om, dev).requires_grad_(True)
+    st = _c(smaps, dev) if smaps is not None else None
+    z = gram(xt, omt, plan, st)
+    z.backward(_c(g, dev))
+
+    z_ex = ndft.gram(om, x, N, smaps)
+    dom_ex, dx_ex = ndft.gram_vjp(om, x, g, N, smaps)
+    ez = ndft.rel_l2(_np(z), z_ex)
+    ex = ndft.rel_l2(_np(xt.grad), dx_ex)
+    eo = ndft.rel_l2(_np(omt.grad), dom_ex)
+    _say(f"  rel z {ez:.2e}  dx {ex:.2e}  domega {eo:.2e}")
+    assert ez < TOL_GRAM
+    assert ex < TOL_GRAM
+    assert eo < TOL_JAC
+
+
+INV_CASES = [((16, 14), 3), ((12, 10, 6), 2), ((15, 17), 1)]
+
+
+@pytest.mark.parametrize("N,C", INV_CASES)
+def test_inverse_forward_and_gradients(N, C, dev):
+    from paper_2111_02912_amd.autograd import inverse
+    from paper_2111_02912_amd.nufft import KbNufft
+    _say(f"inverse N={N} C={C}")
+    n = int(np.prod(N))
+    om = W.uniform_random(3 * n, len(N), seed=6201).astype(np.float32)
+    B = 2
+    x = W.complex_normal((B,) + tuple(N), 6202).astype(np.complex64)
+    g = W.complex_normal((B,) + tuple(N), 6203).astype(np.complex64)
+    smaps = W.sense_maps(C, N).astype(np.complex64) if C > 1 else None
+    lam = 1e-3
+
+    plan = KbNufft(N, device=dev)
+    xt = _c(x, dev).requires_grad_(True)
+    omt = _f(om, dev).requires_grad_(True)
+    st = _c(smaps, dev) if smaps is not None else None
+    z = inverse(xt, omt, plan, st, lam=lam, iters=50)
+    z.backward(_c(g, dev))
+
+    z_ex = inv_ref.solve(om, x, N, smaps, lam)
+    dom_ex, dx_ex = inv_ref.inverse_vjp(om, x, g, N, smaps, lam)
+    ez = ndft.rel_l2(_np(z), z_ex)
+    ex = ndft.rel_l2(_np(xt.grad), dx_ex)
+    eo = ndft.rel_l2(_np(omt.grad), dom_ex)
+    _say(f"  rel z {ez:.2e}  dx {ex:.2e}  domega {eo:.2e}")
+    assert ez < TOL_INV
+    assert ex < TOL_INV
+    assert eo < TOL_INV
+
+
+def test_image_rhs_cg_matches_data_rhs(dev):
+    """CG started from an image right-hand side b = E^H y gives the same
+    iterate as CG started from the data y (same kernels after the start)."""
+    from paper_2111_02912_amd.cg import CgSense
+    from paper_2111_02912_amd.nufft import KbNufft
+    N, C = (40, 36), 4
+    om = W.radial_2d(64, 80, jitter=np.pi / 40, seed=6301).astype(np.float32)
+    smaps = _c(W.sense_maps(C, N), dev)
+    y = _c(W.complex_normal((C, om.shape[0]), 6302), dev)
+    plan = KbNufft(N, device=dev)
+    plan.set_points(_f(om, dev))
+    b = plan.adjoint(y[None], smaps)[0]
+    a = CgSense(plan, C).begin(y, smaps).step(10)
+    r = CgSense(plan, C).begin_rhs(b, smaps).step(10)
+    torch.cuda.synchronize()
+    e = float((a.x - r.x).abs().max() / a.x.abs().max())
+    _say(f"  data-rhs vs image-rhs max rel {e:.2e}")
+    assert e < 1e-5
