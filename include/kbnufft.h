@@ -60,6 +60,8 @@ extern "C" {
 
 #define KBN_OP_FORWARD 0             /* the operator y = E x                    */
 #define KBN_OP_ADJOINT 1             /* the operator x = E^H y                  */
+#define KBN_REG_IDENTITY 0           /* CG regulariser T = I (CG-SENSE)         */
+#define KBN_REG_FINITE_DIFF 1        /* T = first differences per axis (QPLS)   */
 
 typedef struct kbn_plan_s *kbn_plan;
 
@@ -225,12 +227,15 @@ const char *kbn_timing_name(int cls);
 int kbn_plan_destroy(kbn_plan p);
 
 /*
- * CG-SENSE reconstruction (Sec. IV-B: the quadratic reconstruction
- * x = (E^H E + lambda T^H T)^{-1} E^H y with T = I, solved by conjugate
- * gradients; residual ||r|| / ||b|| as in Sec. IV-A), one image, C coils.
+ * CG-SENSE / QPLS reconstruction (Sec. IV-B: the quadratic reconstruction
+ * x = (E^H E + lambda T^H T)^{-1} E^H y solved by conjugate gradients;
+ * residual ||r|| / ||b|| as in Sec. IV-A), one image, C coils.
+ * reg selects T: KBN_REG_IDENTITY (T = I, CG-SENSE) or KBN_REG_FINITE_DIFF
+ * (QPLS: T stacks the first differences (T_d x)_j = x_{j+e_d} - x_j along
+ * every image axis d, for j_d < N_d - 1; no wrap-around at the edges).
  *
  * Plain CG from x0 = 0 (Shewchuk): r = b = E^H y, p = r; per iteration
- * q = E^H E p + lambda p, alpha = r'r / p'q, x += alpha p, r -= alpha q,
+ * q = E^H E p + lambda T^H T p, alpha = r'r / p'q, x += alpha p, r -= alpha q,
  * beta = r'r(new) / r'r(old), p = r + beta p.  Exactly `iters` iterations
  * (no early stop); if p'q or r'r is not positive the step is zero.  Image
  * vectors and arithmetic are FP32; inner products are summed in FP64 with
@@ -247,16 +252,16 @@ int kbn_plan_destroy(kbn_plan p);
  * x: c64 [N..]; y: c64 [C][M]; smaps: c64 [C][N..] or NULL (C = 1).
  * The same plan's points must stay set between begin and the last step.
  * Errors: INVALID_ARG (null pointers, C < 1, iters < 0, lambda < 0 or
- * not finite), NO_POINTS, OOM/HIP (workspace growth, launches).
+ * not finite, unknown reg), NO_POINTS, OOM/HIP (workspace growth, launches).
  */
 int kbn_cg_work_bytes(kbn_plan p, int C, int64_t *bytes);
 int kbn_cg_begin(kbn_plan p, int C, const void *smaps, const void *y, void *x, void *work,
                  void *stream);
-int kbn_cg_step(kbn_plan p, int C, const void *smaps, double lambda, int iters, void *x,
+int kbn_cg_step(kbn_plan p, int C, const void *smaps, double lambda, int reg, int iters, void *x,
                 void *work, void *stream);
 
 /*
- * Start a solve of (E^H E + lambda I) x = b for an image right-hand side b
+ * Start a solve of (E^H E + lambda T^H T) x = b for an image right-hand side b
  * (c64 [N..], device) instead of b = E^H y: x = 0, r = p = b.  Used to apply
  * the regularised inverse of Sec. II-E to an image (and to its upstream
  * gradient).  Continue with kbn_cg_step.  Errors as kbn_cg_begin.

@@ -20,6 +20,8 @@ KBN_ERR_NONFINITE = -5
 KBN_ERR_NO_POINTS = -6
 KBN_OP_FORWARD = 0
 KBN_OP_ADJOINT = 1
+KBN_REG_IDENTITY = 0
+KBN_REG_FINITE_DIFF = 1
 KBN_TASK_FORWARD = 0
 KBN_TASK_ADJOINT = 1
 KBN_TASK_JAC_OMEGA_FWD = 2
@@ -111,7 +113,7 @@ def lib():
     L.kbn_batch_destroy.argtypes = [vp]
     L.kbn_cg_work_bytes.argtypes = [vp, ci, ctypes.POINTER(i64)]
     L.kbn_cg_begin.argtypes = [vp, ci, vp, vp, vp, vp, vp]
-    L.kbn_cg_step.argtypes = [vp, ci, vp, ctypes.c_double, ci, vp, vp, vp]
+    L.kbn_cg_step.argtypes = [vp, ci, vp, ctypes.c_double, ci, ci, vp, vp, vp]
     L.kbn_cg_begin_image.argtypes = [vp, ci, vp, vp, vp, vp]
     for name in EXPORTS:
         if name not in ("kbn_strerror", "kbn_last_error", "kbn_timing_name"):

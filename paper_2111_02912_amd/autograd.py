@@ -169,31 +169,29 @@ class _GramOp(torch.autograd.Function):
         return gx, gom, None, None
 
 
-def _cg_solve(plan: KbNufft, x, smaps, lam: float, iters: int):
-    """F^{-1} x image by image with the library's CG (F = E^H E + lam I),
-    starting from the right-hand side x itself (CG-SENSE in the library takes
-    E^H y; here the right-hand side is an image, so y is not formed: the
-    solve runs on E^H E + lam I with b = x)."""
+def _cg_solve(plan: KbNufft, x, smaps, lam: float, iters: int, reg: str):
+    """F^{-1} x image by image with the library's CG (F = E^H E + lam T^H T),
+    started from the image right-hand side b = x."""
     from .cg import CgSense
     C = 1 if smaps is None else int(smaps.shape[0])
     out = torch.empty_like(x)
     s = CgSense(plan, C)
     for b in range(x.shape[0]):
-        s.begin_rhs(x[b], smaps).step(iters, lam)
+        s.begin_rhs(x[b], smaps).step(iters, lam, reg)
         out[b].copy_(s.x)
     return out
 
 
 class _InverseOp(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, x, omega, smaps, plan, lam, iters):
+    def forward(ctx, x, omega, smaps, plan, lam, iters, reg):
         _no_map_grad(smaps)
         plan.ensure_points(omega)
         xb = x.reshape((-1,) + plan.N).contiguous()
-        z = _cg_solve(plan, xb, smaps, lam, iters)
+        z = _cg_solve(plan, xb, smaps, lam, iters, reg)
         ctx.plan = plan
         ctx.xshape = x.shape
-        ctx.lam, ctx.iters = lam, iters
+        ctx.lam, ctx.iters, ctx.reg = lam, iters, reg
         ctx.save_for_backward(z, omega, smaps)
         return z.reshape(x.shape)
 
@@ -203,13 +201,13 @@ class _InverseOp(torch.autograd.Function):
         z, omega, smaps = ctx.saved_tensors
         plan = ctx.plan
         plan.ensure_points(omega)
-        w = _cg_solve(plan, g.contiguous().reshape(z.shape), smaps, ctx.lam, ctx.iters)
+        w = _cg_solve(plan, g.contiguous().reshape(z.shape), smaps, ctx.lam, ctx.iters, ctx.reg)
         gom = None
         if ctx.needs_input_grad[1]:
             _, gom = _gram_vjp(plan, z, w, smaps, False, True)
             gom = -gom
         gx = w.reshape(ctx.xshape) if ctx.needs_input_grad[0] else None
-        return gx, gom, None, None, None, None
+        return gx, gom, None, None, None, None, None
 
 
 def gram(x: torch.Tensor, omega: torch.Tensor, plan: KbNufft,
@@ -220,8 +218,12 @@ def gram(x: torch.Tensor, omega: torch.Tensor, plan: KbNufft,
 
 def inverse(x: torch.Tensor, omega: torch.Tensor, plan: KbNufft,
             smaps: Optional[torch.Tensor] = None, lam: float = 1e-3,
-            iters: int = 20) -> torch.Tensor:
-    """z = (E^H E + lam I)^{-1} x by `iters` CG iterations per image; the
-    backward solves with the same operator (the paper's approach of treating
-    the solve as exact and differentiating the exact inverse)."""
-    return _InverseOp.apply(x, omega, smaps, plan, float(lam), int(iters))
+            iters: int = 20, reg: str = "identity") -> torch.Tensor:
+    """z = (E^H E + lam T^H T)^{-1} x by `iters` CG iterations per image
+    (T = I for reg "identity", first differences along each image axis for
+    "finite_diff"); the backward solves with the same operator (the solve is
+    treated as exact and the exact inverse is differentiated).  Memory does
+    not grow with the number of iterations."""
+    from .cg import reg_code
+    reg_code(reg)
+    return _InverseOp.apply(x, omega, smaps, plan, float(lam), int(iters), reg)

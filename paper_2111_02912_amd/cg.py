@@ -1,7 +1,8 @@
-"""CG-SENSE reconstruction on the GPU (kbn_cg_* of the C ABI).
+"""CG-SENSE and QPLS reconstruction on the GPU (kbn_cg_* of the C ABI).
 
-Solves (E^H E + lambda I) x = E^H y by plain conjugate gradients from x = 0
-(Sec. IV-B, T = I), entirely in the HIP library: this module allocates the
+Solves (E^H E + lambda T^H T) x = E^H y by plain conjugate gradients from
+x = 0 (Sec. IV-B; T = I is CG-SENSE, T = first differences along each image
+axis is QPLS), entirely in the HIP library: this module allocates the
 solver's work buffer and the image with PyTorch and passes pointers.
 """
 from __future__ import annotations
@@ -16,6 +17,13 @@ from ._lib import check
 from .nufft import KbNufft, _ptr, _stream
 
 _SCAL = 8  # leading doubles of the work buffer that hold the CG scalars
+REGS = {"identity": _lib.KBN_REG_IDENTITY, "finite_diff": _lib.KBN_REG_FINITE_DIFF}
+
+
+def reg_code(reg) -> int:
+    if reg not in REGS:
+        raise ValueError(f"reg must be one of {sorted(REGS)}, got {reg!r}")
+    return REGS[reg]
 
 
 class CgSense:
@@ -56,11 +64,12 @@ class CgSense:
                                             _stream(p.device)), "kbn_cg_begin_image")
         return self
 
-    def step(self, iters: int, lam: float = 1e-3):
+    def step(self, iters: int, lam: float = 1e-3, reg: str = "identity"):
+        """Run `iters` more iterations with F = E^H E + lam T^H T."""
         p = self.plan
         s = self._keep[1]
-        check(_lib.lib().kbn_cg_step(p._h, self.C, _ptr(s), float(lam), int(iters), _ptr(self.x),
-                                     _ptr(self.work), _stream(p.device)), "kbn_cg_step")
+        check(_lib.lib().kbn_cg_step(p._h, self.C, _ptr(s), float(lam), reg_code(reg), int(iters),
+                                     _ptr(self.x), _ptr(self.work), _stream(p.device)), "kbn_cg_step")
         return self
 
     def scalars(self) -> torch.Tensor:
@@ -73,8 +82,8 @@ class CgSense:
 
 
 def cg_sense(plan: KbNufft, y: torch.Tensor, smaps: Optional[torch.Tensor] = None,
-             lam: float = 1e-3, iters: int = 10):
+             lam: float = 1e-3, iters: int = 10, reg: str = "identity"):
     """Return (x [*N] complex64, ||r||/||b||) after `iters` CG iterations."""
     C = 1 if smaps is None else int(smaps.shape[0])
-    s = CgSense(plan, C).begin(y, smaps).step(iters, lam)
+    s = CgSense(plan, C).begin(y, smaps).step(iters, lam, reg)
     return s.x, s.residual()

@@ -1,6 +1,7 @@
-// Conjugate-gradient vector kernels for CG-SENSE, (E^H E + lambda I) x = E^H y
-// (Sec. IV-B: CG-SENSE is the quadratic reconstruction with T = I; the
-// residual norm ||r|| / ||b|| of Sec. IV-A).
+// Conjugate-gradient vector kernels for the quadratic reconstruction
+// (E^H E + lambda T^H T) x = b of Sec. IV-B: T = I (CG-SENSE) or T = the
+// first differences along each image axis (QPLS), zero beyond the image
+// edge; residual norm ||r|| / ||b|| of Sec. IV-A.
 //
 // Inner products are reduced deterministically: a fixed grid for a given
 // length, one FP64 partial per block in a fixed tree order, then one block
@@ -53,6 +54,38 @@ __global__ __launch_bounds__(TPB) void k_cg_q(float2 *__restrict__ q, const floa
         qv.y += lam * pv.y;
         q[i] = qv;
         acc += (double)pv.x * qv.x + (double)pv.y * qv.y;
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// q += lambda T^H T p for T = first differences along each axis (the
+// path-graph Laplacian per axis: sum over in-image neighbours of p_i - p_nb),
+// partial Re <p, q>.  Image [n0][n1][n2] row-major.
+__global__ __launch_bounds__(TPB) void k_cg_q_fd(float2 *__restrict__ q, const float2 *__restrict__ p,
+                                                 float lam, int n0, int n1, int n2, int64_t n,
+                                                 double *__restrict__ part) {
+    __shared__ double sh[TPB];
+    const int64_t s0 = (int64_t)n1 * n2;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+        const int i2 = (int)(i % n2);
+        const int64_t t = i / n2;
+        const int i1 = (int)(t % n1);
+        const int i0 = (int)(t / n1);
+        const float2 c = p[i];
+        float lx = 0.f, ly = 0.f;
+        if (i0 > 0) { const float2 v = p[i - s0]; lx += c.x - v.x; ly += c.y - v.y; }
+        if (i0 < n0 - 1) { const float2 v = p[i + s0]; lx += c.x - v.x; ly += c.y - v.y; }
+        if (i1 > 0) { const float2 v = p[i - n2]; lx += c.x - v.x; ly += c.y - v.y; }
+        if (i1 < n1 - 1) { const float2 v = p[i + n2]; lx += c.x - v.x; ly += c.y - v.y; }
+        if (i2 > 0) { const float2 v = p[i - 1]; lx += c.x - v.x; ly += c.y - v.y; }
+        if (i2 < n2 - 1) { const float2 v = p[i + 1]; lx += c.x - v.x; ly += c.y - v.y; }
+        float2 qv = q[i];
+        qv.x += lam * lx;
+        qv.y += lam * ly;
+        q[i] = qv;
+        acc += (double)c.x * qv.x + (double)c.y * qv.y;
     }
     const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -137,7 +170,7 @@ int kbn_cg_nparts(int64_t n) {
 }
 
 hipError_t kbn_launch_cg(int kind, int64_t n, float2 *x, float2 *r, float2 *p, float2 *q, float lam,
-                         double *scal, double *part, hipStream_t s) {
+                         KbnCgImage img, double *scal, double *part, hipStream_t s) {
     const int g = kbn_cg_nparts(n);
     switch (kind) {
     case KBN_CGK_INIT:
@@ -145,7 +178,12 @@ hipError_t kbn_launch_cg(int kind, int64_t n, float2 *x, float2 *r, float2 *p, f
         k_cg_scalars<<<dim3(1), dim3(TPB), 0, s>>>(part, g, scal, 0);
         break;
     case KBN_CGK_Q:
-        k_cg_q<<<dim3(g), dim3(TPB), 0, s>>>(q, p, lam, n, part);
+        if (img.reg == KBN_REG_FINITE_DIFF) {
+            if ((int64_t)img.n0 * img.n1 * img.n2 != n) return hipErrorInvalidValue;
+            k_cg_q_fd<<<dim3(g), dim3(TPB), 0, s>>>(q, p, lam, img.n0, img.n1, img.n2, n, part);
+        } else {
+            k_cg_q<<<dim3(g), dim3(TPB), 0, s>>>(q, p, lam, n, part);
+        }
         k_cg_scalars<<<dim3(1), dim3(TPB), 0, s>>>(part, g, scal, 1);
         break;
     case KBN_CGK_XR:

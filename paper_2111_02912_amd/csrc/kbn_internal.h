@@ -223,9 +223,14 @@ double kbn_internal_cost(kbn_plan p, int B, int C, int jac, int type1);
 #define KBN_CG_MAXPARTS 1024
 // kernel groups of one CG step
 #define KBN_CGK_INIT 0  // x = 0, p = r, rr = bb = |r|^2
-#define KBN_CGK_Q 1     // q += lambda p, alpha = rr / <p, q>
+#define KBN_CGK_Q 1     // q += lambda T^H T p, alpha = rr / <p, q>
 #define KBN_CGK_XR 2    // x += alpha p, r -= alpha q, beta, rr, rel
 #define KBN_CGK_P 3     // p = r + beta p
 int kbn_cg_nparts(int64_t n);
+// image extent for the regulariser stencil, unused axes 1 (row-major, n0 slowest)
+struct KbnCgImage {
+    int reg;  // KBN_REG_IDENTITY or KBN_REG_FINITE_DIFF
+    int n0, n1, n2;
+};
 hipError_t kbn_launch_cg(int kind, int64_t n, float2 *x, float2 *r, float2 *p, float2 *q, float lam,
-                         double *scal, double *part, hipStream_t s);
+                         KbnCgImage img, double *scal, double *part, hipStream_t s);

@@ -862,9 +862,13 @@ static int64_t cg_bytes(kbn_plan p, int C, CgBufs *b, void *work) {
     return total;
 }
 
-static int cg_launch(int kind, int64_t n, float2 *x, const CgBufs &b, float lam, hipStream_t s) {
-    return launched(kbn_launch_cg(kind, n, x, b.r, b.p, b.q, lam, b.scal, b.part, s), "cg vector kernel",
-                    s);
+static int cg_launch(kbn_plan p, int kind, int64_t n, float2 *x, const CgBufs &b, float lam, int reg,
+                     hipStream_t s) {
+    KbnCgImage img{reg, 1, 1, 1};
+    int *ext[3] = {&img.n0, &img.n1, &img.n2};
+    for (int d = 0; d < p->D; ++d) *ext[d] = (int)p->N[d];
+    return launched(kbn_launch_cg(kind, n, x, b.r, b.p, b.q, lam, img, b.scal, b.part, s),
+                    "cg vector kernel", s);
 }
 
 int kbn_cg_work_bytes(kbn_plan p, int C, int64_t *bytes) {
@@ -888,7 +892,7 @@ int kbn_cg_begin(kbn_plan p, int C, const void *smaps, const void *y, void *x, v
     // r = b = E^H y (x0 = 0), p = r
     rc = run_type1(p, 1, C, (const float2 *)y, (const float2 *)smaps, b.r, stream);
     if (rc != KBN_OK) return rc;
-    return cg_launch(KBN_CGK_INIT, npix, (float2 *)x, b, 0.f, stream);
+    return cg_launch(p, KBN_CGK_INIT, npix, (float2 *)x, b, 0.f, KBN_REG_IDENTITY, stream);
 }
 
 int kbn_cg_begin_image(kbn_plan p, int C, const void *b, void *x, void *work, void *stream_) {
@@ -903,23 +907,25 @@ int kbn_cg_begin_image(kbn_plan p, int C, const void *b, void *x, void *work, vo
     for (int d = 0; d < p->D; ++d) npix *= p->N[d];
     // r = b (x0 = 0), p = r
     KBN_HIP(hipMemcpyAsync(cb.r, b, sizeof(float2) * npix, hipMemcpyDeviceToDevice, stream));
-    return cg_launch(KBN_CGK_INIT, npix, (float2 *)x, cb, 0.f, stream);
+    return cg_launch(p, KBN_CGK_INIT, npix, (float2 *)x, cb, 0.f, KBN_REG_IDENTITY, stream);
 }
 
-int kbn_cg_step(kbn_plan p, int C, const void *smaps, double lambda, int iters, void *x, void *work,
-                void *stream_) {
+int kbn_cg_step(kbn_plan p, int C, const void *smaps, double lambda, int reg, int iters, void *x,
+                void *work, void *stream_) {
     int rc = check_common(p, 1, C, x, smaps, work);
     if (rc != KBN_OK) return rc;
     if (!work) return fail(KBN_ERR_INVALID_ARG, "null work buffer");
     if (iters < 0) return fail(KBN_ERR_INVALID_ARG, "iters must be >= 0");
     if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(KBN_ERR_INVALID_ARG, "lambda must be finite and >= 0");
+    if (reg != KBN_REG_IDENTITY && reg != KBN_REG_FINITE_DIFF)
+        return fail(KBN_ERR_INVALID_ARG, "reg must be KBN_REG_IDENTITY or KBN_REG_FINITE_DIFF");
     hipStream_t stream = (hipStream_t)stream_;
     CgBufs b;
     cg_bytes(p, C, &b, work);
     int64_t npix = 1;
     for (int d = 0; d < p->D; ++d) npix *= p->N[d];
     for (int it = 0; it < iters; ++it) {
-        // q = E^H E p (+ lambda p in the vector kernel)
+        // q = E^H E p (+ lambda T^H T p in the vector kernel)
         if (p->M > 0) {
             rc = run_type2(p, 1, C, 1, 0, b.p, (const float2 *)smaps, 0, b.ytmp, nullptr, nullptr, 0,
                            stream);
@@ -927,9 +933,9 @@ int kbn_cg_step(kbn_plan p, int C, const void *smaps, double lambda, int iters, 
         }
         rc = run_type1(p, 1, C, b.ytmp, (const float2 *)smaps, b.q, stream);
         if (rc != KBN_OK) return rc;
-        rc = cg_launch(KBN_CGK_Q, npix, (float2 *)x, b, (float)lambda, stream);
-        if (rc == KBN_OK) rc = cg_launch(KBN_CGK_XR, npix, (float2 *)x, b, 0.f, stream);
-        if (rc == KBN_OK) rc = cg_launch(KBN_CGK_P, npix, (float2 *)x, b, 0.f, stream);
+        rc = cg_launch(p, KBN_CGK_Q, npix, (float2 *)x, b, (float)lambda, reg, stream);
+        if (rc == KBN_OK) rc = cg_launch(p, KBN_CGK_XR, npix, (float2 *)x, b, 0.f, reg, stream);
+        if (rc == KBN_OK) rc = cg_launch(p, KBN_CGK_P, npix, (float2 *)x, b, 0.f, reg, stream);
         if (rc != KBN_OK) return rc;
     }
     return KBN_OK;

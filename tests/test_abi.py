@@ -22,6 +22,15 @@ def test_header_and_binding_agree():
     assert declared_symbols() == sorted(_lib.EXPORTS)
 
 
+def test_header_constants_match_binding():
+    inc = os.path.join(ROOT, "include")
+    src = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
+    consts = re.findall(r"#define\s+(KBN_[A-Z_0-9]+)\s+\(?(-?\d+)\)?", src)
+    assert len(consts) >= 15
+    for name, val in consts:
+        assert getattr(_lib, name) == int(val), name
+
+
 def test_library_exports_every_symbol():
     L = ctypes.CDLL(_lib.LIB_PATH)
     for name in declared_symbols():

@@ -6,7 +6,8 @@ so they are compared at twice the single-NUFFT tolerance (4e-5, relative
 L2); dL/domega is four NUFFT-sized products (two Jacobian NUFFTs, two
 forward NUFFTs) and is compared at the Jacobian tolerance 1e-4.
 
-Inverse z = (E^H E + lam I)^{-1} x by CG on the GPU against dense FP64
+Inverse z = (E^H E + lam T^H T)^{-1} x (T = I, or first differences along
+each axis as in QPLS) by CG on the GPU against dense FP64
 solves of the exact normal matrix.  The problems have condition number
 ~35-40 (uniform random sampling, M = 3 n), 50 CG iterations take the
 Krylov error below 1e-6, and what remains is the Gram operator's error
@@ -93,31 +94,34 @@ def test_gram_forward_and_gradients(N, B, C, dev):
     assert eo < TOL_JAC
 
 
-INV_CASES = [((16, 14), 3), ((12, 10, 6), 2), ((15, 17), 1)]
+INV_CASES = [((16, 14), 3, "identity"), ((12, 10, 6), 2, "identity"), ((15, 17), 1, "identity"),
+             ((16, 14), 3, "finite_diff"), ((12, 10, 6), 2, "finite_diff")]
 
 
-@pytest.mark.parametrize("N,C", INV_CASES)
-def test_inverse_forward_and_gradients(N, C, dev):
+@pytest.mark.parametrize("N,C,reg", INV_CASES)
+def test_inverse_forward_and_gradients(N, C, reg, dev):
+    """T = I with lambda 1e-3, and QPLS (T = first differences) with
+    lambda 20, which changes z by ~27% against T = I at condition ~20-25."""
     from paper_2111_02912_amd.autograd import inverse
     from paper_2111_02912_amd.nufft import KbNufft
-    _say(f"inverse N={N} C={C}")
+    _say(f"inverse N={N} C={C} reg={reg}")
     n = int(np.prod(N))
     om = W.uniform_random(3 * n, len(N), seed=6201).astype(np.float32)
     B = 2
     x = W.complex_normal((B,) + tuple(N), 6202).astype(np.complex64)
     g = W.complex_normal((B,) + tuple(N), 6203).astype(np.complex64)
     smaps = W.sense_maps(C, N).astype(np.complex64) if C > 1 else None
-    lam = 1e-3
+    lam = 1e-3 if reg == "identity" else 20.0
 
     plan = KbNufft(N, device=dev)
     xt = _c(x, dev).requires_grad_(True)
     omt = _f(om, dev).requires_grad_(True)
     st = _c(smaps, dev) if smaps is not None else None
-    z = inverse(xt, omt, plan, st, lam=lam, iters=50)
+    z = inverse(xt, omt, plan, st, lam=lam, iters=50, reg=reg)
     z.backward(_c(g, dev))
 
-    z_ex = inv_ref.solve(om, x, N, smaps, lam)
-    dom_ex, dx_ex = inv_ref.inverse_vjp(om, x, g, N, smaps, lam)
+    z_ex = inv_ref.solve(om, x, N, smaps, lam, reg)
+    dom_ex, dx_ex = inv_ref.inverse_vjp(om, x, g, N, smaps, lam, reg)
     ez = ndft.rel_l2(_np(z), z_ex)
     ex = ndft.rel_l2(_np(xt.grad), dx_ex)
     eo = ndft.rel_l2(_np(omt.grad), dom_ex)
