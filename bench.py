@@ -26,9 +26,15 @@ Other workloads (one JSON line each, not the default):
                      arriving as a Poisson process at 50/s: 80% 2D spiral
                      (N 192..384, M 20k..60k), 20% 96^3 kooshball; latency
                      p50/p99 of a continuous-batching server.
+  --workload jacobian  the Gram and PSD-inverse Jacobian test case of
+                     Sec. IV-A (time and memory tables): gradients of
+                     ||f(x)||^2 w.r.t. omega and x for f = E^H E and
+                     f = (E^H E + lambda I)^{-1} (20 CG iterations), 8 coils,
+                     one radial spoke, images 40^2 and 400^2, plus the
+                     memory case 200 x 200 x 100.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B]
-                       [--workload step|batch|train|serve]
+                       [--workload step|batch|train|serve|jacobian]
 """
 from __future__ import annotations
 
@@ -287,6 +293,84 @@ def bench_train(args):
     print(json.dumps(out), flush=True)
 
 
+# Sec. IV-A time and memory tables (RTX 2080 Ti, seconds; MB of
+# torch.cuda.max_memory_allocated), the proposed method's column
+PAPER_JAC_S = {"gram_40": 0.1, "gram_400": 0.2, "inverse_40": 0.9, "inverse_400": 2.5}
+PAPER_JAC_MB = {"gram_40": 2.8, "gram_400": 267.5, "inverse_40": 2.9, "inverse_400": 272.0,
+                "gram_3d": 10.1e3, "inverse_3d": 10.8e3}
+
+
+def bench_jacobian(args):
+    """Gram and PSD-inverse Jacobian test case: one step = index pass, f(x),
+    loss ||f(x)||^2 and its backward to omega and x."""
+    import numpy as np
+    import torch
+
+    from paper_2111_02912_amd import workloads as W
+    from paper_2111_02912_amd.autograd import gram, inverse
+    from paper_2111_02912_amd.nufft import KbNufft
+
+    dev = torch.device("cuda", 0)
+    C = 8
+    cases = {}
+    for size in (40, 400, "3d"):
+        if size == "3d":
+            N = (200, 200, 100)
+            om = W.kooshball_3d(1, 400)
+        else:
+            N = (size, size)
+            om = W.radial_2d(1, 2 * size)  # one spoke through the centre, 2N samples
+        smaps = W.sense_maps(C, N).astype(np.complex64)
+        x = W.complex_normal((1,) + N, 7001).astype(np.complex64)
+        for op in ("gram", "inverse"):
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+            torch.cuda.reset_peak_memory_stats()
+            plan = KbNufft(N, device=dev)
+            xt = torch.from_numpy(x).to(dev).requires_grad_(True)
+            omt = torch.from_numpy(om).to(dev).requires_grad_(True)
+            st = torch.from_numpy(smaps).to(dev)
+
+            def step():
+                xt.grad = None
+                omt.grad = None
+                plan.set_points(omt.detach())
+                plan.ensure_points(omt)
+                if op == "gram":
+                    z = gram(xt, omt, plan, st)
+                else:
+                    z = inverse(xt, omt, plan, st, lam=1e-3, iters=20)
+                loss = torch.view_as_real(z).pow(2).sum()
+                loss.backward()
+
+            steps = args.steps if size != "3d" else max(1, min(args.steps, 5))
+            ms = _wall_ms(step, steps, max(1, min(args.warmup, 2)))
+            torch.cuda.synchronize()
+            key = f"{op}_{size}"
+            peak = torch.cuda.max_memory_allocated(dev)
+            ws = plan.info()["workspace_bytes"]
+            cases[key] = {"N": list(N), "M": int(om.shape[0]), "coils": C, "s": ms * 1e-3,
+                          "torch_peak_MB": peak / 2 ** 20, "plan_workspace_MB": ws / 2 ** 20,
+                          "total_MB": (peak + ws) / 2 ** 20,
+                          "paper_s": PAPER_JAC_S.get(key), "paper_MB": PAPER_JAC_MB.get(key)}
+            plan.close()
+            del xt, omt, st
+    value = cases["inverse_400"]["s"]
+    out = {
+        "metric": "PSD-inverse Jacobian test case time (s): gradients of ||f(x)||^2 w.r.t. omega and x",
+        "value": value, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": value * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": value / PAPER_JAC_S["inverse_400"], "dtype": "f32", "data": "synthetic",
+        "config": {"workload": ("Gram / PSD-inverse Jacobian test case: 400x400 image (also 40x40 and "
+                                "200x200x100), 8 coils, one radial spoke of 2N samples, "
+                                "f = (E^H E + 1e-3 I)^{-1} by 20 CG iterations forward and backward"),
+                   "images": "complex64 N(0,1) stand-in for the phantom crop with random phase"},
+        "baseline_hardware": "paper: RTX 2080 Ti (context only)",
+        "cases": cases,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def serve_pool(dev, n2d, n3d, coils=8, seed=5001):
     """Resident problems: square 2D spirals and 96^3 kooshballs with
     Gaussian-bump maps and noiseless data y = E x_true."""
@@ -404,7 +488,8 @@ def main():
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-images", type=int, default=2)
-    ap.add_argument("--workload", choices=("step", "batch", "train", "serve"), default="step")
+    ap.add_argument("--workload", choices=("step", "batch", "train", "serve", "jacobian"),
+                    default="step")
     ap.add_argument("--requests", type=int, default=2000, help="serve workload: measured requests")
     ap.add_argument("--warm-requests", type=int, default=100, help="serve workload: unmeasured first requests")
     ap.add_argument("--rate", type=float, default=50.0, help="serve workload: arrivals per second")
@@ -432,6 +517,8 @@ def main():
         return bench_serve(args)
     if args.workload == "train":
         return bench_train(args)
+    if args.workload == "jacobian":
+        return bench_jacobian(args)
 
     import numpy as np
     import torch

@@ -353,6 +353,19 @@ int64_t img_rows(kbn_plan p) {  // product of the leading image axes
     return r;
 }
 
+// Work split under the workspace cap: whole images (all coils) per chunk
+// while one image fits, else one image at a time in runs of coils.
+struct Chunks {
+    int64_t bc;  // images per chunk
+    int cc;      // coils per chunk (C unless one image does not fit)
+};
+
+static Chunks split_chunks(int64_t B, int C, int64_t per_coil, int64_t max_ws) {
+    if ((int64_t)C * per_coil <= max_ws)
+        return {std::max<int64_t>(1, std::min<int64_t>(B, max_ws / ((int64_t)C * per_coil))), C};
+    return {1, (int)std::max<int64_t>(1, std::min<int64_t>(C, max_ws / per_coil))};
+}
+
 // Forward-type pipeline: scaling (+ coil map, + coordinate weight), FFT
 // passes, then gather.  mode 0 writes y; mode 1 folds the omega-Jacobian.
 int run_type2(kbn_plan p, int B, int C, int nw, int weighted, const float2 *x,
@@ -360,35 +373,38 @@ int run_type2(kbn_plan p, int B, int C, int nw, int weighted, const float2 *x,
               int accumulate, hipStream_t stream) {
     const int D = p->D;
     const int64_t gsz = p->gsize();
-    const int64_t per_img = (int64_t)C * nw * gsz * (int64_t)sizeof(float2) * 2;
-    int64_t bc = std::max<int64_t>(1, std::min<int64_t>(B, p->max_ws / per_img));
+    const int64_t per_coil = (int64_t)nw * gsz * (int64_t)sizeof(float2) * 2;
+    const Chunks ck = split_chunks(B, C, per_coil, p->max_ws);
+    const int64_t units = ck.bc * ck.cc;  // image-coil pairs of the largest chunk
     const KbnGeom geom0 = p->geom();
-    // per-group partial omega-gradients (mode 1), sized for the largest chunk
-    // channel groups of any chunk are at most min(images x coils of the
-    // largest chunk, ceil(2048 / blocks)) (a smaller last chunk can have
-    // more groups than the largest one)
-    const int64_t blocks0 = kbn_gather_shape(geom0, p->M, (int)(bc * C * nw), nw).blocks;
-    const int64_t groups_max = std::max<int64_t>(1, std::min<int64_t>(bc * C, (2048 + blocks0 - 1) / blocks0));
+    // per-group partial omega-gradients (mode 1): the gather's point blocks
+    // do not depend on the channel count, and a chunk's channel groups are at
+    // most min(its image-coil pairs, ceil(2048 / blocks))
+    const int64_t blocks0 = kbn_gather_shape(geom0, p->M, (int)(units * nw), nw).blocks;
+    const int64_t groups_max = std::max<int64_t>(1, std::min<int64_t>(units, (2048 + blocks0 - 1) / blocks0));
     const int64_t part_bytes = mode == 1 ? (int64_t)groups_max * p->M * D * (int64_t)sizeof(float) : 0;
-    int rc = ensure_ws(p, bc * per_img + part_bytes, stream);
+    int rc = ensure_ws(p, units * per_coil + part_bytes, stream);
     if (rc != KBN_OK) return rc;
     float2 *bufA = p->ws;
-    float2 *bufB = p->ws + bc * C * nw * gsz;
-    float *part = (float *)(p->ws + 2 * bc * C * nw * gsz);
+    float2 *bufB = p->ws + units * nw * gsz;
+    float *part = (float *)(p->ws + 2 * units * nw * gsz);
     const int64_t R0 = img_rows(p);
     const int Nl = p->N[D - 1];
     const KbnGeom geom = p->geom();
-    for (int64_t b0 = 0; b0 < B; b0 += bc) {
-        const int64_t nb = std::min<int64_t>(bc, B - b0);
-        const int64_t nch = nb * C * nw;
+    for (int64_t b0 = 0; b0 < B; b0 += ck.bc)
+    for (int c0 = 0; c0 < C; c0 += ck.cc) {
+        const int64_t nb = std::min<int64_t>(ck.bc, B - b0);
+        const int ncc = std::min(ck.cc, C - c0);
+        const int64_t nch = nb * ncc * nw;
+        const int64_t k0 = (b0 * C + c0) * p->M;  // k-space offset of the chunk
         KbnFirstPassArgs fa;
         fa.x = x + b0 * R0 * Nl;
-        fa.smaps = smaps;
+        fa.smaps = smaps ? smaps + (int64_t)c0 * R0 * Nl : nullptr;
         fa.out = bufA;
         fa.nlines = nch * R0;
         fa.R0 = (int)R0;
         fa.Nl = Nl;
-        fa.C = C;
+        fa.C = ncc;
         fa.nw = nw;
         fa.weighted = weighted;
         fa.D = D;
@@ -429,7 +445,7 @@ int run_type2(kbn_plan p, int B, int C, int nw, int weighted, const float2 *x,
         ga.grid = cur;
         ga.gsize = gsz;
         ga.nch = (int)nch;
-        ga.C = C;
+        ga.C = ncc;
         ga.nw = nw;
         ga.M = p->M;
         ga.order = p->order;
@@ -438,11 +454,11 @@ int run_type2(kbn_plan p, int B, int C, int nw, int weighted, const float2 *x,
         ga.toff = p->toff;
         ga.subs = p->subs;
         ga.nsub = p->nsub;
-        ga.y = mode == 0 ? y + b0 * C * p->M : nullptr;
-        ga.v = mode == 1 ? v + b0 * C * p->M : nullptr;
+        ga.y = mode == 0 ? y + k0 : nullptr;
+        ga.v = mode == 1 ? v + k0 : nullptr;
         ga.domega = dom;
         ga.part = part;
-        ga.accumulate = (accumulate || b0 > 0) ? 1 : 0;
+        ga.accumulate = (accumulate || b0 > 0 || c0 > 0) ? 1 : 0;
         KBN_LAUNCH(mode == 0 ? KBN_CLASS_GATHER : KBN_CLASS_GATHER_JAC, kbn_launch_gather(geom, ga, mode, stream), "gather");
     }
     return KBN_OK;
@@ -456,24 +472,27 @@ int run_type1(kbn_plan p, int B, int C, const float2 *y, const float2 *smaps, fl
     const int64_t gsz = p->gsize();
     int64_t tcells = 1;
     for (int d = 0; d < D; ++d) tcells *= p->To[d];
-    // per image: two grids, k-space in tile order, partial tiles of split owner tiles
-    const int64_t per_img =
-        (int64_t)C * (gsz * 2 + p->M + (int64_t)p->smax * tcells) * (int64_t)sizeof(float2);
-    int64_t bc = std::max<int64_t>(1, std::min<int64_t>(B, p->max_ws / per_img));
-    int rc = ensure_ws(p, bc * per_img, stream);
+    // per image-coil pair: two grids, k-space in tile order, partial tiles
+    // of split owner tiles
+    const int64_t per_coil = (gsz * 2 + p->M + (int64_t)p->smax * tcells) * (int64_t)sizeof(float2);
+    const Chunks ck = split_chunks(B, C, per_coil, p->max_ws);
+    const int64_t units = ck.bc * ck.cc;
+    int rc = ensure_ws(p, units * per_coil, stream);
     if (rc != KBN_OK) return rc;
     float2 *bufA = p->ws;
-    float2 *bufB = p->ws + bc * C * gsz;
-    float2 *bufY = p->ws + 2 * bc * C * gsz;
-    float2 *bufP = bufY + bc * C * p->M;
+    float2 *bufB = p->ws + units * gsz;
+    float2 *bufY = p->ws + 2 * units * gsz;
+    float2 *bufP = bufY + units * p->M;
     const int64_t R0 = img_rows(p);
     const int Nl = p->N[D - 1];
     const KbnGeom geom = p->geom();
-    for (int64_t b0 = 0; b0 < B; b0 += bc) {
-        const int64_t nb = std::min<int64_t>(bc, B - b0);
-        const int64_t nch = nb * C;
+    for (int64_t b0 = 0; b0 < B; b0 += ck.bc)
+    for (int c0 = 0; c0 < C; c0 += ck.cc) {
+        const int64_t nb = std::min<int64_t>(ck.bc, B - b0);
+        const int ncc = std::min(ck.cc, C - c0);
+        const int64_t nch = nb * ncc;
         KbnSpreadArgs sa;
-        sa.y = y + b0 * C * p->M;
+        sa.y = y + (b0 * C + c0) * p->M;
         sa.ys = bufY;
         sa.grid = bufA;
         sa.gsize = gsz;
@@ -520,13 +539,13 @@ int run_type1(kbn_plan p, int B, int C, const float2 *y, const float2 *smaps, fl
         }
         KbnLastAdjArgs la;
         la.in = cur;
-        la.smaps = smaps;
+        la.smaps = smaps ? smaps + (int64_t)c0 * R0 * Nl : nullptr;
         la.x = x + b0 * R0 * Nl;
         la.nlines = nb * R0;
         la.R0 = (int)R0;
         la.Nl = Nl;
-        la.C = C;
-        la.accumulate = 0;
+        la.C = ncc;
+        la.accumulate = c0 > 0 ? 1 : 0;  // later coil runs add to the image
         la.D = D;
         for (int d = 0; d < KBN_MAX_D; ++d) {
             la.N[d] = p->N[d];

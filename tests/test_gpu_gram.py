@@ -149,3 +149,32 @@ def test_image_rhs_cg_matches_data_rhs(dev):
     e = float((a.x - r.x).abs().max() / a.x.abs().max())
     _say(f"  data-rhs vs image-rhs max rel {e:.2e}")
     assert e < 1e-5
+
+
+def test_inverse_memory_constant_in_iterations(dev):
+    """The inverse layer's memory does not grow with the number of CG
+    iterations (the backward solves again instead of storing iterates):
+    the peak of PyTorch's allocations and the plan's workspace are the same
+    for 5 and for 60 iterations."""
+    from paper_2111_02912_amd.autograd import inverse
+    from paper_2111_02912_amd.nufft import KbNufft
+    N, C = (64, 64), 4
+    om = W.radial_2d(32, 128, seed=6401).astype(np.float32)
+    smaps = _c(W.sense_maps(C, N), dev)
+    x = W.complex_normal((1,) + N, 6402).astype(np.complex64)
+    plan = KbNufft(N, device=dev)
+    omt = _f(om, dev).requires_grad_(True)
+    peaks = []
+    for iters in (5, 60, 5):
+        xt = _c(x, dev).requires_grad_(True)
+        torch.cuda.synchronize()
+        base = torch.cuda.memory_allocated(dev)
+        torch.cuda.reset_peak_memory_stats(dev)
+        z = inverse(xt, omt, plan, smaps, lam=1e-3, iters=iters)
+        torch.view_as_real(z).pow(2).sum().backward()
+        torch.cuda.synchronize()
+        peaks.append((torch.cuda.max_memory_allocated(dev) - base, plan.info()["workspace_bytes"]))
+        del z, xt
+        omt.grad = None
+    _say(f"  peak bytes above inputs / plan workspace for 5, 60, 5 iterations: {peaks}")
+    assert peaks[0] == peaks[1] == peaks[2]

@@ -249,6 +249,41 @@ def test_chunked_jacobian_last_chunk_with_more_groups(dev):
     assert ndft.rel_l2(outs[1][rows], ex) < 1e-4
 
 
+def test_workspace_cap_splits_coils(dev):
+    """When one image's coils do not fit under the workspace cap, the plan
+    runs one image at a time in runs of coils (forward: runs of 2, 2, 1 of
+    5 coils; Jacobian and adjoint: one coil at a time).  Forward values are
+    per channel and must not change at all; the adjoint and the
+    omega-gradient add the runs in a different order (1e-6).  Both are also
+    compared with the exact NUDFT, and the workspace stays under the cap
+    (plus the omega-gradient's per-group partials)."""
+    N, B, C = (48, 40), 2, 5
+    _say(f"coil-chunked plan N={N} B={B} C={C}")
+    om = W.radial_2d(24, 96, jitter=np.pi / 48, seed=35).astype(np.float32)
+    M = om.shape[0]
+    x = W.complex_normal((B,) + N, 36)
+    g = W.complex_normal((B, C, M), 37)
+    smaps = _c(W.sense_maps(C, N), dev)
+    p1 = _plan(N, dev)
+    cap = 300_000
+    p2 = _plan(N, dev, max_workspace=cap)
+    for p in (p1, p2):
+        p.set_points(_f(om, dev))
+    a = [_np(p.forward(_c(x, dev), smaps)) for p in (p1, p2)]
+    b = [_np(p.adjoint(_c(g, dev), smaps)) for p in (p1, p2)]
+    c = [_np(p.jac_omega_fwd(_c(x, dev), _c(g, dev), smaps)) for p in (p1, p2)]
+    assert np.array_equal(a[0], a[1])
+    assert ndft.rel_l2(b[1], b[0]) < 1e-6
+    assert ndft.rel_l2(c[1], c[0]) < 1e-6
+    sm = W.sense_maps(C, N)
+    assert ndft.rel_l2(a[1], ndft.sense_forward(om, x, N, sm)) < TOL_NUFFT
+    assert ndft.rel_l2(b[1], ndft.sense_adjoint(om, g, N, sm)) < TOL_NUFFT
+    assert ndft.rel_l2(c[1], ndft.jac_omega_fwd(om, x, g, N, sm)) < TOL_JAC
+    ws = p2.info()["workspace_bytes"]
+    _say(f"  workspace {ws} bytes under cap {cap}")
+    assert ws <= cap + 64 * M * 2 * 4
+
+
 def test_throughput_shape_sampled(dev):
     """256x256, 64 spokes x 512 samples + jitter, sigma 2, J 6: sampled rows/pixels."""
     _say("256x256 M=32768 sampled parity")
