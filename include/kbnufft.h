@@ -13,7 +13,7 @@
  * Jacobians with respect to omega, evaluated as extra NUFFTs of images
  * weighted by the coordinate grids r^[d] (Sec. II-C eq. (e,Ax), Sec. II-D
  * eq. (e,A'y), JVP rule eq. (e,jac,Ax,v) of Sec. III), for the multi-coil
- * SENSE model E = (I_C kron A) S of Sec. II-F.
+ * SENSE model E = (I_C kron A) S of Sec. II-G.
  *
  * Conventions (all binding):
  *   - D in {1, 2, 3}.  Images are row-major, axis 0 slowest; the coordinate
@@ -120,7 +120,7 @@ int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts
 int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream);
 
 /*
- * y[b][c] = A(omega) (s_c (.) x_b)   (type-2 NUFFT; Sec. II-B, II-F).
+ * y[b][c] = A(omega) (s_c (.) x_b)   (type-2 NUFFT; Sec. II-B, II-G).
  * x: c64 [B][N...]; smaps: c64 [C][N...] or NULL (then C == 1);
  * y: c64 [B][C][M], overwritten.
  * Errors: INVALID_ARG (B < 1, C < 1, NULL pointers, smaps NULL with C > 1),
@@ -131,7 +131,7 @@ int kbn_forward(kbn_plan p, int B, int C, const void *x, const void *smaps, void
 
 /*
  * x_b = sum_c conj(s_c) (.) A(omega)^H y[b][c]   (type-1 NUFFT; Sec. II-D,
- * II-F).  y: c64 [B][C][M]; x: c64 [B][N...], overwritten.
+ * II-G).  y: c64 [B][C][M]; x: c64 [B][N...], overwritten.
  * Errors as kbn_forward.
  */
 int kbn_adjoint(kbn_plan p, int B, int C, const void *y, const void *smaps, void *x,
@@ -263,7 +263,7 @@ int kbn_cg_step(kbn_plan p, int C, const void *smaps, double lambda, int reg, in
 /*
  * Start a solve of (E^H E + lambda T^H T) x = b for an image right-hand side b
  * (c64 [N..], device) instead of b = E^H y: x = 0, r = p = b.  Used to apply
- * the regularised inverse of Sec. II-E to an image (and to its upstream
+ * the regularised inverse of Sec. II-F to an image (and to its upstream
  * gradient).  Continue with kbn_cg_step.  Errors as kbn_cg_begin.
  */
 int kbn_cg_begin_image(kbn_plan p, int C, const void *b, void *x, void *work, void *stream);

@@ -7,7 +7,7 @@ imports it.
 Contents
   ndft       exact FP64 non-uniform DFT (C, OpenMP) and the closed-form
              omega/x Jacobian-vector products derived from it (Sec. II-C,
-             II-D, II-F; eq. (e,jac,Ax,v)).
+             II-D, II-G; eq. (e,jac,Ax,v)).
   nufft_ref  FP64 Kaiser-Bessel NUFFT written step by step as the appendix
              describes it (scale, zero-padded K-point FFT, J-tap
              interpolation), plus the window and its Fourier transform.
@@ -15,5 +15,5 @@ Contents
              tile order that the index pass must reproduce bit for bit.
   cg         FP64 conjugate-gradient CG-SENSE reconstruction.
   inverse    the regularised inverse (E^H E + lambda I)^{-1} by dense FP64 solves,
-             and the gradients of the Gram and inverse operators (Sec. II-E).
+             and the gradients of the Gram and inverse operators (Sec. II-E, II-F).
 """

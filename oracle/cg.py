@@ -7,7 +7,7 @@ gradients; with T = I this is CG-SENSE, with T a finite-difference operator
 it is QPLS.  The paper does not fix the finite differences' boundary; the
 reading here is the non-circular first difference along each image axis,
 (T_d x)_j = x_{j + e_d} - x_j for j_d < N_d - 1, stacked over d.  E = (I_C kron A) S is the SENSE
-model of Sec. II-F, applied here by the exact NUDFT of ``ndft``.  The solver
+model of Sec. II-G, applied here by the exact NUDFT of ``ndft``.  The solver
 is the plain conjugate-gradient method of the reference the paper cites for
 the residual norm (Shewchuk), started from x0 = 0 and run for a fixed
 number of iterations; the reported residual is ||r|| / ||b|| with the

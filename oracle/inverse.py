@@ -4,7 +4,7 @@ Test infrastructure only (see the package docstring).
 
 T is the identity or the finite-difference operator of ``cg`` (T does not
 depend on omega, so the gradient formulas are the same for both).
-Sec. II-E treats the inverse as solved accurately (so that its Jacobian is
+Sec. II-F treats the inverse as solved accurately (so that its Jacobian is
 that of the exact inverse, evaluated approximately): with w = F^{-1} g,
   dL/dx     = w                            (F is Hermitian)
   dL/domega = - gram_vjp(x := F^{-1} x, g := w)

@@ -122,7 +122,7 @@ def adjoint(omega, y, N, wdim: int = -1, pix=None) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# SENSE model E = (I_C kron A) S (Sec. II-F)
+# SENSE model E = (I_C kron A) S (Sec. II-G)
 # ---------------------------------------------------------------------------
 
 def _coil_images(x, smaps, N):
@@ -212,7 +212,7 @@ def rel_l2(a, b) -> float:
 
 
 # ---------------------------------------------------------------------------
-# Gram and regularised-inverse operators (Sec. II-E)
+# Gram and regularised-inverse operators (Sec. II-E, II-F)
 # ---------------------------------------------------------------------------
 
 def gram_vjp(omega, x, g, N, smaps=None):

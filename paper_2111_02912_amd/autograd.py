@@ -1,7 +1,7 @@
 """Differentiable NUFFT layers: torch.autograd.Function pairs whose backward
 passes are the omega-Jacobians of the paper.
 
-Forward operator y = E(omega) x with E = (I_C kron A(omega)) S (Sec. II-F):
+Forward operator y = E(omega) x with E = (I_C kron A(omega)) S (Sec. II-G):
   * grad_x     = E^H g                               (Sec. II-C: dAx/dx = A)
   * grad_omega = sum_{b,c} Im{ A(s_c x_b r^[d]) conj(g_{b,c}) }
     (eq. (e,Ax) combined with the vector-Jacobian rule (e,jac,Ax,v))
@@ -105,10 +105,11 @@ class KbNufftLayer(torch.nn.Module):
     differentiable in their first argument and in omega.
     """
 
-    def __init__(self, N: Sequence[int], sigma: float = 2.0, J: int = 6, tile=None):
+    def __init__(self, N: Sequence[int], sigma: float = 2.0, J: int = 6, tile=None,
+                 accuracy: Optional[str] = None):
         super().__init__()
         self.N = tuple(int(n) for n in N)
-        self._cfg = dict(sigma=sigma, J=J, tile=tile)
+        self._cfg = dict(sigma=sigma, J=J, tile=tile, accuracy=accuracy)
         self._plans = {}
 
     def plan(self, device) -> KbNufft:
@@ -126,7 +127,7 @@ class KbNufftLayer(torch.nn.Module):
 
 
 # ---------------------------------------------------------------------------
-# Gram and regularised-inverse operators (Sec. II-E)
+# Gram and regularised-inverse operators (Sec. II-E, II-F)
 # ---------------------------------------------------------------------------
 
 def _gram_vjp(plan: KbNufft, x, g, smaps, need_x: bool, need_om: bool):

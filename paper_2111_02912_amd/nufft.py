@@ -23,6 +23,12 @@ def _ptr(t: Optional[torch.Tensor]):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+# (sigma, J) presets: the default high-accuracy setting (relative error
+# ~7e-6 against the NUDFT) and the low-accuracy setting used for training
+# in Sec. IV-C (grid 1.25 N, J = 5; error ~1e-3)
+ACCURACY = {"high": (2.0, 6), "low": (1.25, 5)}
+
+
 class KbNufft:
     """Kaiser-Bessel NUFFT plan for images of shape ``N`` on one GPU.
 
@@ -32,7 +38,11 @@ class KbNufft:
 
     def __init__(self, N: Sequence[int], sigma: float = 2.0, J: int = 6,
                  tile: Optional[Sequence[int]] = None, max_workspace: int = 0,
-                 spread_tile: int = 0, device=None):
+                 spread_tile: int = 0, device=None, accuracy: Optional[str] = None):
+        if accuracy is not None:
+            if accuracy not in ACCURACY:
+                raise ValueError(f"accuracy must be one of {sorted(ACCURACY)}, got {accuracy!r}")
+            sigma, J = ACCURACY[accuracy]
         self.N = tuple(int(n) for n in N)
         self.D = len(self.N)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())

@@ -9,7 +9,7 @@ The shapes follow the paper's workloads: 2D radial spokes through the k-space
 centre (the accuracy experiment of Sec. IV-A uses one radial spoke), variable
 density spiral interleaves (16 interleaves x 1280 samples, the trajectory
 learning experiments of Sec. IV-B), 3D radial "kooshball" spokes and smooth
-multi-coil sensitivity maps (the SENSE model of Sec. II-F).  The paper's own
+multi-coil sensitivity maps (the SENSE model of Sec. II-G).  The paper's own
 images (fastMRI, Shepp-Logan crop) and ESPIRiT maps are replaced by seeded
 Gaussian noise images and Gaussian-bump maps of the same shapes.
 

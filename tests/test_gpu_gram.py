@@ -1,4 +1,4 @@
-"""Gram and regularised-inverse layers (Sec. II-E) on the GPU against the
+"""Gram and regularised-inverse layers (Sec. II-E, II-F) on the GPU against the
 FP64 oracle.
 
 Gram operator z = E^H E x: the forward and dL/dx are two NUFFTs in a row,

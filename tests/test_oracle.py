@@ -241,6 +241,26 @@ def test_nufft_ref_approximates_ndft(N):
     assert errs[0] > 3 * errs[1] > 9 * errs[2]
 
 
+@pytest.mark.parametrize("N", [(40,), (32, 24), (12, 10, 8)])
+def test_nufft_ref_low_accuracy_mode(N):
+    """sigma = 1.25, J = 5 (the low-accuracy training setting of Sec. IV-C):
+    K = 7-smooth >= 1.25 N, the adjoint identity still exact, and the error
+    against the NUDFT of order 1e-3 -- far above the sigma = 2, J = 6 floor,
+    so a plan that silently kept sigma = 2 or J = 6 fails the lower bound."""
+    D = len(N)
+    om = W.uniform_random(300, D, seed=64)
+    x = _rand_c(N, 65)
+    y = _rand_c((300,), 66)
+    p = nufft_ref.Params(N, 1.25, 5)
+    assert all(k >= 1.25 * n and k < 1.25 * n + 8 for k, n in zip(p.K, N))
+    lhs = _inner(nufft_ref.forward(p, om, x), y)
+    rhs = _inner(x, nufft_ref.adjoint(p, om, y))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    ef = ndft.rel_l2(nufft_ref.forward(p, om, x), ndft.forward(om, x, N))
+    ea = ndft.rel_l2(nufft_ref.adjoint(p, om, y), ndft.adjoint(om, y, N))
+    assert 3e-4 < ef < 3e-3 and 3e-4 < ea < 3e-3
+
+
 def test_nufft_ref_jacobian_via_weighted_nufft():
     """A(x (.) r^[d]) from the NUFFT approximates the exact Jacobian diagonal."""
     N = (32, 32)

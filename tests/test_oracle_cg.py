@@ -1,7 +1,7 @@
 """Pins of the FP64 CG-SENSE oracle against routines other than itself.
 
 The SENSE matrix E is formed densely here straight from its definition
-(a_mj = exp(-i omega_m . r_j), Sec. II-B; E = (I_C kron A) S, Sec. II-F), so
+(a_mj = exp(-i omega_m . r_j), Sec. II-B; E = (I_C kron A) S, Sec. II-G), so
 that the pins do not go through the oracle's NUDFT code.
 """
 import numpy as np

@@ -1,8 +1,8 @@
-"""Pins of the Gram and regularised-inverse gradients (Sec. II-E).
+"""Pins of the Gram and regularised-inverse gradients (Sec. II-E, II-F).
 
 The independent route is torch FP64 autograd through dense matrices built
 from the definition a_mj = exp(-i omega_m . r_j) (Sec. II-B) and the SENSE
-model E = (I_C kron A) S (Sec. II-F); the inverse goes through
+model E = (I_C kron A) S (Sec. II-G); the inverse goes through
 torch.linalg.solve.  A central finite difference of the oracle's own Gram
 operator ties the omega-gradient to the forward map as well.
 """
