@@ -251,7 +251,7 @@ def bench_train(args):
     dev = torch.device("cuda", 0)
     N, om, x, smaps = W.spiral_sense_case()
     B, C, M = x.shape[0], smaps.shape[0], om.shape[0]
-    plan = KbNufft(N, device=dev)
+    plan = KbNufft(N, device=dev, accuracy=args.accuracy)
     xt = torch.from_numpy(x).to(dev).requires_grad_(True)
     st = torch.from_numpy(smaps).to(dev)
     omt = torch.from_numpy(om).to(dev).requires_grad_(True)
@@ -287,7 +287,8 @@ def bench_train(args):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": (f"SENSE trajectory learning: {N[0]}x{N[1]}, {B} images x {C} coils, "
                                 f"16 x 1280 spiral (M = {M}), loss |E(omega) x - y|^2, autograd "
-                                "backward to x and omega, SGD on omega")},
+                                "backward to x and omega, SGD on omega"),
+                   "sigma": plan.opts["sigma"], "J": plan.opts["J"], "K": list(plan.K)},
         "kernel_ms_per_step": kt,
     }
     print(json.dumps(out), flush=True)
@@ -503,6 +504,8 @@ def main():
     ap.add_argument("--streams", type=int, default=4, help="batch workload: streams")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="batch workload: default tiles instead of tuned ones")
+    ap.add_argument("--accuracy", choices=("high", "low"), default="high",
+                    help="step/train workloads: sigma 2, J 6 (high) or sigma 1.25, J 5 (low)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="after the run, copy this many bytes device-to-device once (a "
                          "known-size reference dispatch for hardware byte counters)")
@@ -532,7 +535,7 @@ def main():
     M = om.shape[0]
     D = len(N)
     g = W.complex_normal((B, 1, M), 2101)
-    p = KbNufft(N, device=dev)
+    p = KbNufft(N, device=dev, accuracy=args.accuracy)
     om_t = torch.from_numpy(om).to(dev)
     x_t = torch.from_numpy(x).to(dev)
     g_t = torch.from_numpy(g).to(dev)
@@ -614,7 +617,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "2D KB-NUFFT step: index pass + forward + omega-Jacobian + adjoint",
-            "N": list(N), "K": list(p.K), "M": M, "batch": B, "sigma": 2.0, "J": 6,
+            "N": list(N), "K": list(p.K), "M": M, "batch": B, "sigma": p.opts["sigma"], "J": p.opts["J"],
             "trajectory": "64 golden-angle radial spokes x 512 samples, uniform +-pi/256 jitter",
             "images": "complex64, re/im i.i.d. N(0,1)",
         },

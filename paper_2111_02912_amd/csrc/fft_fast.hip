@@ -241,6 +241,7 @@ __device__ __forceinline__ int pos_to_img(int p, int n) {
 template <int L, int E, bool INV, int NT>
 __global__ void __launch_bounds__(NT) k_cols(KbnMidPassArgs a, const float2 *__restrict__ tw) {
     using F = Fft<L, E, INV>;
+    static_assert(NT % F::TL == 0, "a workgroup holds whole lines");
     constexpr int LINES = NT / F::TL;
     __shared__ float2 lds[L * LINES];
     const int l = threadIdx.x % LINES;
@@ -269,13 +270,14 @@ __global__ void __launch_bounds__(NT) k_cols(KbnMidPassArgs a, const float2 *__r
 
 // ---- forward first pass along the last axis (with prologue) ----------------
 // LDS layout [line][position]
-template <int L, int E>
-__global__ void __launch_bounds__(KBN_BLOCK) k_rows_first(KbnFirstPassArgs a, const float2 *__restrict__ tw) {
+template <int L, int E, int NT>
+__global__ void __launch_bounds__(NT) k_rows_first(KbnFirstPassArgs a, const float2 *__restrict__ tw) {
     using F = Fft<L, E, false>;
-    constexpr int LINES = KBN_BLOCK / F::TL;
+    static_assert(NT % F::TL == 0, "a workgroup holds whole lines");
+    constexpr int LINES = NT / F::TL;
     __shared__ float2 lds[L * LINES];
     __shared__ float2 twl[L];
-    for (int i = threadIdx.x; i < L; i += KBN_BLOCK) twl[i] = tw[i];
+    for (int i = threadIdx.x; i < L; i += NT) twl[i] = tw[i];
     const int li = threadIdx.x / F::TL;
     const int u = threadIdx.x % F::TL;
     const int64_t line = (int64_t)blockIdx.x * LINES + li;
@@ -332,13 +334,14 @@ __global__ void __launch_bounds__(KBN_BLOCK) k_rows_first(KbnFirstPassArgs a, co
 }
 
 // ---- last inverse pass along the last axis (crop, scaling, coil sum) -------
-template <int L, int E>
-__global__ void __launch_bounds__(KBN_BLOCK) k_rows_last_adj(KbnLastAdjArgs a, const float2 *__restrict__ tw) {
+template <int L, int E, int NT>
+__global__ void __launch_bounds__(NT) k_rows_last_adj(KbnLastAdjArgs a, const float2 *__restrict__ tw) {
     using F = Fft<L, E, true>;
-    constexpr int LINES = KBN_BLOCK / F::TL;
+    static_assert(NT % F::TL == 0, "a workgroup holds whole lines");
+    constexpr int LINES = NT / F::TL;
     __shared__ float2 lds[L * LINES];
     __shared__ float2 twl[L];
-    for (int i = threadIdx.x; i < L; i += KBN_BLOCK) twl[i] = tw[i];
+    for (int i = threadIdx.x; i < L; i += NT) twl[i] = tw[i];
     const int li = threadIdx.x / F::TL;
     const int u = threadIdx.x % F::TL;
     const int64_t line = (int64_t)blockIdx.x * LINES + li;
@@ -405,18 +408,26 @@ __global__ void __launch_bounds__(KBN_BLOCK) k_rows_last_adj(KbnLastAdjArgs a, c
 }
 
 // Elements per thread for each specialised length: rows (last axis) and
-// columns (strided axes, 64 KiB of LDS per workgroup).
+// columns (strided axes, at most 64 KiB of LDS per workgroup).  Every radix
+// of a length's plan must divide E (radices 8, 4, 2, 3, 5), L / E threads
+// serve one line and a workgroup holds whole lines: 400 = 2^4 5^2 takes
+// E = 20 (radices 4,4,5,5) with 20 threads per line in 320-thread
+// workgroups; 480 = 2^5 3 5 takes E = 60 (4,4,2,3,5) with 128 threads.
 constexpr int row_e(int L) {
     return L == 128 ? 8 : L == 256 ? 8 : L == 512 ? 8 : L == 1024 ? 16 : L == 192 ? 12
-           : L == 384 ? 12 : L == 640 ? 20 : L == 768 ? 24 : 0;
+           : L == 384 ? 12 : L == 640 ? 10 : L == 768 ? 24 : L == 160 ? 10 : L == 320 ? 10
+           : L == 400 ? 10 : L == 480 ? 60 : 0;
 }
 constexpr int col_e(int L) {
     return L == 128 ? 8 : L == 256 ? 16 : L == 512 ? 16 : L == 1024 ? 32 : L == 192 ? 12
-           : L == 384 ? 24 : L == 640 ? 20 : L == 768 ? 24 : 0;
+           : L == 384 ? 24 : L == 640 ? 20 : L == 768 ? 24 : L == 160 ? 20 : L == 320 ? 20
+           : L == 400 ? 20 : L == 480 ? 60 : 0;
 }
+// threads per row-pass workgroup
+constexpr int row_nt(int L) { return L == 400 ? 320 : L == 480 ? 128 : KBN_BLOCK; }
 // threads per column-pass workgroup (512 for L = 512: 16 columns of 32
 // threads, 64 KB of LDS, measured faster than 256 threads with E = 32)
-constexpr int col_nt(int L) { return L == 512 ? 512 : KBN_BLOCK; }
+constexpr int col_nt(int L) { return L == 512 ? 512 : L == 400 ? 320 : L == 480 ? 128 : KBN_BLOCK; }
 
 template <int L>
 hipError_t launch_cols(const KbnMidPassArgs &a, const float2 *tw, int inverse, hipStream_t s) {
@@ -435,22 +446,27 @@ hipError_t launch_cols(const KbnMidPassArgs &a, const float2 *tw, int inverse, h
 template <int L>
 hipError_t launch_rows_first(const KbnFirstPassArgs &a, const float2 *tw, hipStream_t s) {
     constexpr int E = row_e(L);
-    constexpr int LINES = KBN_BLOCK / (L / E);
+    constexpr int NT = row_nt(L);
+    constexpr int LINES = NT / (L / E);
     const dim3 grid((unsigned)((a.nlines + LINES - 1) / LINES));
-    k_rows_first<L, E><<<grid, dim3(KBN_BLOCK), 0, s>>>(a, tw);
+    k_rows_first<L, E, NT><<<grid, dim3(NT), 0, s>>>(a, tw);
     return hipGetLastError();
 }
 
 template <int L>
 hipError_t launch_rows_last(const KbnLastAdjArgs &a, const float2 *tw, hipStream_t s) {
     constexpr int E = row_e(L);
-    constexpr int LINES = KBN_BLOCK / (L / E);
+    constexpr int NT = row_nt(L);
+    constexpr int LINES = NT / (L / E);
     const dim3 grid((unsigned)((a.nlines + LINES - 1) / LINES));
-    k_rows_last_adj<L, E><<<grid, dim3(KBN_BLOCK), 0, s>>>(a, tw);
+    k_rows_last_adj<L, E, NT><<<grid, dim3(NT), 0, s>>>(a, tw);
     return hipGetLastError();
 }
 
-#define KBN_FAST_SIZES(X) X(128) X(192) X(256) X(384) X(512) X(640) X(768) X(1024)
+#define KBN_FAST_SIZES(X) \
+    X(128) X(160) X(192) X(256) X(320) X(384) X(400) X(480) X(512) X(640) X(768) X(1024)
+#define KBN_FAST_LAST_SIZES(X) \
+    X(128) X(160) X(192) X(256) X(320) X(384) X(400) X(512) X(640) X(768) X(1024)
 
 }  // namespace
 
@@ -458,6 +474,16 @@ bool kbn_fast_fft_size(int L) {
     switch (L) {
 #define KBN_CASE(n) case n:
         KBN_FAST_SIZES(KBN_CASE)
+#undef KBN_CASE
+        return true;
+        default: return false;
+    }
+}
+
+bool kbn_fast_last_size(int L) {
+    switch (L) {
+#define KBN_CASE(n) case n:
+        KBN_FAST_LAST_SIZES(KBN_CASE)
 #undef KBN_CASE
         return true;
         default: return false;
@@ -486,7 +512,7 @@ hipError_t kbn_launch_fast_first(const KbnFirstPassArgs &a, int L, const float2 
 hipError_t kbn_launch_fast_last(const KbnLastAdjArgs &a, int L, const float2 *tw, hipStream_t s) {
     switch (L) {
 #define KBN_CASE(n) case n: return launch_rows_last<n>(a, tw, s);
-        KBN_FAST_SIZES(KBN_CASE)
+        KBN_FAST_LAST_SIZES(KBN_CASE)
 #undef KBN_CASE
         default: return hipErrorInvalidValue;
     }

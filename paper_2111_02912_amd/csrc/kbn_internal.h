@@ -133,6 +133,9 @@ int kbn_lines_per_block(const KbnRadix &rp, int maxe);
 // Compile-time specialised passes (fft_fast.hip) for the lengths where
 // kbn_fast_fft_size() is true; they return hipErrorInvalidValue otherwise.
 bool kbn_fast_fft_size(int L);
+// the specialised last adjoint pass exists for a subset of those lengths (it
+// holds E accumulators besides the E values: above E = 32 it would spill)
+bool kbn_fast_last_size(int L);
 hipError_t kbn_launch_fast_first(const KbnFirstPassArgs &a, int L, const float2 *tw, hipStream_t s);
 hipError_t kbn_launch_fast_mid(const KbnMidPassArgs &a, int L, const float2 *tw, int inverse,
                                hipStream_t s);

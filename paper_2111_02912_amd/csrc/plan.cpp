@@ -551,7 +551,7 @@ int run_type1(kbn_plan p, int B, int C, const float2 *y, const float2 *smaps, fl
             la.N[d] = p->N[d];
             la.deap[d] = p->deap[d];
         }
-        if (p->fast_fft && kbn_fast_fft_size(p->K[D - 1]))
+        if (p->fast_fft && kbn_fast_last_size(p->K[D - 1]))
             KBN_LAUNCH(KBN_CLASS_FFT_LAST_ADJ, kbn_launch_fast_last(la, p->K[D - 1], p->tw[D - 1], stream),
                        "last adjoint pass");
         else

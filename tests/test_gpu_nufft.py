@@ -334,10 +334,12 @@ def test_bench_configuration_sampled(dev):
     assert e_f < TOL_NUFFT and e_a < TOL_NUFFT and e_j < TOL_JAC
 
 
-@pytest.mark.parametrize("N", [(64, 96), (160, 128), (48, 40, 64), (256, 130)])
+@pytest.mark.parametrize("N", [(64, 96), (160, 128), (48, 40, 64), (256, 130), (80, 200), (240, 160),
+                               (200, 64), (40, 100, 80)])
 def test_specialised_fft_matches_generic(N, dev, monkeypatch):
     """The compile-time specialised FFT passes and the generic ones agree, and
-    both match the oracle (K = 128, 192, 320->generic, 256, 96->generic...)."""
+    both match the oracle (K = 128, 192, 320, 256, 96->generic, 160, 400,
+    480, 200->generic ...)."""
     _say(f"specialised vs generic FFT N={N}")
     D = len(N)
     om = W.uniform_random(2500, D, seed=91)
