@@ -14,6 +14,10 @@ Contents
   points_ref the per-point grid offsets, fractions, tile ids and the stable
              tile order that the index pass must reproduce bit for bit.
   cg         FP64 conjugate-gradient CG-SENSE reconstruction.
-  inverse    the regularised inverse (E^H E + lambda I)^{-1} by dense FP64 solves,
-             and the gradients of the Gram and inverse operators (Sec. II-E, II-F).
+  inverse    the regularised inverse (E^H E + lambda T^H T)^{-1} by dense FP64
+             solves, and the gradients of the Gram and inverse operators
+             (Sec. II-E, II-F).
+  field      the off-resonance model of Sec. II-H: the exact operator, the
+             segmented form sum_l diag(b_l) A diag(c_l) and its omega-gradients,
+             and linear-interpolation time segmentation.
 """
