@@ -269,6 +269,53 @@ int kbn_cg_step(kbn_plan p, int C, const void *smaps, double lambda, int reg, in
 int kbn_cg_begin_image(kbn_plan p, int C, const void *b, void *x, void *work, void *stream);
 
 /*
+ * Off-resonance (field inhomogeneity) model, Sec. II-H.  The exact system
+ * matrix a_ij = exp(-i omega_i . r_j) exp(-i w_j t_i) is approximated by
+ *   E_f = sum_l diag(b_l) A(omega) diag(c_l),   b_l in C^M, c_l in C^N,
+ * and with coil maps E = sum_l diag(b_l) (I_C kron A) diag(c_l) S.  The
+ * Jacobians follow by putting E_f in place of A (b and c do not depend on
+ * omega).
+ *   b: c64 [L][M] k-space weights;  c: c64 [L][N..] image-domain factors
+ *   (device, caller-owned); x, y, smaps, g, domega as for the plain calls.
+ * kbn_field_forward:        y[b][k] = sum_l b_l (.) A(c_l s_k x_b)
+ * kbn_field_adjoint:        x_b = sum_{l,k} conj(c_l s_k) (.) A^H(conj(b_l) (.) y[b][k])
+ * kbn_field_jac_omega_fwd:  dL/domega for y = E x, upstream g [B][C][M]
+ *                           = sum_{b,k,l} Im{ b_l A(c_l s_k x_b (.) r^[d]) conj(g_{b,k}) }
+ * kbn_field_jac_omega_adj:  dL/domega for x = E^H y, upstream g [B][N..]
+ *                           = sum_{b,k,l} Im{ A(c_l s_k g_b (.) r^[d]) b_l conj(y_{b,k}) }
+ * The x-gradients are the other operator: E^H g (forward) and E g (adjoint).
+ * The plan keeps a second workspace for the L*C virtual coil maps c_l s_k
+ * and the k-space of L*C virtual coils for a chunk of images (chunked to
+ * stay under max_workspace); it grows on demand like the grid workspace.
+ * Errors: as the plain calls, and INVALID_ARG for L < 1 or null b / c.
+ */
+int kbn_field_forward(kbn_plan p, int B, int C, int L, const void *x, const void *smaps,
+                      const void *b, const void *c, void *y, void *stream);
+int kbn_field_adjoint(kbn_plan p, int B, int C, int L, const void *y, const void *smaps,
+                      const void *b, const void *c, void *x, void *stream);
+int kbn_field_jac_omega_fwd(kbn_plan p, int B, int C, int L, const void *x, const void *smaps,
+                            const void *b, const void *c, const void *g, float *domega,
+                            int accumulate, void *stream);
+int kbn_field_jac_omega_adj(kbn_plan p, int B, int C, int L, const void *y, const void *smaps,
+                            const void *b, const void *c, const void *g, float *domega,
+                            int accumulate, void *stream);
+
+/*
+ * Linear-interpolation time segmentation for the model above (the paper
+ * leaves the choice of b and c to the approximation methods it cites):
+ * segment times tau_l = t0 + (t1 - t0) l / (L - 1) (the midpoint when
+ * L = 1), c_lj = exp(-i w_j tau_l), and b_il the linear interpolation
+ * weights of t_i between its two neighbouring tau_l (t_i clamped to
+ * [t0, t1]; sum_l b_il = 1).
+ *   t: float [M] readout times (s);  w: float [npix] field map (rad/s);
+ *   b: c64 [L][M] out;  c: c64 [L][npix] out   (device pointers)
+ * Errors: INVALID_ARG (M < 0, npix < 1, L < 1, t0/t1 not finite or t1 < t0,
+ * null pointers), HIP.
+ */
+int kbn_field_segments(int64_t M, const float *t, double t0, double t1, int64_t npix,
+                       const float *w, int L, void *b, void *c, void *stream);
+
+/*
  * Batches: many independent operator calls issued together.
  *
  * Not an operation of the paper; an executor for running many SENSE

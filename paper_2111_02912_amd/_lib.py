@@ -36,7 +36,8 @@ EXPORTS = (
     "kbn_last_error", "kbn_timing", "kbn_timing_read", "kbn_timing_name",
     "kbn_batch_create", "kbn_batch_run", "kbn_batch_capture", "kbn_batch_launch",
     "kbn_batch_destroy", "kbn_cg_work_bytes", "kbn_cg_begin", "kbn_cg_step",
-    "kbn_cg_begin_image",
+    "kbn_cg_begin_image", "kbn_field_forward", "kbn_field_adjoint", "kbn_field_jac_omega_fwd",
+    "kbn_field_jac_omega_adj", "kbn_field_segments",
 )
 
 
@@ -115,6 +116,12 @@ def lib():
     L.kbn_cg_begin.argtypes = [vp, ci, vp, vp, vp, vp, vp]
     L.kbn_cg_step.argtypes = [vp, ci, vp, ctypes.c_double, ci, ci, vp, vp, vp]
     L.kbn_cg_begin_image.argtypes = [vp, ci, vp, vp, vp, vp]
+    L.kbn_field_forward.argtypes = [vp, ci, ci, ci, vp, vp, vp, vp, vp, vp]
+    L.kbn_field_adjoint.argtypes = [vp, ci, ci, ci, vp, vp, vp, vp, vp, vp]
+    L.kbn_field_jac_omega_fwd.argtypes = [vp, ci, ci, ci, vp, vp, vp, vp, vp, vp, ci, vp]
+    L.kbn_field_jac_omega_adj.argtypes = [vp, ci, ci, ci, vp, vp, vp, vp, vp, vp, ci, vp]
+    L.kbn_field_segments.argtypes = [ctypes.c_int64, vp, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_int64, vp, ci, vp, vp, vp]
     for name in EXPORTS:
         if name not in ("kbn_strerror", "kbn_last_error", "kbn_timing_name"):
             getattr(L, name).restype = ci

@@ -127,6 +127,76 @@ class KbNufftLayer(torch.nn.Module):
 
 
 # ---------------------------------------------------------------------------
+# Off-resonance model (Sec. II-H): E_f = sum_l diag(b_l) A diag(c_l) (with S)
+# ---------------------------------------------------------------------------
+
+class _FieldForwardOp(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, omega, smaps, b, c, plan):
+        _no_map_grad(smaps)
+        if b.requires_grad or c.requires_grad:
+            raise NotImplementedError("gradients with respect to b and c are not provided")
+        plan.ensure_points(omega)
+        ctx.plan = plan
+        ctx.xshape = x.shape
+        ctx.save_for_backward(x, omega, smaps, b, c)
+        return plan.field_forward(x, b, c, smaps)
+
+    @staticmethod
+    @once_differentiable
+    def backward(ctx, g):
+        x, omega, smaps, b, c = ctx.saved_tensors
+        plan = ctx.plan
+        plan.ensure_points(omega)
+        g = g.contiguous()
+        gx = gom = None
+        if ctx.needs_input_grad[0]:
+            gx = plan.field_adjoint(g, b, c, smaps).reshape(ctx.xshape)
+        if ctx.needs_input_grad[1]:
+            gom = plan.field_jac_omega_fwd(x, g, b, c, smaps)
+        return gx, gom, None, None, None, None
+
+
+class _FieldAdjointOp(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, y, omega, smaps, b, c, plan):
+        _no_map_grad(smaps)
+        if b.requires_grad or c.requires_grad:
+            raise NotImplementedError("gradients with respect to b and c are not provided")
+        plan.ensure_points(omega)
+        ctx.plan = plan
+        ctx.yshape = y.shape
+        ctx.save_for_backward(y, omega, smaps, b, c)
+        return plan.field_adjoint(y, b, c, smaps)
+
+    @staticmethod
+    @once_differentiable
+    def backward(ctx, g):
+        y, omega, smaps, b, c = ctx.saved_tensors
+        plan = ctx.plan
+        plan.ensure_points(omega)
+        g = g.contiguous()
+        gy = gom = None
+        if ctx.needs_input_grad[0]:
+            gy = plan.field_forward(g, b, c, smaps).reshape(ctx.yshape)
+        if ctx.needs_input_grad[1]:
+            gom = plan.field_jac_omega_adj(y, g, b, c, smaps)
+        return gy, gom, None, None, None, None
+
+
+def nufft_field(x: torch.Tensor, omega: torch.Tensor, plan: KbNufft, b: torch.Tensor, c: torch.Tensor,
+                smaps: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """y = E_f(omega) x with E_f = sum_l diag(b_l) A diag(c_l) S; [B, C, M]."""
+    return _FieldForwardOp.apply(x, omega, smaps, b, c, plan)
+
+
+def nufft_field_adjoint(y: torch.Tensor, omega: torch.Tensor, plan: KbNufft, b: torch.Tensor,
+                        c: torch.Tensor, smaps: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """x = E_f(omega)^H y; [B, *N]."""
+    return _FieldAdjointOp.apply(y, omega, smaps, b, c, plan)
+
+
+# ---------------------------------------------------------------------------
 # Gram and regularised-inverse operators (Sec. II-E, II-F)
 # ---------------------------------------------------------------------------
 

@@ -17,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libkbnufft.so")
 
-SOURCES = ["plan.cpp", "batch.cpp", "points.hip", "fft.hip", "fft_fast.hip", "interp.hip", "cg.hip"]
+SOURCES = ["plan.cpp", "batch.cpp", "points.hip", "fft.hip", "fft_fast.hip", "interp.hip", "cg.hip",
+           "field.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -230,6 +230,20 @@ double kbn_internal_cost(kbn_plan p, int B, int C, int jac, int type1);
 #define KBN_CGK_XR 2    // x += alpha p, r -= alpha q, beta, rr, rel
 #define KBN_CGK_P 3     // p = r + beta p
 int kbn_cg_nparts(int64_t n);
+
+// ---------------------------------------------------------------------------
+// Off-resonance model kernels (field.hip): virtual coil maps c_l s_k
+// (v = l*C + k), k-space expansion by conj(b_l) and combination by b_l, and
+// linear-interpolation time segmentation
+// ---------------------------------------------------------------------------
+hipError_t kbn_launch_field_maps(int L, int C, int64_t npix, const float2 *c, const float2 *smaps,
+                                 float2 *vm, hipStream_t s);
+hipError_t kbn_launch_field_expand(int64_t nb, int L, int C, int64_t M, const float2 *bw,
+                                   const float2 *y, float2 *ye, hipStream_t s);
+hipError_t kbn_launch_field_combine(int64_t nb, int L, int C, int64_t M, const float2 *bw,
+                                    const float2 *ye, float2 *y, hipStream_t s);
+hipError_t kbn_launch_field_segments(int64_t M, const float *t, double t0, double t1, int64_t npix,
+                                     const float *w, int L, float2 *bw, float2 *c, hipStream_t s);
 // image extent for the regulariser stencil, unused axes 1 (row-major, n0 slowest)
 struct KbnCgImage {
     int reg;  // KBN_REG_IDENTITY or KBN_REG_FINITE_DIFF

@@ -203,6 +203,9 @@ struct kbn_plan_s {
     // grid workspace
     float2 *ws = nullptr;
     int64_t ws_bytes = 0, max_ws = 0;
+    // off-resonance workspace: virtual coil maps and expanded k-space
+    char *fws = nullptr;
+    int64_t fws_bytes = 0;
     // captured batch graphs that hold this plan's buffer addresses; while
     // non-zero the plan refuses anything that would move or resize them
     int graph_refs = 0;
@@ -320,6 +323,7 @@ void free_plan(kbn_plan p) {
     dev_free(p->scomb);
     dev_free(p->scounts);
     dev_free(p->ws);
+    dev_free(p->fws);
     delete p;
 }
 
@@ -958,6 +962,145 @@ int kbn_cg_step(kbn_plan p, int C, const void *smaps, double lambda, int reg, in
         if (rc != KBN_OK) return rc;
     }
     return KBN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Off-resonance model (Sec. II-H): E = sum_l diag(b_l) (I_C kron A) diag(c_l) S.
+// The L segments are L*C virtual coils with maps c_l s_k; k-space is expanded
+// by conj(b_l) before the spread / Jacobian gather and combined by b_l after
+// the forward gather.  Images are processed in chunks so that the expanded
+// k-space of a chunk stays under the workspace cap.
+// ---------------------------------------------------------------------------
+struct FieldBufs {
+    float2 *vm, *ye;
+    int64_t bc;  // images per chunk
+};
+
+static int field_prep(kbn_plan p, int B, int C, int L, const void *smaps, const void *bw, const void *c,
+                      FieldBufs *fb, hipStream_t stream) {
+    if (L < 1) return fail(KBN_ERR_INVALID_ARG, "L must be >= 1");
+    if (!c || (!bw && p->M > 0)) return fail(KBN_ERR_INVALID_ARG, "null segment coefficients");
+    int64_t npix = 1;
+    for (int d = 0; d < p->D; ++d) npix *= p->N[d];
+    const int64_t LC = (int64_t)L * C;
+    if (LC > (1 << 20)) return fail(KBN_ERR_INVALID_ARG, "L * C too large");
+    const int64_t per_img = LC * std::max<int64_t>(p->M, 0) * (int64_t)sizeof(float2);
+    fb->bc = per_img > 0 ? std::max<int64_t>(1, std::min<int64_t>(B, p->max_ws / per_img)) : B;
+    const int64_t o_ye = (LC * npix * (int64_t)sizeof(float2) + 255) / 256 * 256;
+    const int64_t bytes = o_ye + fb->bc * per_img;
+    if (bytes > p->fws_bytes) {
+        if (p->graph_refs > 0)
+            return fail(KBN_ERR_UNSUPPORTED, "workspace growth on a plan held by a captured batch");
+        if (p->fws) KBN_HIP(hipStreamSynchronize(stream));  // the old buffer may still be in use
+        dev_free(p->fws);
+        p->fws_bytes = 0;
+        int rc = dev_alloc(&p->fws, bytes);
+        if (rc != KBN_OK) return rc;
+        p->fws_bytes = bytes;
+    }
+    fb->vm = (float2 *)p->fws;
+    fb->ye = (float2 *)(p->fws + o_ye);
+    return launched(kbn_launch_field_maps(L, C, npix, (const float2 *)c, (const float2 *)smaps, fb->vm, stream),
+                    "field maps", stream);
+}
+
+int kbn_field_forward(kbn_plan p, int B, int C, int L, const void *x, const void *smaps, const void *bw,
+                      const void *c, void *y, void *stream_) {
+    int rc = check_common(p, B, C, x, smaps, y);
+    if (rc != KBN_OK) return rc;
+    if (p->M == 0) return L < 1 ? fail(KBN_ERR_INVALID_ARG, "L must be >= 1") : KBN_OK;
+    hipStream_t stream = (hipStream_t)stream_;
+    FieldBufs fb;
+    rc = field_prep(p, B, C, L, smaps, bw, c, &fb, stream);
+    if (rc != KBN_OK) return rc;
+    const int64_t npix = (int64_t)img_rows(p) * p->N[p->D - 1];
+    const int LC = L * C;
+    for (int64_t b0 = 0; b0 < B; b0 += fb.bc) {
+        const int64_t nb = std::min<int64_t>(fb.bc, B - b0);
+        rc = run_type2(p, (int)nb, LC, 1, 0, (const float2 *)x + b0 * npix, fb.vm, 0, fb.ye, nullptr,
+                       nullptr, 0, stream);
+        if (rc != KBN_OK) return rc;
+        rc = launched(kbn_launch_field_combine(nb, L, C, p->M, (const float2 *)bw, fb.ye,
+                                               (float2 *)y + b0 * C * p->M, stream),
+                      "field combine", stream);
+        if (rc != KBN_OK) return rc;
+    }
+    return KBN_OK;
+}
+
+int kbn_field_adjoint(kbn_plan p, int B, int C, int L, const void *y, const void *smaps, const void *bw,
+                      const void *c, void *x, void *stream_) {
+    int rc = check_common(p, B, C, x, smaps, y);
+    if (rc != KBN_OK) return rc;
+    hipStream_t stream = (hipStream_t)stream_;
+    FieldBufs fb;
+    rc = field_prep(p, B, C, L, smaps, bw, c, &fb, stream);
+    if (rc != KBN_OK) return rc;
+    const int64_t npix = (int64_t)img_rows(p) * p->N[p->D - 1];
+    for (int64_t b0 = 0; b0 < B; b0 += fb.bc) {
+        const int64_t nb = std::min<int64_t>(fb.bc, B - b0);
+        rc = launched(kbn_launch_field_expand(nb, L, C, p->M, (const float2 *)bw,
+                                              (const float2 *)y + b0 * C * std::max<int64_t>(p->M, 0), fb.ye,
+                                              stream),
+                      "field expand", stream);
+        if (rc != KBN_OK) return rc;
+        rc = run_type1(p, (int)nb, L * C, fb.ye, fb.vm, (float2 *)x + b0 * npix, stream);
+        if (rc != KBN_OK) return rc;
+    }
+    return KBN_OK;
+}
+
+// shared by the two omega-Jacobians: expand the k-space operand kv by
+// conj(b_l) and gather the Jacobian channels of the image operand im
+static int field_jac(kbn_plan p, int B, int C, int L, const void *im, const void *smaps, const void *bw,
+                     const void *c, const void *kv, float *dom, int accumulate, hipStream_t stream) {
+    if (!dom) return fail(KBN_ERR_INVALID_ARG, "null domega");
+    FieldBufs fb;
+    int rc = field_prep(p, B, C, L, smaps, bw, c, &fb, stream);
+    if (rc != KBN_OK) return rc;
+    const int64_t npix = (int64_t)img_rows(p) * p->N[p->D - 1];
+    for (int64_t b0 = 0; b0 < B; b0 += fb.bc) {
+        const int64_t nb = std::min<int64_t>(fb.bc, B - b0);
+        rc = launched(kbn_launch_field_expand(nb, L, C, p->M, (const float2 *)bw,
+                                              (const float2 *)kv + b0 * C * p->M, fb.ye, stream),
+                      "field expand", stream);
+        if (rc != KBN_OK) return rc;
+        rc = run_jac(p, (int)nb, L * C, (const float2 *)im + b0 * npix, fb.vm, fb.ye, dom,
+                     (accumulate || b0 > 0) ? 1 : 0, stream);
+        if (rc != KBN_OK) return rc;
+    }
+    return KBN_OK;
+}
+
+int kbn_field_jac_omega_fwd(kbn_plan p, int B, int C, int L, const void *x, const void *smaps,
+                            const void *bw, const void *c, const void *g, float *domega, int accumulate,
+                            void *stream) {
+    int rc = check_common(p, B, C, x, smaps, g);
+    if (rc != KBN_OK) return rc;
+    if (L < 1) return fail(KBN_ERR_INVALID_ARG, "L must be >= 1");
+    if (p->M == 0) return KBN_OK;
+    return field_jac(p, B, C, L, x, smaps, bw, c, g, domega, accumulate, (hipStream_t)stream);
+}
+
+int kbn_field_jac_omega_adj(kbn_plan p, int B, int C, int L, const void *y, const void *smaps,
+                            const void *bw, const void *c, const void *g, float *domega, int accumulate,
+                            void *stream) {
+    int rc = check_common(p, B, C, g, smaps, y);
+    if (rc != KBN_OK) return rc;
+    if (L < 1) return fail(KBN_ERR_INVALID_ARG, "L must be >= 1");
+    if (p->M == 0) return KBN_OK;
+    return field_jac(p, B, C, L, g, smaps, bw, c, y, domega, accumulate, (hipStream_t)stream);
+}
+
+int kbn_field_segments(int64_t M, const float *t, double t0, double t1, int64_t npix, const float *w,
+                       int L, void *bw, void *c, void *stream) {
+    if (M < 0 || npix < 1 || L < 1) return fail(KBN_ERR_INVALID_ARG, "bad sizes");
+    if (!std::isfinite(t0) || !std::isfinite(t1) || t1 < t0)
+        return fail(KBN_ERR_INVALID_ARG, "segment window must be finite with t1 >= t0");
+    if ((M > 0 && (!t || !bw)) || !w || !c) return fail(KBN_ERR_INVALID_ARG, "null pointer");
+    return launched(kbn_launch_field_segments(M, t, t0, t1, npix, w, L, (float2 *)bw, (float2 *)c,
+                                              (hipStream_t)stream),
+                    "field segments", (hipStream_t)stream);
 }
 
 int kbn_plan_info(kbn_plan p, int64_t *K, int *tile, int *ntiles, double *beta, int64_t *M,

@@ -201,6 +201,91 @@ class KbNufft:
               "kbn_jac_x")
         return out
 
+    # -- off-resonance model (Sec. II-H): E = sum_l diag(b_l) A diag(c_l) S --
+    def _seg(self, b: torch.Tensor, c: torch.Tensor):
+        if c.dtype != torch.complex64 or c.device != self.device or c.dim() != self.D + 1 \
+                or tuple(c.shape[1:]) != self.N:
+            raise TypeError(f"c must be complex64 [L, *{self.N}] on {self.device}")
+        L = int(c.shape[0])
+        if b.dtype != torch.complex64 or b.device != self.device or tuple(b.shape) != (L, self.M):
+            raise TypeError(f"b must be complex64 [{L}, {self.M}] on {self.device}")
+        return b.contiguous(), c.contiguous(), L
+
+    def field_forward(self, x, b, c, smaps=None) -> torch.Tensor:
+        """y[b, k] = sum_l b_l (.) A(c_l s_k x_b); returns [B, C, M]."""
+        self._need_points()
+        xx = self._img(x, "x")
+        s, C = self._maps(smaps)
+        bb, cc, L = self._seg(b, c)
+        B = xx.shape[0]
+        y = torch.empty((B, C, self.M), dtype=torch.complex64, device=self.device)
+        check(_lib.lib().kbn_field_forward(self._h, B, C, L, _ptr(xx), _ptr(s), _ptr(bb), _ptr(cc), _ptr(y),
+                                           _stream(self.device)), "kbn_field_forward")
+        return y
+
+    def field_adjoint(self, y, b, c, smaps=None) -> torch.Tensor:
+        """x_b = sum_{l,k} conj(c_l s_k) (.) A^H(conj(b_l) (.) y[b, k]); [B, *N]."""
+        self._need_points()
+        s, C = self._maps(smaps)
+        bb, cc, L = self._seg(b, c)
+        B = y.numel() // (C * self.M) if self.M else y.shape[0]
+        yy = self._ksp(y, B, C, "y")
+        x = torch.empty((B,) + self.N, dtype=torch.complex64, device=self.device)
+        check(_lib.lib().kbn_field_adjoint(self._h, B, C, L, _ptr(yy), _ptr(s), _ptr(bb), _ptr(cc), _ptr(x),
+                                           _stream(self.device)), "kbn_field_adjoint")
+        return x
+
+    def field_jac_omega_fwd(self, x, g, b, c, smaps=None, out=None, accumulate: bool = False):
+        """dL/domega for y = E_f x given g = dL/dy [B, C, M]; returns [M, D]."""
+        self._need_points()
+        xx = self._img(x, "x")
+        s, C = self._maps(smaps)
+        bb, cc, L = self._seg(b, c)
+        B = xx.shape[0]
+        gg = self._ksp(g, B, C, "g")
+        dom = out if out is not None else torch.empty((self.M, self.D), dtype=torch.float32, device=self.device)
+        check(_lib.lib().kbn_field_jac_omega_fwd(self._h, B, C, L, _ptr(xx), _ptr(s), _ptr(bb), _ptr(cc),
+                                                 _ptr(gg), _ptr(dom), int(accumulate), _stream(self.device)),
+              "kbn_field_jac_omega_fwd")
+        return dom
+
+    def field_jac_omega_adj(self, y, g, b, c, smaps=None, out=None, accumulate: bool = False):
+        """dL/domega for x = E_f^H y given g = dL/dx [B, *N]; returns [M, D]."""
+        self._need_points()
+        gg = self._img(g, "g")
+        s, C = self._maps(smaps)
+        bb, cc, L = self._seg(b, c)
+        B = gg.shape[0]
+        yy = self._ksp(y, B, C, "y")
+        dom = out if out is not None else torch.empty((self.M, self.D), dtype=torch.float32, device=self.device)
+        check(_lib.lib().kbn_field_jac_omega_adj(self._h, B, C, L, _ptr(yy), _ptr(s), _ptr(bb), _ptr(cc),
+                                                 _ptr(gg), _ptr(dom), int(accumulate), _stream(self.device)),
+              "kbn_field_jac_omega_adj")
+        return dom
+
+    def field_segments(self, t: torch.Tensor, w: torch.Tensor, L: int, t0=None, t1=None):
+        """Linear-interpolation time segmentation (b [L, M], c [L, *N]) for
+        readout times t [M] (s) and field map w [*N] (rad/s); the segment
+        times span [t0, t1] (default: the range of t)."""
+        if t.dtype != torch.float32 or t.device != self.device or t.dim() != 1:
+            raise TypeError(f"t must be float32 [M] on {self.device}")
+        if w.dtype != torch.float32 or w.device != self.device or tuple(w.shape) != self.N:
+            raise TypeError(f"w must be float32 {self.N} on {self.device}")
+        M = int(t.shape[0])
+        if t0 is None or t1 is None:
+            lo, hi = (float(t.min()), float(t.max())) if M else (0.0, 0.0)
+            t0 = lo if t0 is None else t0
+            t1 = hi if t1 is None else t1
+        b = torch.empty((int(L), M), dtype=torch.complex64, device=self.device)
+        c = torch.empty((int(L),) + self.N, dtype=torch.complex64, device=self.device)
+        tt, ww = t.contiguous(), w.contiguous()
+        npix = 1
+        for n in self.N:
+            npix *= n
+        check(_lib.lib().kbn_field_segments(M, _ptr(tt), float(t0), float(t1), npix, _ptr(ww), int(L),
+                                            _ptr(b), _ptr(c), _stream(self.device)), "kbn_field_segments")
+        return b, c
+
     def info(self) -> dict:
         K = (ctypes.c_int64 * 3)()
         T = (ctypes.c_int * 3)()

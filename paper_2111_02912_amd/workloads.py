@@ -112,6 +112,32 @@ def sense_maps(C: int, N) -> np.ndarray:
     return out
 
 
+def field_map(N, peak_hz: float = 60.0, seed: int = 0) -> np.ndarray:
+    """Smooth off-resonance map in rad/s (float32 [*N]): a positive and a
+    negative Gaussian bump (width 0.2 max N) at seeded positions plus a
+    linear ramp along axis 0, scaled so that the largest |w| is 2 pi peak_hz
+    (a shimmed head at 3 T has tens of Hz)."""
+    N = tuple(int(n) for n in N)
+    g = rng(seed)
+    grids = np.meshgrid(*[np.arange(n, dtype=np.float64) - n // 2 for n in N], indexing="ij")
+    width = 0.2 * max(N)
+    out = 0.3 * grids[0] / max(1, N[0] // 2)
+    for sign in (1.0, -1.0):
+        centre = [g.uniform(-0.3, 0.3) * n for n in N]
+        d2 = sum((x - p) ** 2 for x, p in zip(grids, centre))
+        out = out + sign * np.exp(-d2 / (2.0 * width * width))
+    out = out / max(1e-12, np.abs(out).max())
+    return (2.0 * math.pi * peak_hz * out).astype(np.float32)
+
+
+def readout_times(interleaves: int, samples: int, dwell: float = 4e-6, t0: float = 0.0) -> np.ndarray:
+    """Readout time of every sample (float32 [interleaves * samples], s):
+    each interleave is read out from t0 with a constant dwell time, matching
+    the sample order of ``spiral_2d`` and ``radial_2d``."""
+    s = t0 + dwell * np.arange(samples, dtype=np.float64)
+    return np.tile(s, interleaves).astype(np.float32)
+
+
 # ---------------------------------------------------------------------------
 # Named workloads (sizes of the paper-shaped configurations)
 # ---------------------------------------------------------------------------
