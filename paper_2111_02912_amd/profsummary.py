@@ -1,6 +1,7 @@
 """Turn rocprofv3 CSV output into the short text summaries kept under profiles/.
 
   python -m paper_2111_02912_amd.profsummary stats KERNEL_STATS_CSV --cmd "..."
+  python -m paper_2111_02912_amd.profsummary bench BENCH_OUTPUT --cmd "..." --title "..."
   python -m paper_2111_02912_amd.profsummary pmc FETCH_CSV WRITE_CSV --calib-bytes N
          --cmd-fetch "..." --cmd-write "..." [--json OUT.json]
 
@@ -138,9 +139,55 @@ def pmc(fetch_csv, write_csv, calib_bytes, cmd_f, cmd_w, json_out=None, steps=1)
     return "\n".join(out) + "\n"
 
 
+def _fmt(v, indent=2):
+    pad = " " * indent
+    if isinstance(v, dict):
+        lines = []
+        for k, x in v.items():
+            if isinstance(x, dict):
+                lines.append(f"{pad}{k}:")
+                lines.extend(_fmt(x, indent + 2))
+            else:
+                lines.append(f"{pad}{k}: {_num(x)}")
+        return lines
+    return [f"{pad}{_num(v)}"]
+
+
+def _num(x):
+    if isinstance(x, float):
+        return f"{x:.6g}"
+    if isinstance(x, list):
+        return "[" + ", ".join(_num(e) for e in x) + "]"
+    return str(x)
+
+
+def bench(path: str, cmd: str, title: str) -> str:
+    """Text summary of the last JSON line a bench.py run printed."""
+    lines = [ln for ln in open(path).read().splitlines() if ln.strip().startswith("{")]
+    d = json.loads(lines[-1])
+    out = [title, f"command: {cmd}", f"source hash: {sources_hash()}", ""]
+    head = ("metric", "value", "unit", "ms_per_step", "steps", "warmup", "dtype", "vs_baseline")
+    for k in head:
+        if k in d:
+            out.append(f"{k}: {_num(d[k])}")
+    for k, v in d.items():
+        if k in head or k in ("n_gpus", "higher_is_better", "scaling", "data"):
+            continue
+        if isinstance(v, dict):
+            out.append(f"{k}:")
+            out.extend(_fmt(v))
+        else:
+            out.append(f"{k}: {_num(v)}")
+    return "\n".join(out) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="mode", required=True)
+    bsub = sub.add_parser("bench")
+    bsub.add_argument("json")
+    bsub.add_argument("--cmd", required=True)
+    bsub.add_argument("--title", required=True)
     s = sub.add_parser("stats")
     s.add_argument("csv")
     s.add_argument("--cmd", required=True)
@@ -153,7 +200,9 @@ def main():
     p.add_argument("--json")
     p.add_argument("--steps", type=int, default=1, help="steps (incl. warm-up) in the counted run")
     a = ap.parse_args()
-    if a.mode == "stats":
+    if a.mode == "bench":
+        sys.stdout.write(bench(a.json, a.cmd, a.title))
+    elif a.mode == "stats":
         sys.stdout.write(stats(a.csv, a.cmd))
     else:
         sys.stdout.write(pmc(a.fetch_csv, a.write_csv, a.calib_bytes, a.cmd_fetch, a.cmd_write, a.json,
