@@ -33,8 +33,13 @@ Other workloads (one JSON line each, not the default):
                      one radial spoke, images 40^2 and 400^2, plus the
                      memory case 200 x 200 x 100.
 
+  --workload learn   trajectory learning as in Sec. IV-B: 320x320, mini-batch
+                     12, 8 coils, 16 shots x 1280 samples on 40 quadratic
+                     spline kernels, CG-SENSE (20 iterations) through the
+                     inverse layer, gradient/slew penalties, one Adam step.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B]
-                       [--workload step|batch|train|serve|jacobian]
+                       [--workload step|batch|train|serve|jacobian|learn]
 """
 from __future__ import annotations
 
@@ -372,6 +377,37 @@ def bench_jacobian(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_learn(args):
+    """One Adam step of trajectory learning per step (Sec. IV-B sizes)."""
+    import numpy as np
+    import torch
+
+    from paper_2111_02912_amd import workloads as W
+    from paper_2111_02912_amd.learn import TrajectoryLearner
+
+    dev = torch.device("cuda", 0)
+    N, B, C = (320, 320), 12, 8
+    x = torch.from_numpy(W.complex_normal((B,) + N, 8901)).to(dev)
+    smaps = torch.from_numpy(W.sense_maps(C, N)).to(dev)
+    tl = TrajectoryLearner(N, shots=16, samples=1280, knots=40, lam=1e-3, cg_iters=20, lr=1e-4,
+                           accuracy=args.accuracy, device=dev)
+    hist = []
+    ms = _wall_ms(lambda: hist.append(tl.step(x, smaps)), args.steps, args.warmup)
+    out = {
+        "metric": "trajectory-learning Adam step, images/s",
+        "value": B / (ms * 1e-3), "unit": "images/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": ("trajectory learning: 320x320, mini-batch 12, 8 coils, 16 shots x 1280 "
+                                "samples (40 quadratic spline kernels per shot, radial start), CG-SENSE "
+                                "lambda 1e-3 with 20 CG iterations through the inverse layer, gradient "
+                                "5 G/cm and slew 15 G/cm/ms soft limits (mu 10), Adam lr 1e-4"),
+                   "sigma": tl.plan.opts["sigma"], "J": tl.plan.opts["J"]},
+        "loss_first_last": [hist[0][0], hist[-1][0]] if hist else None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def serve_pool(dev, n2d, n3d, coils=8, seed=5001):
     """Resident problems: square 2D spirals and 96^3 kooshballs with
     Gaussian-bump maps and noiseless data y = E x_true."""
@@ -489,7 +525,7 @@ def main():
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-images", type=int, default=2)
-    ap.add_argument("--workload", choices=("step", "batch", "train", "serve", "jacobian"),
+    ap.add_argument("--workload", choices=("step", "batch", "train", "serve", "jacobian", "learn"),
                     default="step")
     ap.add_argument("--requests", type=int, default=2000, help="serve workload: measured requests")
     ap.add_argument("--warm-requests", type=int, default=100, help="serve workload: unmeasured first requests")
@@ -522,6 +558,8 @@ def main():
         return bench_train(args)
     if args.workload == "jacobian":
         return bench_jacobian(args)
+    if args.workload == "learn":
+        return bench_learn(args)
 
     import numpy as np
     import torch

@@ -229,7 +229,10 @@ int kbn_plan_destroy(kbn_plan p);
 /*
  * CG-SENSE / QPLS reconstruction (Sec. IV-B: the quadratic reconstruction
  * x = (E^H E + lambda T^H T)^{-1} E^H y solved by conjugate gradients;
- * residual ||r|| / ||b|| as in Sec. IV-A), one image, C coils.
+ * residual ||r|| / ||b|| as in Sec. IV-A), for B independent images with
+ * C coils each, solved together: every iteration applies E^H E to all B
+ * images in one forward and one adjoint call, and each image keeps its own
+ * CG scalars.
  * reg selects T: KBN_REG_IDENTITY (T = I, CG-SENSE) or KBN_REG_FINITE_DIFF
  * (QPLS: T stacks the first differences (T_d x)_j = x_{j+e_d} - x_j along
  * every image axis d, for j_d < N_d - 1; no wrap-around at the edges).
@@ -243,30 +246,34 @@ int kbn_plan_destroy(kbn_plan p);
  * needs no host synchronisation and its result does not depend on other
  * work running on the GPU.
  *
- * work: a caller-owned device buffer of kbn_cg_work_bytes bytes holding
- * the solver state between calls; its first doubles are
+ * work: a caller-owned device buffer of kbn_cg_work_bytes(p, B, C) bytes
+ * holding the solver state between calls; it starts with 32 doubles per
+ * image (image b at doubles 32 b ..):
  *   [0] r'r  [1] b'b  [2] p'q  [3] alpha  [4] beta
  *   [5] ||r|| / ||b|| (0 if b = 0)  [6] iterations done
  * kbn_cg_begin sets x = 0 and the state for y; kbn_cg_step runs `iters`
- * more iterations (calls may be split, e.g. one iteration at a time).
- * x: c64 [N..]; y: c64 [C][M]; smaps: c64 [C][N..] or NULL (C = 1).
+ * more iterations (calls may be split, e.g. one iteration at a time; B and
+ * C must stay those of the begin call).
+ * x: c64 [B][N..]; y: c64 [B][C][M]; smaps: c64 [C][N..] or NULL (C = 1).
  * The same plan's points must stay set between begin and the last step.
- * Errors: INVALID_ARG (null pointers, C < 1, iters < 0, lambda < 0 or
- * not finite, unknown reg), NO_POINTS, OOM/HIP (workspace growth, launches).
+ * Errors: INVALID_ARG (null pointers, B outside 1..65535, C < 1, iters < 0,
+ * lambda < 0 or not finite, unknown reg), NO_POINTS, OOM/HIP (workspace
+ * growth, launches).
  */
-int kbn_cg_work_bytes(kbn_plan p, int C, int64_t *bytes);
-int kbn_cg_begin(kbn_plan p, int C, const void *smaps, const void *y, void *x, void *work,
+int kbn_cg_work_bytes(kbn_plan p, int B, int C, int64_t *bytes);
+int kbn_cg_begin(kbn_plan p, int B, int C, const void *smaps, const void *y, void *x, void *work,
                  void *stream);
-int kbn_cg_step(kbn_plan p, int C, const void *smaps, double lambda, int reg, int iters, void *x,
-                void *work, void *stream);
+int kbn_cg_step(kbn_plan p, int B, int C, const void *smaps, double lambda, int reg, int iters,
+                void *x, void *work, void *stream);
 
 /*
- * Start a solve of (E^H E + lambda T^H T) x = b for an image right-hand side b
- * (c64 [N..], device) instead of b = E^H y: x = 0, r = p = b.  Used to apply
- * the regularised inverse of Sec. II-F to an image (and to its upstream
- * gradient).  Continue with kbn_cg_step.  Errors as kbn_cg_begin.
+ * Start a solve of (E^H E + lambda T^H T) x = b for image right-hand sides b
+ * (c64 [B][N..], device) instead of b = E^H y: x = 0, r = p = b.  Used to
+ * apply the regularised inverse of Sec. II-F to images (and to their
+ * upstream gradients).  Continue with kbn_cg_step.  Errors as kbn_cg_begin.
  */
-int kbn_cg_begin_image(kbn_plan p, int C, const void *b, void *x, void *work, void *stream);
+int kbn_cg_begin_image(kbn_plan p, int B, int C, const void *b, void *x, void *work,
+                       void *stream);
 
 /*
  * Off-resonance (field inhomogeneity) model, Sec. II-H.  The exact system

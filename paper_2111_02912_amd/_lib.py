@@ -112,10 +112,10 @@ def lib():
     L.kbn_batch_capture.argtypes = [vp, vp]
     L.kbn_batch_launch.argtypes = [vp, vp]
     L.kbn_batch_destroy.argtypes = [vp]
-    L.kbn_cg_work_bytes.argtypes = [vp, ci, ctypes.POINTER(i64)]
-    L.kbn_cg_begin.argtypes = [vp, ci, vp, vp, vp, vp, vp]
-    L.kbn_cg_step.argtypes = [vp, ci, vp, ctypes.c_double, ci, ci, vp, vp, vp]
-    L.kbn_cg_begin_image.argtypes = [vp, ci, vp, vp, vp, vp]
+    L.kbn_cg_work_bytes.argtypes = [vp, ci, ci, ctypes.POINTER(i64)]
+    L.kbn_cg_begin.argtypes = [vp, ci, ci, vp, vp, vp, vp, vp]
+    L.kbn_cg_step.argtypes = [vp, ci, ci, vp, ctypes.c_double, ci, ci, vp, vp, vp]
+    L.kbn_cg_begin_image.argtypes = [vp, ci, ci, vp, vp, vp, vp]
     L.kbn_field_forward.argtypes = [vp, ci, ci, ci, vp, vp, vp, vp, vp, vp]
     L.kbn_field_adjoint.argtypes = [vp, ci, ci, ci, vp, vp, vp, vp, vp, vp]
     L.kbn_field_jac_omega_fwd.argtypes = [vp, ci, ci, ci, vp, vp, vp, vp, vp, vp, ci, vp]

@@ -1,7 +1,9 @@
 // Conjugate-gradient vector kernels for the quadratic reconstruction
 // (E^H E + lambda T^H T) x = b of Sec. IV-B: T = I (CG-SENSE) or T = the
 // first differences along each image axis (QPLS), zero beyond the image
-// edge; residual norm ||r|| / ||b|| of Sec. IV-A.
+// edge; residual norm ||r|| / ||b|| of Sec. IV-A.  A launch serves a batch
+// of independent images: one grid row per image, each with its own partial
+// sums and scalars.
 //
 // Inner products are reduced deterministically: a fixed grid for a given
 // length, one FP64 partial per block in a fixed tree order, then one block
@@ -31,6 +33,11 @@ __global__ __launch_bounds__(TPB) void k_cg_init(float2 *__restrict__ x, const f
                                                  float2 *__restrict__ p, int64_t n,
                                                  double *__restrict__ part) {
     __shared__ double sh[TPB];
+    const int64_t im = blockIdx.y;  // image of this block
+    x += im * n;
+    r += im * n;
+    p += im * n;
+    part += im * KBN_CG_MAXPARTS;
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
         const float2 v = r[i];
@@ -46,6 +53,10 @@ __global__ __launch_bounds__(TPB) void k_cg_init(float2 *__restrict__ x, const f
 __global__ __launch_bounds__(TPB) void k_cg_q(float2 *__restrict__ q, const float2 *__restrict__ p,
                                               float lam, int64_t n, double *__restrict__ part) {
     __shared__ double sh[TPB];
+    const int64_t im = blockIdx.y;  // image of this block
+    q += im * n;
+    p += im * n;
+    part += im * KBN_CG_MAXPARTS;
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
         const float2 pv = p[i];
@@ -66,6 +77,10 @@ __global__ __launch_bounds__(TPB) void k_cg_q_fd(float2 *__restrict__ q, const f
                                                  float lam, int n0, int n1, int n2, int64_t n,
                                                  double *__restrict__ part) {
     __shared__ double sh[TPB];
+    const int64_t im = blockIdx.y;  // image of this block
+    q += im * n;
+    p += im * n;
+    part += im * KBN_CG_MAXPARTS;
     const int64_t s0 = (int64_t)n1 * n2;
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
@@ -98,6 +113,13 @@ __global__ __launch_bounds__(TPB) void k_cg_xr(float2 *__restrict__ x, float2 *_
                                                const double *__restrict__ scal, int64_t n,
                                                double *__restrict__ part) {
     __shared__ double sh[TPB];
+    const int64_t im = blockIdx.y;  // image of this block
+    x += im * n;
+    r += im * n;
+    p += im * n;
+    q += im * n;
+    scal += im * KBN_CG_NSCAL;
+    part += im * KBN_CG_MAXPARTS;
     const float a = (float)scal[KBN_CG_ALPHA];
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
@@ -118,6 +140,10 @@ __global__ __launch_bounds__(TPB) void k_cg_xr(float2 *__restrict__ x, float2 *_
 // p = r + beta p
 __global__ __launch_bounds__(TPB) void k_cg_p(float2 *__restrict__ p, const float2 *__restrict__ r,
                                               const double *__restrict__ scal, int64_t n) {
+    const int64_t im = blockIdx.y;  // image of this block
+    p += im * n;
+    r += im * n;
+    scal += im * KBN_CG_NSCAL;
     const float b = (float)scal[KBN_CG_BETA];
     for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
         const float2 rv = r[i];
@@ -136,6 +162,9 @@ __global__ __launch_bounds__(TPB) void k_cg_p(float2 *__restrict__ p, const floa
 __global__ __launch_bounds__(TPB) void k_cg_scalars(const double *__restrict__ part, int nparts,
                                                     double *__restrict__ scal, int stage) {
     __shared__ double sh[TPB];
+    const int64_t im = blockIdx.x;  // one block per image
+    part += im * KBN_CG_MAXPARTS;
+    scal += im * KBN_CG_NSCAL;
     double acc = 0.0;
     for (int i = threadIdx.x; i < nparts; i += TPB) acc += part[i];
     const double s = block_sum(acc, sh);
@@ -169,29 +198,32 @@ int kbn_cg_nparts(int64_t n) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(b, KBN_CG_MAXPARTS));
 }
 
-hipError_t kbn_launch_cg(int kind, int64_t n, float2 *x, float2 *r, float2 *p, float2 *q, float lam,
-                         KbnCgImage img, double *scal, double *part, hipStream_t s) {
+hipError_t kbn_launch_cg(int kind, int nimg, int64_t n, float2 *x, float2 *r, float2 *p, float2 *q,
+                         float lam, KbnCgImage img, double *scal, double *part, hipStream_t s) {
+    // one grid row per image; partials [nimg][KBN_CG_MAXPARTS], scalars [nimg][KBN_CG_NSCAL]
+    if (nimg < 1 || nimg > 65535) return hipErrorInvalidValue;
     const int g = kbn_cg_nparts(n);
+    const dim3 grid(g, nimg), gs(nimg);
     switch (kind) {
     case KBN_CGK_INIT:
-        k_cg_init<<<dim3(g), dim3(TPB), 0, s>>>(x, r, p, n, part);
-        k_cg_scalars<<<dim3(1), dim3(TPB), 0, s>>>(part, g, scal, 0);
+        k_cg_init<<<grid, dim3(TPB), 0, s>>>(x, r, p, n, part);
+        k_cg_scalars<<<gs, dim3(TPB), 0, s>>>(part, g, scal, 0);
         break;
     case KBN_CGK_Q:
         if (img.reg == KBN_REG_FINITE_DIFF) {
             if ((int64_t)img.n0 * img.n1 * img.n2 != n) return hipErrorInvalidValue;
-            k_cg_q_fd<<<dim3(g), dim3(TPB), 0, s>>>(q, p, lam, img.n0, img.n1, img.n2, n, part);
+            k_cg_q_fd<<<grid, dim3(TPB), 0, s>>>(q, p, lam, img.n0, img.n1, img.n2, n, part);
         } else {
-            k_cg_q<<<dim3(g), dim3(TPB), 0, s>>>(q, p, lam, n, part);
+            k_cg_q<<<grid, dim3(TPB), 0, s>>>(q, p, lam, n, part);
         }
-        k_cg_scalars<<<dim3(1), dim3(TPB), 0, s>>>(part, g, scal, 1);
+        k_cg_scalars<<<gs, dim3(TPB), 0, s>>>(part, g, scal, 1);
         break;
     case KBN_CGK_XR:
-        k_cg_xr<<<dim3(g), dim3(TPB), 0, s>>>(x, r, p, q, scal, n, part);
-        k_cg_scalars<<<dim3(1), dim3(TPB), 0, s>>>(part, g, scal, 2);
+        k_cg_xr<<<grid, dim3(TPB), 0, s>>>(x, r, p, q, scal, n, part);
+        k_cg_scalars<<<gs, dim3(TPB), 0, s>>>(part, g, scal, 2);
         break;
     case KBN_CGK_P:
-        k_cg_p<<<dim3(g), dim3(TPB), 0, s>>>(p, r, scal, n);
+        k_cg_p<<<grid, dim3(TPB), 0, s>>>(p, r, scal, n);
         break;
     default:
         return hipErrorInvalidValue;

@@ -249,5 +249,6 @@ struct KbnCgImage {
     int reg;  // KBN_REG_IDENTITY or KBN_REG_FINITE_DIFF
     int n0, n1, n2;
 };
-hipError_t kbn_launch_cg(int kind, int64_t n, float2 *x, float2 *r, float2 *p, float2 *q, float lam,
-                         KbnCgImage img, double *scal, double *part, hipStream_t s);
+#define KBN_CG_MAXB 65535  // images per CG launch (grid rows)
+hipError_t kbn_launch_cg(int kind, int nimg, int64_t n, float2 *x, float2 *r, float2 *p, float2 *q,
+                         float lam, KbnCgImage img, double *scal, double *part, hipStream_t s);

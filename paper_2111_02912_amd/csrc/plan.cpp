@@ -857,7 +857,8 @@ int kbn_jac_x(kbn_plan p, int op, int B, int C, const void *g, const void *smaps
     return fail(KBN_ERR_INVALID_ARG, "unknown op");
 }
 
-// CG work buffer: scalars, block partials, r, p, q (images), E p (k-space)
+// CG work buffer for B images: scalars [B][KBN_CG_NSCAL], block partials
+// [B][KBN_CG_MAXPARTS], r, p, q (images [B][N..]), E p (k-space [B][C][M])
 struct CgBufs {
     double *scal, *part;
     float2 *r, *p, *q, *ytmp;
@@ -865,14 +866,14 @@ struct CgBufs {
 
 static int64_t cg_align(int64_t b) { return (b + 255) / 256 * 256; }
 
-static int64_t cg_bytes(kbn_plan p, int C, CgBufs *b, void *work) {
+static int64_t cg_bytes(kbn_plan p, int B, int C, CgBufs *b, void *work) {
     int64_t npix = 1;
     for (int d = 0; d < p->D; ++d) npix *= p->N[d];
-    const int64_t o_part = cg_align(KBN_CG_NSCAL * 8);
-    const int64_t o_r = o_part + cg_align(KBN_CG_MAXPARTS * 8);
-    const int64_t img = cg_align(npix * 8);
+    const int64_t o_part = cg_align((int64_t)B * KBN_CG_NSCAL * 8);
+    const int64_t o_r = o_part + cg_align((int64_t)B * KBN_CG_MAXPARTS * 8);
+    const int64_t img = cg_align((int64_t)B * npix * 8);
     const int64_t o_y = o_r + 3 * img;
-    const int64_t total = o_y + cg_align(std::max<int64_t>(p->M, 0) * C * 8);
+    const int64_t total = o_y + cg_align(std::max<int64_t>(p->M, 0) * C * B * 8);
     if (b) {
         char *w = (char *)work;
         b->scal = (double *)w;
@@ -885,57 +886,70 @@ static int64_t cg_bytes(kbn_plan p, int C, CgBufs *b, void *work) {
     return total;
 }
 
-static int cg_launch(kbn_plan p, int kind, int64_t n, float2 *x, const CgBufs &b, float lam, int reg,
+static int cg_launch(kbn_plan p, int kind, int B, int64_t n, float2 *x, const CgBufs &b, float lam, int reg,
                      hipStream_t s) {
     KbnCgImage img{reg, 1, 1, 1};
     int *ext[3] = {&img.n0, &img.n1, &img.n2};
     for (int d = 0; d < p->D; ++d) *ext[d] = (int)p->N[d];
-    return launched(kbn_launch_cg(kind, n, x, b.r, b.p, b.q, lam, img, b.scal, b.part, s),
+    return launched(kbn_launch_cg(kind, B, n, x, b.r, b.p, b.q, lam, img, b.scal, b.part, s),
                     "cg vector kernel", s);
 }
 
-int kbn_cg_work_bytes(kbn_plan p, int C, int64_t *bytes) {
-    if (!p || !bytes) return fail(KBN_ERR_INVALID_ARG, "null argument");
-    if (p->M < 0) return fail(KBN_ERR_NO_POINTS, "kbn_set_points has not been called");
-    if (C < 1) return fail(KBN_ERR_INVALID_ARG, "C must be >= 1");
-    *bytes = cg_bytes(p, C, nullptr, nullptr);
+static int cg_check_batch(int B) {
+    if (B < 1 || B > KBN_CG_MAXB) return fail(KBN_ERR_INVALID_ARG, "B must be in 1..65535");
     return KBN_OK;
 }
 
-int kbn_cg_begin(kbn_plan p, int C, const void *smaps, const void *y, void *x, void *work,
+int kbn_cg_work_bytes(kbn_plan p, int B, int C, int64_t *bytes) {
+    if (!p || !bytes) return fail(KBN_ERR_INVALID_ARG, "null argument");
+    if (p->M < 0) return fail(KBN_ERR_NO_POINTS, "kbn_set_points has not been called");
+    if (C < 1) return fail(KBN_ERR_INVALID_ARG, "C must be >= 1");
+    int rc = cg_check_batch(B);
+    if (rc != KBN_OK) return rc;
+    *bytes = cg_bytes(p, B, C, nullptr, nullptr);
+    return KBN_OK;
+}
+
+int kbn_cg_begin(kbn_plan p, int B, int C, const void *smaps, const void *y, void *x, void *work,
                  void *stream_) {
-    int rc = check_common(p, 1, C, x, smaps, y);
+    int rc = cg_check_batch(B);
+    if (rc != KBN_OK) return rc;
+    rc = check_common(p, B, C, x, smaps, y);
     if (rc != KBN_OK) return rc;
     if (!work) return fail(KBN_ERR_INVALID_ARG, "null work buffer");
     hipStream_t stream = (hipStream_t)stream_;
     CgBufs b;
-    cg_bytes(p, C, &b, work);
+    cg_bytes(p, B, C, &b, work);
     int64_t npix = 1;
     for (int d = 0; d < p->D; ++d) npix *= p->N[d];
     // r = b = E^H y (x0 = 0), p = r
-    rc = run_type1(p, 1, C, (const float2 *)y, (const float2 *)smaps, b.r, stream);
+    rc = run_type1(p, B, C, (const float2 *)y, (const float2 *)smaps, b.r, stream);
     if (rc != KBN_OK) return rc;
-    return cg_launch(p, KBN_CGK_INIT, npix, (float2 *)x, b, 0.f, KBN_REG_IDENTITY, stream);
+    return cg_launch(p, KBN_CGK_INIT, B, npix, (float2 *)x, b, 0.f, KBN_REG_IDENTITY, stream);
 }
 
-int kbn_cg_begin_image(kbn_plan p, int C, const void *b, void *x, void *work, void *stream_) {
+int kbn_cg_begin_image(kbn_plan p, int B, int C, const void *b, void *x, void *work, void *stream_) {
     if (!p) return fail(KBN_ERR_INVALID_ARG, "null plan");
     if (p->M < 0) return fail(KBN_ERR_NO_POINTS, "kbn_set_points has not been called");
     if (C < 1) return fail(KBN_ERR_INVALID_ARG, "C must be >= 1");
+    int rc = cg_check_batch(B);
+    if (rc != KBN_OK) return rc;
     if (!b || !x || !work) return fail(KBN_ERR_INVALID_ARG, "null pointer");
     hipStream_t stream = (hipStream_t)stream_;
     CgBufs cb;
-    cg_bytes(p, C, &cb, work);
+    cg_bytes(p, B, C, &cb, work);
     int64_t npix = 1;
     for (int d = 0; d < p->D; ++d) npix *= p->N[d];
     // r = b (x0 = 0), p = r
-    KBN_HIP(hipMemcpyAsync(cb.r, b, sizeof(float2) * npix, hipMemcpyDeviceToDevice, stream));
-    return cg_launch(p, KBN_CGK_INIT, npix, (float2 *)x, cb, 0.f, KBN_REG_IDENTITY, stream);
+    KBN_HIP(hipMemcpyAsync(cb.r, b, sizeof(float2) * npix * B, hipMemcpyDeviceToDevice, stream));
+    return cg_launch(p, KBN_CGK_INIT, B, npix, (float2 *)x, cb, 0.f, KBN_REG_IDENTITY, stream);
 }
 
-int kbn_cg_step(kbn_plan p, int C, const void *smaps, double lambda, int reg, int iters, void *x,
+int kbn_cg_step(kbn_plan p, int B, int C, const void *smaps, double lambda, int reg, int iters, void *x,
                 void *work, void *stream_) {
-    int rc = check_common(p, 1, C, x, smaps, work);
+    int rc = cg_check_batch(B);
+    if (rc != KBN_OK) return rc;
+    rc = check_common(p, B, C, x, smaps, work);
     if (rc != KBN_OK) return rc;
     if (!work) return fail(KBN_ERR_INVALID_ARG, "null work buffer");
     if (iters < 0) return fail(KBN_ERR_INVALID_ARG, "iters must be >= 0");
@@ -944,21 +958,21 @@ int kbn_cg_step(kbn_plan p, int C, const void *smaps, double lambda, int reg, in
         return fail(KBN_ERR_INVALID_ARG, "reg must be KBN_REG_IDENTITY or KBN_REG_FINITE_DIFF");
     hipStream_t stream = (hipStream_t)stream_;
     CgBufs b;
-    cg_bytes(p, C, &b, work);
+    cg_bytes(p, B, C, &b, work);
     int64_t npix = 1;
     for (int d = 0; d < p->D; ++d) npix *= p->N[d];
     for (int it = 0; it < iters; ++it) {
-        // q = E^H E p (+ lambda T^H T p in the vector kernel)
+        // q = E^H E p for every image (+ lambda T^H T p in the vector kernel)
         if (p->M > 0) {
-            rc = run_type2(p, 1, C, 1, 0, b.p, (const float2 *)smaps, 0, b.ytmp, nullptr, nullptr, 0,
+            rc = run_type2(p, B, C, 1, 0, b.p, (const float2 *)smaps, 0, b.ytmp, nullptr, nullptr, 0,
                            stream);
             if (rc != KBN_OK) return rc;
         }
-        rc = run_type1(p, 1, C, b.ytmp, (const float2 *)smaps, b.q, stream);
+        rc = run_type1(p, B, C, b.ytmp, (const float2 *)smaps, b.q, stream);
         if (rc != KBN_OK) return rc;
-        rc = cg_launch(p, KBN_CGK_Q, npix, (float2 *)x, b, (float)lambda, reg, stream);
-        if (rc == KBN_OK) rc = cg_launch(p, KBN_CGK_XR, npix, (float2 *)x, b, 0.f, reg, stream);
-        if (rc == KBN_OK) rc = cg_launch(p, KBN_CGK_P, npix, (float2 *)x, b, 0.f, reg, stream);
+        rc = cg_launch(p, KBN_CGK_Q, B, npix, (float2 *)x, b, (float)lambda, reg, stream);
+        if (rc == KBN_OK) rc = cg_launch(p, KBN_CGK_XR, B, npix, (float2 *)x, b, 0.f, reg, stream);
+        if (rc == KBN_OK) rc = cg_launch(p, KBN_CGK_P, B, npix, (float2 *)x, b, 0.f, reg, stream);
         if (rc != KBN_OK) return rc;
     }
     return KBN_OK;

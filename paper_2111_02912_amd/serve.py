@@ -269,8 +269,8 @@ class GpuExecutor:
         plan, solver = req.handle
         p = req.problem
         with torch.cuda.stream(self.streams[req.lane]):
-            rel = solver.scalars()[5:6].clone()
-        req.result = {"x": solver.x if self.keep_results else None, "rel": rel}
+            rel = solver.scalars()[0, 5:6].clone()
+        req.result = {"x": solver.x[0] if self.keep_results else None, "rel": rel}
         req.handle = None
         self.held -= self.state_size(p)
         self.idle.setdefault(p.pid, []).append(plan)

@@ -142,10 +142,10 @@ def test_unknown_regulariser_rejected(dev):
     s = CgSense(plan, smaps.shape[0]).begin(_c(y, dev), _c(smaps, dev))
     with pytest.raises(ValueError):
         s.step(1, 1e-3, reg="tv")
-    rc = _lib.lib().kbn_cg_step(plan._h, s.C, _ptr(s._keep[1]), 1e-3, 7, 1, _ptr(s.x), _ptr(s.work),
+    rc = _lib.lib().kbn_cg_step(plan._h, 1, s.C, _ptr(s._keep[1]), 1e-3, 7, 1, _ptr(s.x), _ptr(s.work),
                                 _stream(dev))
     assert rc == _lib.KBN_ERR_INVALID_ARG
-    assert float(s.scalars()[6].item()) == 0.0
+    assert float(s.scalars()[0, 6].item()) == 0.0
 
 
 @pytest.mark.parametrize("kind,seed,reg,lam", [("spiral", 8051, "identity", 1e-3),
@@ -179,8 +179,32 @@ def test_split_steps_are_bit_identical(dev):
     b = CgSense(plan, smaps.shape[0]).begin(yt, st).step(4).step(0).step(6)
     torch.cuda.synchronize()
     assert torch.equal(a.x, b.x)
-    assert torch.equal(a.scalars()[:7], b.scalars()[:7])
-    assert float(a.scalars()[6].item()) == 10.0
+    assert torch.equal(a.scalars()[:, :7], b.scalars()[:, :7])
+    assert float(a.scalars()[0, 6].item()) == 10.0
+
+
+def test_batched_solve_equals_separate_solves(dev):
+    """Three images solved together (one E^H E call per iteration for all,
+    per-image scalars) give the same bits as three separate solves: every
+    kernel treats images independently and reduces each image in a fixed
+    order.  One image of the batch has zero data and must stay at zero."""
+    from paper_2111_02912_amd.cg import CgSense, cg_sense
+    from paper_2111_02912_amd.nufft import KbNufft
+    N, om, smaps, y = _problem("2d", 8601)
+    ys = [y, np.zeros_like(y), ndft.sense_forward(om, W.complex_normal(N, 8602)[None], N, smaps)[0]]
+    yb = _c(np.stack(ys).astype(np.complex64), dev)
+    plan = KbNufft(N, device=dev)
+    plan.set_points(_f(om, dev))
+    st = _c(smaps, dev)
+    for reg, lam in (("identity", 1e-3), ("finite_diff", 10.0)):
+        xb, rb = cg_sense(plan, yb, st, lam=lam, iters=10, reg=reg)
+        for i in range(3):
+            xi, ri = cg_sense(plan, yb[i], st, lam=lam, iters=10, reg=reg)
+            assert torch.equal(xb[i], xi), (reg, i)
+            assert float(rb[i]) == ri
+        assert not torch.any(xb[1] != 0) and float(rb[1]) == 0.0
+    s = CgSense(plan, smaps.shape[0], 3).begin(yb, st).step(4)
+    assert s.scalars().shape == (3, 8) and torch.all(s.scalars()[:, 6] == 4.0)
 
 
 def test_zero_data_gives_zero(dev):
