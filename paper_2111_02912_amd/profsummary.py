@@ -60,13 +60,18 @@ def kernel_class(name: str):
     return None
 
 
+# sources of the NUFFT kernels, their launch configuration and the plan
+# (the CG, off-resonance and batch sources do not affect those kernels)
+NUFFT_SOURCES = ("kbn_internal.h", "kbn_window.h", "plan.cpp", "points.hip", "fft.hip", "fft_fast.hip",
+                 "interp.hip")
+
+
 def sources_hash() -> str:
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".cpp", ".h")):
-            with open(os.path.join(CSRC, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
+    for name in NUFFT_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
