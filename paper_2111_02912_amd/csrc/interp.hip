@@ -31,9 +31,12 @@ namespace {
 // one tile).  Channels are taken CP at a time (CP = 2 or 4): their grid
 // regions (tile plus the tap reach) are loaded into LDS interleaved, with
 // coalesced reads, and every thread interpolates its point for all CP
-// channels from LDS, one 16-byte read per tap and channel pair.  Subproblems
+// channels from LDS, one 16-byte read per tap and channel pair.  With LA the
+// region of the next CP channels is loaded into registers while the current
+// ones are interpolated (each thread keeps the grid offsets of its region
+// cells, computed once), so the grid reads overlap the interpolation.  Subproblems
 // of the extra tile id ntiles hold the flagged points, whose outputs are NaN.
-template <int D, int J, int MODE, int CP>
+template <int D, int J, int MODE, int CP, bool LA>
 __global__ void __launch_bounds__(KBN_BLOCK) k_gather_staged(KbnGeom g, KbnGatherArgs a, int cg) {
     constexpr int H = CP / 2;  // float4 (channel pairs) per region cell
     extern __shared__ float4 reg4[];
@@ -94,27 +97,84 @@ __global__ void __launch_bounds__(KBN_BLOCK) k_gather_staged(KbnGeom g, KbnGathe
         }
     }
     float jac[KBN_MAX_D] = {0.f, 0.f, 0.f};
-    for (int ch = ch0; ch < ch1; ch += CP) {
-        const int nc = min(CP, ch1 - ch);
-        for (int i = threadIdx.x; i < R; i += KBN_BLOCK) {
-            int rem = i;
-            int64_t gi = 0, gstride = 1;
+    // LA: region cells of this thread and their grid offsets (the same for
+    // every channel), and the next channel group's region loaded ahead
+    constexpr int MAXC = LA ? (48 * 1024 / (CP * 8) + KBN_BLOCK - 1) / KBN_BLOCK : 1;
+    int goff[MAXC];
+    float4 pre[MAXC][H];
+    auto fetch = [&](int chb) {
+        const int nc = min(CP, ch1 - chb);
+#pragma unroll
+        for (int k = 0; k < MAXC; ++k) {
+            const int i = (int)threadIdx.x + k * KBN_BLOCK;
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                float2 v0 = make_float2(0.f, 0.f), v1 = v0;
+                if (i < R) {
+                    if (2 * h < nc) v0 = a.grid[(int64_t)(chb + 2 * h) * a.gsize + goff[k]];
+                    if (2 * h + 1 < nc) v1 = a.grid[(int64_t)(chb + 2 * h + 1) * a.gsize + goff[k]];
+                }
+                pre[k][h] = make_float4(v0.x, v0.y, v1.x, v1.y);
+            }
+        }
+    };
+    if constexpr (LA) {
+#pragma unroll
+        for (int k = 0; k < MAXC; ++k) {
+            const int i = (int)threadIdx.x + k * KBN_BLOCK;
+            int rem = i < R ? i : 0;
+            int gi = 0, gstride = 1;
 #pragma unroll
             for (int d = D - 1; d >= 0; --d) {
                 const int e = rem % E[d];
                 rem /= E[d];
-                gi += (int64_t)wrapk(o[d] + e, g.K[d]) * gstride;
+                gi += wrapk(o[d] + e, g.K[d]) * gstride;
                 gstride *= g.K[d];
             }
+            goff[k] = gi;
+        }
+        if (ch0 < ch1) fetch(ch0);
+    }
+    for (int ch = ch0; ch < ch1; ch += CP) {
+        const int nc = min(CP, ch1 - ch);
+        if constexpr (LA) {
 #pragma unroll
-            for (int h = 0; h < H; ++h) {
-                const float2 v0 = 2 * h < nc ? a.grid[(int64_t)(ch + 2 * h) * a.gsize + gi] : make_float2(0.f, 0.f);
-                const float2 v1 =
-                    2 * h + 1 < nc ? a.grid[(int64_t)(ch + 2 * h + 1) * a.gsize + gi] : make_float2(0.f, 0.f);
-                reg4[i * H + h] = make_float4(v0.x, v0.y, v1.x, v1.y);
+            for (int k = 0; k < MAXC; ++k) {
+                const int i = (int)threadIdx.x + k * KBN_BLOCK;
+                if (i < R) {
+#pragma unroll
+                    for (int h = 0; h < H; ++h) reg4[i * H + h] = pre[k][h];
+                }
+            }
+        } else {
+            for (int i = threadIdx.x; i < R; i += KBN_BLOCK) {
+                int rem = i;
+                int64_t gi = 0, gstride = 1;
+#pragma unroll
+                for (int d = D - 1; d >= 0; --d) {
+                    const int e = rem % E[d];
+                    rem /= E[d];
+                    gi += (int64_t)wrapk(o[d] + e, g.K[d]) * gstride;
+                    gstride *= g.K[d];
+                }
+#pragma unroll
+                for (int h = 0; h < H; ++h) {
+                    const float2 v0 = 2 * h < nc ? a.grid[(int64_t)(ch + 2 * h) * a.gsize + gi] : make_float2(0.f, 0.f);
+                    const float2 v1 =
+                        2 * h + 1 < nc ? a.grid[(int64_t)(ch + 2 * h + 1) * a.gsize + gi] : make_float2(0.f, 0.f);
+                    reg4[i * H + h] = make_float4(v0.x, v0.y, v1.x, v1.y);
+                }
             }
         }
+        // upstream values of this group (mode 1), read before the next group's loads
+        float2 vv[CP];
+#pragma unroll
+        for (int k = 0; k < CP; ++k)
+            vv[k] = (MODE == 1 && act && k < nc) ? a.v[(int64_t)((ch + k) / a.nw) * a.M + q] : make_float2(0.f, 0.f);
         __syncthreads();
+        if constexpr (LA) {
+            if (ch + CP < ch1) fetch(ch + CP);
+        }
         if (act) {
             float4 acc[H];
 #pragma unroll
@@ -213,8 +273,7 @@ __global__ void __launch_bounds__(KBN_BLOCK) k_gather_staged(KbnGeom g, KbnGathe
                 if (MODE == 0) {
                     a.y[(int64_t)c * a.M + q] = make_float2(ax, ay);
                 } else {
-                    const float2 vv = a.v[(int64_t)(c / a.nw) * a.M + q];
-                    const float im = ay * vv.x - ax * vv.y;  // Im{acc conj(v)}
+                    const float im = ay * vv[k].x - ax * vv[k].y;  // Im{acc conj(v)}
                     const int wd = c % a.nw;
 #pragma unroll
                     for (int d = 0; d < D; ++d)
@@ -810,10 +869,13 @@ hipError_t gather_dj(const KbnGeom &g, const KbnGatherArgs &a, int mode, hipStre
     const KbnGatherShape sh = kbn_gather_shape(g, a.M, a.nch, a.nw);
     dim3 grid((unsigned)sh.blocks, (unsigned)sh.groups);
     if (sh.staged) {
+        // loading ahead pays in 3D (96^3 x 8 coils: 11-14%); in 2D it cost
+        // occupancy for no gain in the full step
+        constexpr bool LA = D == 3;
         if (mode == 0)
-            k_gather_staged<D, J, 0, 2><<<grid, dim3(KBN_BLOCK), sh.lds, s>>>(g, a, sh.cg);
+            k_gather_staged<D, J, 0, 2, LA><<<grid, dim3(KBN_BLOCK), sh.lds, s>>>(g, a, sh.cg);
         else
-            k_gather_staged<D, J, 1, 2><<<grid, dim3(KBN_BLOCK), sh.lds, s>>>(g, a, sh.cg);
+            k_gather_staged<D, J, 1, 2, LA><<<grid, dim3(KBN_BLOCK), sh.lds, s>>>(g, a, sh.cg);
     } else {
         if (mode == 0)
             k_gather<D, J, 0><<<grid, dim3(KBN_BLOCK), 0, s>>>(g, a, sh.cg);
