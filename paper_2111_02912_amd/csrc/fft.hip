@@ -356,7 +356,8 @@ k_last_adj(KbnLastAdjArgs a, KbnRadix rp, const float2 *__restrict__ tw, int nl)
                 const int64_t bl = line / a.R0;
                 const int row = (int)(line - bl * a.R0);
                 float2 v = buf[li * L + wrap_pos(j, Nl, L)];
-                if (a.smaps) v = cmulc(v, a.smaps[((int64_t)c * a.R0 + row) * Nl + j]);
+                const int cm = a.cmod > 0 ? (int)(bl % a.cmod) : c;
+                if (a.smaps) v = cmulc(v, a.smaps[((int64_t)cm * a.R0 + row) * Nl + j]);
                 const float f = deap_l[j] * row_factor(row, a.D, a.N, a.deap, -1);
                 acc[k].x += v.x * f;
                 acc[k].y += v.y * f;
@@ -427,6 +428,33 @@ hipError_t kbn_launch_mid_pass(const KbnMidPassArgs &a, const KbnRadix &rp, cons
         else
             k_mid_pass<16, false><<<dim3((unsigned)blocks), dim3(KBN_BLOCK), lds, s>>>(a, rp, tw, nl);
     }
+    return hipGetLastError();
+}
+
+// coil sum of the per-coil images of the split last pass, in coil order
+__global__ void __launch_bounds__(KBN_BLOCK)
+k_coil_sum(const float2 *__restrict__ ws, int64_t nb, int C, int64_t npix, float2 *__restrict__ x,
+           int accumulate) {
+    const int64_t n = nb * npix;
+    for (int64_t i = (int64_t)blockIdx.x * KBN_BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * KBN_BLOCK) {
+        const int64_t b = i / npix;
+        const int64_t j = i - b * npix;
+        float2 acc = accumulate ? x[i] : make_float2(0.f, 0.f);
+        for (int c = 0; c < C; ++c) {
+            const float2 v = ws[(b * C + c) * npix + j];
+            acc.x += v.x;
+            acc.y += v.y;
+        }
+        x[i] = acc;
+    }
+}
+
+hipError_t kbn_launch_coil_sum(const float2 *ws, int64_t nb, int C, int64_t npix, float2 *x, int accumulate,
+                               hipStream_t s) {
+    const int64_t n = nb * npix;
+    if (n <= 0) return hipSuccess;
+    const int64_t g = std::min<int64_t>((n + KBN_BLOCK - 1) / KBN_BLOCK, 65536);
+    k_coil_sum<<<dim3((unsigned)g), dim3(KBN_BLOCK), 0, s>>>(ws, nb, C, npix, x, accumulate);
     return hipGetLastError();
 }
 

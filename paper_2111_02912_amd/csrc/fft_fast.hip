@@ -430,7 +430,8 @@ __global__ void __launch_bounds__(NT) k_rows_last_adj(KbnLastAdjArgs a, const fl
             v[i] = line_ok ? in[p] : make_float2(0.f, 0.f);
         }
         if (c > 0) __syncthreads();  // previous coil's last LDS reads are done
-        const float2 *srow = a.smaps ? a.smaps + ((int64_t)c * a.R0 + row) * Nl : nullptr;
+        const int cm = a.cmod > 0 ? (int)(bl % a.cmod) : c;
+        const float2 *srow = a.smaps ? a.smaps + ((int64_t)cm * a.R0 + row) * Nl : nullptr;
         auto lds_idx = [](int pos) { return pos; };
         float2 *ldsl = lds + li * L;
         auto sink = [&](int i, int pos, float2 val) {

@@ -116,6 +116,8 @@ struct KbnLastAdjArgs {        // adjoint: IFFT along the last axis + crop + sca
     float2 *x;                 // [nb][R0][Nl] (batch offset applied)
     int64_t nlines;            // nb * R0
     int R0, Nl, C;
+    int cmod;                  // > 0: C = 1 and line block bl takes coil map bl % cmod (one
+                               // output image per image-coil pair, summed afterwards)
     int accumulate;
     int D;
     int N[KBN_MAX_D];
@@ -126,6 +128,9 @@ hipError_t kbn_launch_first_pass(const KbnFirstPassArgs &a, const KbnRadix &rp,
                                  const float2 *tw, int maxe, hipStream_t s);
 hipError_t kbn_launch_mid_pass(const KbnMidPassArgs &a, const KbnRadix &rp, const float2 *tw,
                                int inverse, int maxe, hipStream_t s);
+// x[b][j] (+)= sum_c ws[b * C + c][j] in coil order, j < npix
+hipError_t kbn_launch_coil_sum(const float2 *ws, int64_t nb, int C, int64_t npix, float2 *x, int accumulate,
+                               hipStream_t s);
 hipError_t kbn_launch_last_adj(const KbnLastAdjArgs &a, const KbnRadix &rp, const float2 *tw,
                                int maxe, hipStream_t s);
 int kbn_lines_per_block(const KbnRadix &rp, int maxe);

@@ -541,15 +541,22 @@ int run_type1(kbn_plan p, int B, int C, const float2 *y, const float2 *smaps, fl
                            kbn_launch_mid_pass(ma, p->rad[d], p->tw[d], 1, p->maxe, stream), "mid pass");
             std::swap(cur, nxt);
         }
+        // With few image rows per coil, the coil loop inside each line would
+        // leave the GPU idle: then every (image, coil) line is transformed on
+        // its own into the free buffer and the coils are summed afterwards.
+        // The choice depends only on the image shape and coil count, so the
+        // same problem gives the same bits whatever the batch size.
+        const bool split = ncc > 1 && R0 < 2048;
         KbnLastAdjArgs la;
         la.in = cur;
         la.smaps = smaps ? smaps + (int64_t)c0 * R0 * Nl : nullptr;
-        la.x = x + b0 * R0 * Nl;
-        la.nlines = nb * R0;
+        la.x = split ? nxt : x + b0 * R0 * Nl;
+        la.nlines = split ? nb * ncc * R0 : nb * R0;
         la.R0 = (int)R0;
         la.Nl = Nl;
-        la.C = ncc;
-        la.accumulate = c0 > 0 ? 1 : 0;  // later coil runs add to the image
+        la.C = split ? 1 : ncc;
+        la.cmod = split ? ncc : 0;
+        la.accumulate = (!split && c0 > 0) ? 1 : 0;  // later coil runs add to the image
         la.D = D;
         for (int d = 0; d < KBN_MAX_D; ++d) {
             la.N[d] = p->N[d];
@@ -562,6 +569,10 @@ int run_type1(kbn_plan p, int B, int C, const float2 *y, const float2 *smaps, fl
             KBN_LAUNCH(KBN_CLASS_FFT_LAST_ADJ,
                        kbn_launch_last_adj(la, p->rad[D - 1], p->tw[D - 1], p->maxe, stream),
                        "last adjoint pass");
+        if (split)
+            KBN_LAUNCH(KBN_CLASS_FFT_LAST_ADJ,
+                       kbn_launch_coil_sum(nxt, nb, ncc, R0 * Nl, x + b0 * R0 * Nl, c0 > 0 ? 1 : 0, stream),
+                       "coil sum");
     }
     return KBN_OK;
 }
