@@ -637,7 +637,7 @@ __global__ void __launch_bounds__(512) k_spread_os(KbnGeom g, KbnSpreadArgs a) {
             const int n = min(EB, e1 - eb);
             __syncthreads();  // previous batch (or work item) consumed
             for (int t = threadIdx.x; t < n; t += nthr) {
-                s_p[t] = a.order[a.rec_p[eb + t]];
+                s_p[t] = a.rec_q[eb + t];
                 if (D == 2) {
 #pragma unroll
                     for (int d = 0; d < D; ++d) {
@@ -731,14 +731,184 @@ __global__ void __launch_bounds__(512) k_spread_os(KbnGeom g, KbnSpreadArgs a) {
     }
 }
 
+// Output-stationary spread with one channel per lane, for 2D 8 x 8 owner
+// tiles and at least 64 channels.  A wave owns one tile for 64 channels and
+// each lane keeps the 64 cell sums of its own channel in registers.  Per
+// staged list entry the lanes share the window weights of each axis,
+// tabulated over the tile's 8 cell coordinates (zero outside the footprint),
+// and a mask of the rows the footprint covers; the wave visits only the
+// covered rows, with wave-uniform branches, and each lane adds weight * y of
+// its channel to the row's cells (a zero weight adds +0 outside the
+// footprint).  A cell's weight is the same product w_axis0 * w_axis1 as in
+// k_spread_os and the entries are added in list order, so both kernels
+// produce the same sums for finite data.  The finished tile goes
+// through LDS two rows at a time, so that each store instruction writes whole
+// row segments of a few channels instead of one cell of 64 channels.
+template <int J, int EB>
+__global__ void __launch_bounds__(64, KBN_SPREAD_CL_WAVES) k_spread_cl(KbnGeom g, KbnSpreadArgs a) {
+    constexpr int T = 8;
+    constexpr int NC = 64;         // channels per wave (one per lane)
+    constexpr int YP = NC + 1;     // padded entry row of the staged values
+    constexpr int TP = 2 * T + 1;  // padded channel row of two transposed tile rows
+    constexpr int SY = EB * YP > NC * TP ? EB * YP : NC * TP;
+    __shared__ float2 s_y[SY];
+    __shared__ float4 s_w[EB][2][T / 4];
+    __shared__ int s_m[EB];  // bit r: row r covered
+    __shared__ int s_p[EB];
+    // window polynomial coefficients of each tap, padded to 12 for float4
+    // reads (read from a global table, the compiler keeps all 66 in vector
+    // registers next to the 128 of the sums)
+    constexpr int CP = 12;
+    static_assert(KBN_NCOEF <= CP, "coefficient padding");
+    static_assert(NC % EB == 0 && (EB * 2 * T) % NC == 0, "batch size");
+    __shared__ float4 s_coef[J * CP / 4];
+    const int lane = threadIdx.x;
+    for (int i = lane; i < J * CP; i += NC) {
+        const int j = i / CP, k = i - j * CP;
+        reinterpret_cast<float *>(s_coef)[i] = k < KBN_NCOEF ? g.coef[j * KBN_NCOEF + k] : 0.f;
+    }
+    const int ch0 = blockIdx.x * NC;
+    const int nchg = min(NC, a.nch - ch0);
+    const int nwork = a.scounts[0];
+    for (int wk = blockIdx.y; wk < nwork; wk += gridDim.y) {
+        const int tile = a.swork[4 * wk];
+        const int slot = a.swork[4 * wk + 3];
+        const int e0 = a.swork[4 * wk + 1], e1 = a.swork[4 * wk + 2];
+        const int tr = tile / g.nto[1];
+        const int a0r = tr * T, a0c = (tile - tr * g.nto[1]) * T;
+        const int ter = min(T, g.K[0] - a0r), tec = min(T, g.K[1] - a0c);
+        float2 acc[T][T];
+#pragma unroll
+        for (int r = 0; r < T; ++r)
+#pragma unroll
+            for (int c = 0; c < T; ++c) acc[r][c] = make_float2(0.f, 0.f);
+        for (int eb = e0; eb < e1; eb += EB) {
+            const int n = min(EB, e1 - eb);
+            __syncthreads();  // previous batch (or tile write-out) consumed
+            if (lane < n) s_p[lane] = a.rec_q[eb + lane];
+            // window weights: lane -> (entry t, axis d, cell cc), EB * 16
+            // cells in passes of 64, each the tap polynomial of its cell with
+            // the Horner steps of kb_weights; the row masks come from a
+            // ballot over the axis-0 cells of each entry
+#pragma unroll
+            for (int it = 0; it < EB * 2 * T / NC; ++it) {
+                const int idx = it * NC + lane;
+                const int t = idx / (2 * T), d = (idx / T) & 1, cc = idx % T;
+                bool in = false;
+                float wv = 0.f;
+                if (t < n) {
+                    const int64_t e = eb + t;
+                    int j = cc - a.rec_l[e * 2 + d];
+                    if (j < 0) j += g.K[d];
+                    in = j < J && cc < (d == 0 ? ter : tec);
+                    const float x = 2.f * a.rec_f[e * 2 + d] - 1.f;
+                    const int jc = in ? j : 0;
+                    float cf[CP];
+#pragma unroll
+                    for (int q = 0; q < CP / 4; ++q) {
+                        const float4 c4 = s_coef[jc * (CP / 4) + q];
+                        cf[4 * q] = c4.x, cf[4 * q + 1] = c4.y, cf[4 * q + 2] = c4.z, cf[4 * q + 3] = c4.w;
+                    }
+                    float acc_w = cf[KBN_NCOEF - 1];
+#pragma unroll
+                    for (int k = KBN_NCOEF - 2; k >= 0; --k) acc_w = fmaf(acc_w, x, cf[k]);
+                    wv = in ? acc_w : 0.f;
+                }
+                reinterpret_cast<float *>(s_w)[idx] = wv;
+                const unsigned long long bal = __ballot(in);
+                if ((lane & (2 * T - 1)) == 0) s_m[t] = (int)((bal >> (lane & ~(2 * T - 1))) & 0xFF);
+            }
+            __syncthreads();
+            // values: 64 channels x EB entries, entries fastest (consecutive
+            // list entries are mostly consecutive samples); a lane keeps one
+            // entry and steps over channels.  Loads past the batch or the
+            // channel count re-read a valid value, so that all are issued
+            // without branches and are in flight together; their addresses
+            // are 32-bit byte offsets from the group's first channel (the
+            // host takes this kernel only when 64 channels of k-space span
+            // less than 2 GiB).
+            {
+                constexpr int KS = NC / EB;  // channels per load round
+                const int t = lane % EB, kb = lane / EB;
+                const int q = t < n ? s_p[t] : 0;
+                const char *base = reinterpret_cast<const char *>(a.y + (int64_t)ch0 * a.M);
+                const unsigned cs = (unsigned)a.M * 8u;  // bytes per channel
+                float2 v[EB];
+#pragma unroll
+                for (int r = 0; r < EB; ++r) {
+                    const unsigned k = (unsigned)min(kb + KS * r, nchg - 1);
+                    v[r] = *reinterpret_cast<const float2 *>(base + ((unsigned)q * 8u + k * cs));
+                }
+#pragma unroll
+                for (int r = 0; r < EB; ++r) s_y[t * YP + kb + KS * r] = v[r];
+            }
+            __syncthreads();
+            for (int i = 0; i < n; ++i) {
+                const float2 v = s_y[i * YP + lane];
+                const int m = __builtin_amdgcn_readfirstlane(s_m[i]);
+                float wr[T], wc[T];
+#pragma unroll
+                for (int q = 0; q < T / 4; ++q) {
+                    const float4 r4 = s_w[i][0][q], c4 = s_w[i][1][q];
+                    wr[4 * q] = r4.x, wr[4 * q + 1] = r4.y, wr[4 * q + 2] = r4.z, wr[4 * q + 3] = r4.w;
+                    wc[4 * q] = c4.x, wc[4 * q + 1] = c4.y, wc[4 * q + 2] = c4.z, wc[4 * q + 3] = c4.w;
+                }
+#pragma unroll
+                for (int r = 0; r < T; ++r) {
+                    if (m & (1 << r)) {
+#pragma unroll
+                        for (int c = 0; c < T; ++c) {
+                            const float w = wr[r] * wc[c];
+                            acc[r][c].x = fmaf(w, v.x, acc[r][c].x);
+                            acc[r][c].y = fmaf(w, v.y, acc[r][c].y);
+                        }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int r0 = 0; r0 < T; r0 += 2) {
+            __syncthreads();
+#pragma unroll
+            for (int dr = 0; dr < 2; ++dr)
+#pragma unroll
+                for (int c = 0; c < T; ++c) s_y[lane * TP + dr * T + c] = acc[r0 + dr][c];
+            __syncthreads();
+            // lane -> one cell of the two rows, stepping over channels
+            const int cell = lane % (2 * T), kb = lane / (2 * T);
+            constexpr int KS = NC / (2 * T);
+            const int r = r0 + cell / T, c = cell % T;
+            if (r < ter && c < tec) {
+                float2 *dst;
+                int64_t step;
+                if (slot >= 0) {
+                    dst = a.partial + ((int64_t)slot * a.nch + ch0 + kb) * (T * T) + r * tec + c;
+                    step = (int64_t)KS * T * T;
+                } else {
+                    dst = a.grid + (int64_t)(ch0 + kb) * a.gsize + (int64_t)(a0r + r) * g.K[1] + a0c + c;
+                    step = (int64_t)KS * a.gsize;
+                }
+#pragma unroll
+                for (int it = 0; it < 2 * T; ++it) {
+                    const int k = kb + KS * it;
+                    if (k < nchg) dst[it * step] = s_y[k * TP + cell];
+                }
+            }
+        }
+    }
+}
+
 // Per-entry records of the owner lists: sorted position, the tap origin
 // relative to the owning tile (in [0, K)) and the window fraction, so that
-// the spread stages entries with one coalesced load round.
+// the spread stages entries with one coalesced load round; and the sample's
+// index in the caller's order, so that the output-stationary spreads read
+// k-space with one dependent load instead of two.
 template <int J>
 __global__ void __launch_bounds__(KBN_BLOCK)
 k_spread_records(KbnGeom g, int64_t M, const int *__restrict__ cell, const float *__restrict__ frac,
-                 const int *__restrict__ ooff, const int *__restrict__ oent, int64_t cap,
-                 int *__restrict__ rec_p, int *__restrict__ rec_l, float *__restrict__ rec_f) {
+                 const int *__restrict__ ooff, const int *__restrict__ oent, const int *__restrict__ order,
+                 int64_t cap, int *__restrict__ rec_p, int *__restrict__ rec_q, int *__restrict__ rec_l,
+                 float *__restrict__ rec_f) {
     const int64_t e = (int64_t)blockIdx.x * KBN_BLOCK + threadIdx.x;
     if (e >= cap || e >= ooff[g.ntiles_own]) return;
     // owning tile: last t with ooff[t] <= e
@@ -756,6 +926,7 @@ k_spread_records(KbnGeom g, int64_t M, const int *__restrict__ cell, const float
     }
     const int p = oent[e];
     rec_p[e] = p;
+    rec_q[e] = order[p];
     for (int d = 0; d < g.D; ++d) {
         int start;
         float f;
@@ -930,6 +1101,20 @@ hipError_t spread_dj(const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s) {
         const char *e = std::getenv("KBN_SPREAD_OS");
         return !(e && e[0] == '0');
     }();
+    static const bool cl_on = [] {
+        const char *e = std::getenv("KBN_SPREAD_CL");
+        return !(e && e[0] == '0');
+    }();
+    if (D == 2 && os_on && cl_on && g.To[0] == 8 && g.To[1] == 8 && a.nch >= 64 &&
+        64 * a.M * (int64_t)sizeof(float2) < ((int64_t)1 << 31)) {
+        dim3 grid_cl((unsigned)((a.nch + 63) / 64), (unsigned)a.nwork_max);
+        k_spread_cl<J, KBN_SPREAD_CL_EB><<<grid_cl, dim3(64), 0, s>>>(g, a);
+        if (a.ncomb_max > 0) {
+            const int ny = std::max(1, std::min(a.ncomb_max, 8 * 256 * 4 / a.nch + 1));
+            k_spread_combine<D><<<dim3((unsigned)a.nch, (unsigned)ny), dim3(64), 0, s>>>(g, a);
+        }
+        return hipGetLastError();
+    }
     if (D >= 2 && tcells <= 512 && os_on) {
         const int want = std::min(a.nch, 32);
         int cpt = 1;
@@ -1028,12 +1213,12 @@ hipError_t kbn_launch_spread(const KbnGeom &g, const KbnSpreadArgs &a, hipStream
 
 
 hipError_t kbn_launch_spread_records(const KbnGeom &g, int64_t M, const int *cell, const float *frac,
-                                     const int *ooff, const int *oent, int64_t cap, int *rec_p,
-                                     int *rec_l, float *rec_f, hipStream_t s) {
+                                     const int *ooff, const int *oent, const int *order, int64_t cap,
+                                     int *rec_p, int *rec_q, int *rec_l, float *rec_f, hipStream_t s) {
     if (M == 0 || cap == 0) return hipSuccess;
     const dim3 grid((unsigned)((cap + KBN_BLOCK - 1) / KBN_BLOCK));
     switch (g.J) {
-#define KBN_REC(j) case j: k_spread_records<j><<<grid, dim3(KBN_BLOCK), 0, s>>>(g, M, cell, frac, ooff, oent, cap, rec_p, rec_l, rec_f); break;
+#define KBN_REC(j) case j: k_spread_records<j><<<grid, dim3(KBN_BLOCK), 0, s>>>(g, M, cell, frac, ooff, oent, order, cap, rec_p, rec_q, rec_l, rec_f); break;
         KBN_REC(2) KBN_REC(3) KBN_REC(4) KBN_REC(5) KBN_REC(6) KBN_REC(7) KBN_REC(8)
 #undef KBN_REC
         default: return hipErrorInvalidValue;

@@ -19,6 +19,12 @@
 #define KBN_SPREAD_EB 64   // list entries staged per spread batch
 #define KBN_SPREAD_SEG 128  // list entries per spread work item (doubled if slots run out)
 #define KBN_SPREAD_SMAX 256 // partial-tile slots for tiles split into several work items
+#ifndef KBN_SPREAD_CL_WAVES
+#define KBN_SPREAD_CL_WAVES 2 // waves per SIMD the channel-per-lane spread is compiled for
+#endif
+#ifndef KBN_SPREAD_CL_EB
+#define KBN_SPREAD_CL_EB 16 // list entries staged per batch of the channel-per-lane spread
+#endif
 #define KBN_SPREAD_LDS (64 * 1024)  // LDS budget of one spread workgroup
 
 // kernel classes reported by kbn_timing_read (order of kClassNames)
@@ -196,6 +202,7 @@ struct KbnSpreadArgs {
     const int *scounts;        // [0] work items, [1] multi-item tiles
     float2 *partial;           // [smax][nch][prod To] partial tiles of multi-item tiles
     const int *rec_p;          // per owner-list entry: sorted sample position
+    const int *rec_q;          // per owner-list entry: the sample's index in the caller's order
     const int *rec_l;          // [entries][D] tap origin relative to the owning tile
     const float *rec_f;        // [entries][D] window fraction
     int nwork_max, ncomb_max;
@@ -204,8 +211,8 @@ struct KbnSpreadArgs {
 hipError_t kbn_launch_gather(const KbnGeom &g, const KbnGatherArgs &a, int mode, hipStream_t s);
 hipError_t kbn_launch_spread(const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s);
 hipError_t kbn_launch_spread_records(const KbnGeom &g, int64_t M, const int *cell, const float *frac,
-                                     const int *ooff, const int *oent, int64_t cap, int *rec_p,
-                                     int *rec_l, float *rec_f, hipStream_t s);
+                                     const int *ooff, const int *oent, const int *order, int64_t cap,
+                                     int *rec_p, int *rec_q, int *rec_l, float *rec_f, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Plan hooks used by the batch executor (plan.cpp)

@@ -197,7 +197,7 @@ struct kbn_plan_s {
     int *subs = nullptr, *nsub = nullptr;
     int *ooff = nullptr, *oent = nullptr, *otile_order = nullptr;
     int *swork = nullptr, *scomb = nullptr, *scounts = nullptr;
-    int *rec_p = nullptr, *rec_l = nullptr;
+    int *rec_p = nullptr, *rec_q = nullptr, *rec_l = nullptr;
     float *rec_f = nullptr;
     int64_t swork_cap = 0;
     // grid workspace
@@ -296,6 +296,7 @@ void free_points(kbn_plan p) {
     dev_free(p->oent);
     dev_free(p->swork);
     dev_free(p->rec_p);
+    dev_free(p->rec_q);
     dev_free(p->rec_l);
     dev_free(p->rec_f);
     p->swork_cap = 0;
@@ -514,6 +515,7 @@ int run_type1(kbn_plan p, int B, int C, const float2 *y, const float2 *smaps, fl
         sa.scounts = p->scounts;
         sa.partial = bufP;
         sa.rec_p = p->rec_p;
+        sa.rec_q = p->rec_q;
         sa.rec_l = p->rec_l;
         sa.rec_f = p->rec_f;
         sa.nwork_max = (int)p->swork_cap;
@@ -789,6 +791,7 @@ int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream_) {
         p->swork_cap = p->ntiles_own + ((cap << D) + KBN_SPREAD_SEG - 1) / KBN_SPREAD_SEG + 1;
         if (rc == KBN_OK) rc = dev_alloc(&p->swork, 4 * p->swork_cap);
         if (rc == KBN_OK) rc = dev_alloc(&p->rec_p, cap << D);
+        if (rc == KBN_OK) rc = dev_alloc(&p->rec_q, cap << D);
         if (rc == KBN_OK) rc = dev_alloc(&p->rec_l, (cap << D) * D);
         if (rc == KBN_OK) rc = dev_alloc(&p->rec_f, (cap << D) * D);
         if (rc != KBN_OK) {
@@ -821,8 +824,8 @@ int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream_) {
                                       p->smax, p->swork, p->scomb, p->scounts, stream),
                "spread lists");
     KBN_LAUNCH(KBN_CLASS_INDEX,
-               kbn_launch_spread_records(p->geom(), M, p->cell, p->frac, p->ooff, p->oent, p->Mcap << p->D,
-                                         p->rec_p, p->rec_l, p->rec_f, stream),
+               kbn_launch_spread_records(p->geom(), M, p->cell, p->frac, p->ooff, p->oent, p->order,
+                                         p->Mcap << p->D, p->rec_p, p->rec_q, p->rec_l, p->rec_f, stream),
                "spread records");
     p->M = M;
     return KBN_OK;

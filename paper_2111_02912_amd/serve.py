@@ -77,7 +77,9 @@ def plan_bytes(N, M: int, coils: int) -> int:
     K = [2 * n + 16 for n in N]  # oversampled sizes round up to a 7-smooth length
     gsz = math.prod(K)
     ws = coils * (2 * gsz + M + 256 * 16 ** D) * 8
-    pts = M * (24 * D + 16 + (2 ** D) * (4 + 8 * D))
+    # per owner-list entry (at most 2^D per sample): list position, sorted and
+    # caller-order sample index, tap origins and fractions
+    pts = M * (24 * D + 16 + (2 ** D) * (12 + 8 * D))
     return int(ws + pts + (1 << 20))
 
 

@@ -404,6 +404,38 @@ def test_largest_grid_and_clustered_samples(dev):
     assert e_f < TOL_NUFFT and e_a < TOL_NUFFT
 
 
+@pytest.mark.parametrize("N,kind,nch", [((64, 64), "radial", 96), ((35, 40), "clustered", 64),
+                                         ((48, 48), "uniform", 160)])
+def test_wide_channel_spread_matches_narrow_groups(N, kind, nch, dev):
+    """2D adjoints of 64 or more channels on 8 x 8 owner tiles run the
+    channel-per-lane spread; the same channels 32 at a time run the
+    cell-per-lane spread.  Both add the same weights in the same list order,
+    so they agree bit for bit, and both match the NUDFT.  Cases: radial
+    (hot centre tiles split into several work items), clustered samples on a
+    grid whose last owner tile is 6 cells wide (K = 70), and a channel count
+    that leaves the last group of 64 partly empty."""
+    _say(f"wide-channel spread N={N} {kind} nch={nch}")
+    if kind == "radial":
+        om = W.radial_2d(32, 2 * max(N), jitter=np.pi / max(N), seed=9501)
+    elif kind == "clustered":
+        hot = W.uniform_random(1500, 2, seed=9502, lo=-0.2, hi=0.25)
+        om = np.concatenate([W.uniform_random(1000, 2, seed=9503), hot])
+    else:
+        om = W.uniform_random(3000, 2, seed=9504)
+    om = om.astype(np.float32)
+    M = om.shape[0]
+    g = W.complex_normal((nch, 1, M), 9505)
+    p = _plan(N, dev, spread_tile=8)
+    p.set_points(_f(om, dev))
+    wide = _np(p.adjoint(_c(g, dev)))
+    narrow = np.concatenate([_np(p.adjoint(_c(g[i:i + 32], dev))) for i in range(0, nch, 32)])
+    assert np.array_equal(wide, narrow)
+    idx = [0, 37, nch - 1]
+    e_a = ndft.rel_l2(wide[idx], ndft.adjoint(om, g[idx, 0], N))
+    _say(f"  adj {e_a:.2e}")
+    assert e_a < TOL_NUFFT
+
+
 @pytest.mark.parametrize("N,st", [((60, 52), 24), ((20, 22, 18), 10)])
 def test_scatter_spread_path(N, st, dev):
     """Owner tiles of more than 512 cells use the scatter spread kernel
