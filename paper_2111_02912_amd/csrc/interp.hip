@@ -1105,7 +1105,12 @@ hipError_t spread_dj(const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s) {
         const char *e = std::getenv("KBN_SPREAD_CL");
         return !(e && e[0] == '0');
     }();
-    if (D == 2 && os_on && cl_on && g.To[0] == 8 && g.To[1] == 8 && a.nch >= 64 &&
+    // channel-per-lane spread: one wave per (owner tile, 64 channels) at two
+    // waves per SIMD, so it needs enough tiles x channel groups to fill the
+    // chip's 2048 wave slots twice; below that the cell-per-lane kernel is
+    // faster (both give the same sums)
+    const int64_t cl_waves = (int64_t)g.ntiles_own * ((a.nch + 63) / 64);
+    if (D == 2 && os_on && cl_on && g.To[0] == 8 && g.To[1] == 8 && a.nch >= 64 && cl_waves >= 4096 &&
         64 * a.M * (int64_t)sizeof(float2) < ((int64_t)1 << 31)) {
         dim3 grid_cl((unsigned)((a.nch + 63) / 64), (unsigned)a.nwork_max);
         k_spread_cl<J, KBN_SPREAD_CL_EB><<<grid_cl, dim3(64), 0, s>>>(g, a);
