@@ -19,6 +19,12 @@
 #define KBN_SPREAD_EB 64   // list entries staged per spread batch
 #define KBN_SPREAD_SEG 128  // list entries per spread work item (doubled if slots run out)
 #define KBN_SPREAD_SMAX 256 // partial-tile slots for tiles split into several work items
+#ifndef KBN_NCHUNKS
+#define KBN_NCHUNKS 1024    // histogram chunks of the index pass (about; each at least KBN_CHUNK_MIN points)
+#endif
+#ifndef KBN_CHUNK_MIN
+#define KBN_CHUNK_MIN 64
+#endif
 #ifndef KBN_SPREAD_CL_WAVES
 #define KBN_SPREAD_CL_WAVES 2 // waves per SIMD the channel-per-lane spread is compiled for
 #endif

@@ -765,7 +765,7 @@ int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream_) {
     // histogram chunks: about a thousand of at least 64 points, so that the
     // counting and scattering kernels fill the GPU; the bin-major count matrix
     // (bins x chunks) is scanned by a multi-block scan
-    int64_t chunk = std::max<int64_t>(64, (M + 1023) / 1024);
+    int64_t chunk = std::max<int64_t>(KBN_CHUNK_MIN, (M + KBN_NCHUNKS - 1) / KBN_NCHUNKS);
     chunk = (chunk + 63) / 64 * 64;
     const int64_t nchunks = M > 0 ? (M + chunk - 1) / chunk : 0;
     const int nbins_o = p->ntiles_own;
