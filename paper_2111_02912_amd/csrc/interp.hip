@@ -1112,7 +1112,7 @@ hipError_t spread_dj(const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s) {
     const int64_t cl_waves = (int64_t)g.ntiles_own * ((a.nch + 63) / 64);
     if (D == 2 && os_on && cl_on && g.To[0] == 8 && g.To[1] == 8 && a.nch >= 64 && cl_waves >= 4096 &&
         64 * a.M * (int64_t)sizeof(float2) < ((int64_t)1 << 31)) {
-        dim3 grid_cl((unsigned)((a.nch + 63) / 64), (unsigned)a.nwork_max);
+        dim3 grid_cl((unsigned)((a.nch + 63) / 64), (unsigned)std::min(a.nwork_max, KBN_GRID_Y_MAX));
         k_spread_cl<J, KBN_SPREAD_CL_EB><<<grid_cl, dim3(64), 0, s>>>(g, a);
         if (a.ncomb_max > 0) {
             const int ny = std::max(1, std::min(a.ncomb_max, 8 * 256 * 4 / a.nch + 1));
@@ -1125,7 +1125,7 @@ hipError_t spread_dj(const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s) {
         int cpt = 1;
         while (cpt < want) cpt *= 2;
         const int ngr = (a.nch + cpt - 1) / cpt;
-        dim3 grid_os((unsigned)ngr, (unsigned)a.nwork_max);
+        dim3 grid_os((unsigned)ngr, (unsigned)std::min(a.nwork_max, KBN_GRID_Y_MAX));
         dim3 blk((unsigned)tcells);
         int tmax = 1;
         for (int d = 0; d < D; ++d) tmax = std::max(tmax, g.To[d]);
@@ -1161,7 +1161,7 @@ hipError_t spread_dj(const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s) {
         dim3 pgrid((unsigned)((a.M + KBN_BLOCK - 1) / KBN_BLOCK), (unsigned)a.nch);
         k_permute<<<pgrid, dim3(KBN_BLOCK), 0, s>>>(a.y, a.ys, a.order, a.M);
     }
-    dim3 grid((unsigned)ng, (unsigned)a.nwork_max);
+    dim3 grid((unsigned)ng, (unsigned)a.nwork_max);  // one workgroup row per work item
     if (sh.A == 1 || D == 1)
         k_spread<D, J, 1><<<grid, dim3(64 * sh.nwave), sh.lds, s>>>(g, a, sh.cw, sh.nwave);
     else

@@ -19,6 +19,7 @@
 #define KBN_SPREAD_EB 64   // list entries staged per spread batch
 #define KBN_SPREAD_SEG 128  // list entries per spread work item (doubled if slots run out)
 #define KBN_SPREAD_SMAX 256 // partial-tile slots for tiles split into several work items
+#define KBN_GRID_Y_MAX 65535 // output-stationary spreads stride over work items beyond this many workgroup rows
 #ifndef KBN_NCHUNKS
 #define KBN_NCHUNKS 1024    // histogram chunks of the index pass (about; each at least KBN_CHUNK_MIN points)
 #endif
