@@ -132,3 +132,34 @@ def test_low_accuracy_preset_and_layer(dev):
     eo = ndft.rel_l2(_np(omt.grad), gom_ex)
     _say(f"  low-accuracy layer: dx {ex:.2e} domega {eo:.2e}")
     assert ex < 5e-3 and eo < 5e-3
+
+
+def test_low_accuracy_bench_configuration_sampled(dev):
+    """The benchmarked step's shape in the low-accuracy mode: 256 images of
+    256 x 256 (K = 320), M = 32768, in one call each, as the benchmark runs
+    them (the adjoint takes the channel-per-lane spread at this size).
+    Forward and adjoint of images in different 64-channel groups against the
+    FP64 three-step NUFFT with the same sigma and J; the omega-gradient,
+    summed over all 256 images, on sampled rows against the exact form."""
+    from paper_2111_02912_amd.nufft import KbNufft
+    B = 256
+    N, om, x = W.throughput_case(batch=B)
+    M = om.shape[0]
+    _say(f"low-accuracy bench configuration B={B} N={N} M={M}")
+    g = W.complex_normal((B, 1, M), 2201)
+    plan = KbNufft(N, accuracy="low", device=dev)
+    P = nufft_ref.Params(N, 1.25, 5)
+    assert tuple(plan.K) == P.K == (320, 320)
+    plan.set_points(_f(om, dev))
+    xt, gt = _c(x, dev), _c(g, dev)
+    y = _np(plan.forward(xt))
+    xa = _np(plan.adjoint(gt))
+    dom = _np(plan.jac_omega_fwd(xt, gt))
+    imgs = [0, 77, 200]
+    ef = ndft.rel_l2(y[imgs, 0], nufft_ref.forward(P, om, x[imgs]))
+    ea = ndft.rel_l2(xa[imgs], nufft_ref.adjoint(P, om, g[imgs, 0]))
+    rows = np.sort(W.rng(2202).choice(M, 128, replace=False))
+    ej = ndft.rel_l2(dom[rows], ndft.jac_omega_fwd(om, x, g, N, rows=rows))
+    _say(f"  vs FP64 three-step: fwd {ef:.2e} adj {ea:.2e}; omega-gradient vs exact {ej:.2e}")
+    assert ef < TOL_REF and ea < TOL_REF
+    assert ej < TOL_EXACT[(1.25, 5)][1]
