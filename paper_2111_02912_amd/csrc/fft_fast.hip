@@ -468,21 +468,41 @@ __global__ void __launch_bounds__(NT) k_rows_last_adj(KbnLastAdjArgs a, const fl
 // serve one line and a workgroup holds whole lines: 400 = 2^4 5^2 takes
 // E = 20 (radices 4,4,5,5) with 20 threads per line in 320-thread
 // workgroups; 480 = 2^5 3 5 takes E = 60 (4,4,2,3,5) with 128 threads.
+// Elements per thread: every radix of the length's plan must divide it, so
+// lengths with factors 2, 3 and 5 take 30 (or a multiple).
 constexpr int row_e(int L) {
     return L == 128 ? 8 : L == 256 ? 8 : L == 512 ? 8 : L == 1024 ? 16 : L == 192 ? 12
            : L == 384 ? 12 : L == 640 ? 10 : L == 768 ? 24 : L == 160 ? 10 : L == 320 ? 10
-           : L == 400 ? 10 : L == 480 ? 60 : 0;
+           : L == 400 ? 10 : L == 480 ? 60 : L == 432 ? 12 : L == 450 ? 30 : L == 486 ? 18
+           : L == 500 ? 20 : L == 540 ? 30 : L == 576 ? 12 : L == 600 ? 30 : L == 648 ? 24
+           : L == 720 ? 30 : L == 750 ? 30 : 0;
 }
 constexpr int col_e(int L) {
     return L == 128 ? 8 : L == 256 ? 16 : L == 512 ? 16 : L == 1024 ? 32 : L == 192 ? 12
            : L == 384 ? 24 : L == 640 ? 20 : L == 768 ? 24 : L == 160 ? 20 : L == 320 ? 20
-           : L == 400 ? 20 : L == 480 ? 60 : 0;
+           : L == 400 ? 20 : L == 480 ? 60 : L == 432 ? 24 : L == 450 ? 30 : L == 486 ? 18
+           : L == 500 ? 20 : L == 540 ? 30 : L == 576 ? 24 : L == 600 ? 30 : L == 648 ? 24
+           : L == 720 ? 30 : L == 750 ? 30 : 0;
 }
-// threads per row-pass workgroup
-constexpr int row_nt(int L) { return L == 400 ? 320 : L == 480 ? 128 : KBN_BLOCK; }
+// threads per row-pass workgroup: whole lines (L / E threads each), 8 lines
+// for the lengths whose line does not divide 256 threads
+constexpr int row_nt(int L) {
+    return L == 400 ? 320 : L == 480 ? 128 : (L == 432 || L == 450 || L == 486 || L == 500 || L == 540 ||
+                                               L == 576 || L == 600 || L == 648 || L == 720 || L == 750)
+                                                  ? 8 * (L / row_e(L))
+                                                  : KBN_BLOCK;
+}
 // threads per column-pass workgroup (512 for L = 512: 16 columns of 32
-// threads, 64 KB of LDS, measured faster than 256 threads with E = 32)
-constexpr int col_nt(int L) { return L == 512 ? 512 : L == 400 ? 320 : L == 480 ? 128 : KBN_BLOCK; }
+// threads, 64 KB of LDS, measured faster than 256 threads with E = 32);
+// 8 columns for the lengths whose column does not divide 256 threads, 16
+// where the tile still fits 64 KB of LDS
+constexpr int col_nt(int L) {
+    return L == 512 ? 512 : L == 400 ? 320 : L == 480 ? 128
+           : (L == 432 || L == 450) ? 16 * (L / col_e(L))
+           : (L == 486 || L == 500 || L == 540 || L == 576 || L == 600 || L == 648 || L == 720 || L == 750)
+               ? 8 * (L / col_e(L))
+               : KBN_BLOCK;
+}
 
 // workgroups of a kernel that can be resident on the current device at once
 template <class K>
@@ -547,9 +567,11 @@ hipError_t launch_rows_last(const KbnLastAdjArgs &a, const float2 *tw, hipStream
 }
 
 #define KBN_FAST_SIZES(X) \
-    X(128) X(160) X(192) X(256) X(320) X(384) X(400) X(480) X(512) X(640) X(768) X(1024)
+    X(128) X(160) X(192) X(256) X(320) X(384) X(400) X(432) X(450) X(480) X(486) X(500) X(512) \
+    X(540) X(576) X(600) X(640) X(648) X(720) X(750) X(768) X(1024)
 #define KBN_FAST_LAST_SIZES(X) \
-    X(128) X(160) X(192) X(256) X(320) X(384) X(400) X(512) X(640) X(768) X(1024)
+    X(128) X(160) X(192) X(256) X(320) X(384) X(400) X(432) X(450) X(486) X(500) X(512) X(540) \
+    X(576) X(600) X(640) X(648) X(720) X(750) X(768) X(1024)
 
 }  // namespace
 
