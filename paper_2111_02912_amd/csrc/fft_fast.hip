@@ -131,8 +131,19 @@ struct SDftOdd {
         }
     }
 };
+template <>
+struct STrig<7> {
+    static constexpr float c[7] = {1.0f, 0.62348980185873353f, -0.22252093395631440f,
+                                   -0.90096886790241912f, -0.90096886790241912f, -0.22252093395631440f,
+                                   0.62348980185873353f};
+    static constexpr float s[7] = {0.0f, 0.78183148246802981f, 0.97492791218182361f,
+                                   0.43388373911755812f, -0.43388373911755812f, -0.97492791218182361f,
+                                   -0.78183148246802981f};
+};
 template <bool INV>
 struct SDft<3, INV> : SDftOdd<3, INV> {};
+template <bool INV>
+struct SDft<7, INV> : SDftOdd<7, INV> {};
 template <bool INV>
 struct SDft<5, INV> : SDftOdd<5, INV> {};
 
@@ -143,6 +154,7 @@ constexpr int pick_radix(int rem, int E) {
            : (rem % 2 == 0 && E % 2 == 0) ? 2
            : (rem % 3 == 0 && E % 3 == 0) ? 3
            : (rem % 5 == 0 && E % 5 == 0) ? 5
+           : (rem % 7 == 0 && E % 7 == 0) ? 7
                                           : 0;
 }
 constexpr int rem_at(int L, int E, int s) {
@@ -475,20 +487,24 @@ constexpr int row_e(int L) {
            : L == 384 ? 12 : L == 640 ? 10 : L == 768 ? 24 : L == 160 ? 10 : L == 320 ? 10
            : L == 400 ? 10 : L == 480 ? 60 : L == 432 ? 12 : L == 450 ? 30 : L == 486 ? 18
            : L == 500 ? 20 : L == 540 ? 30 : L == 576 ? 12 : L == 600 ? 30 : L == 648 ? 24
-           : L == 720 ? 30 : L == 750 ? 30 : 0;
+           : L == 720 ? 30 : L == 750 ? 30 : L == 392 ? 14 : L == 448 ? 28 : L == 504 ? 42
+           : L == 588 ? 42 : L == 672 ? 42 : L == 686 ? 14 : L == 756 ? 42 : 0;
 }
 constexpr int col_e(int L) {
     return L == 128 ? 8 : L == 256 ? 16 : L == 512 ? 16 : L == 1024 ? 32 : L == 192 ? 12
            : L == 384 ? 24 : L == 640 ? 20 : L == 768 ? 24 : L == 160 ? 20 : L == 320 ? 20
            : L == 400 ? 20 : L == 480 ? 60 : L == 432 ? 24 : L == 450 ? 30 : L == 486 ? 18
            : L == 500 ? 20 : L == 540 ? 30 : L == 576 ? 24 : L == 600 ? 30 : L == 648 ? 24
-           : L == 720 ? 30 : L == 750 ? 30 : 0;
+           : L == 720 ? 30 : L == 750 ? 30 : L == 392 ? 28 : L == 448 ? 28 : L == 504 ? 42
+           : L == 588 ? 42 : L == 672 ? 42 : L == 686 ? 14 : L == 756 ? 42 : 0;
 }
 // threads per row-pass workgroup: whole lines (L / E threads each), 8 lines
 // for the lengths whose line does not divide 256 threads
 constexpr int row_nt(int L) {
     return L == 400 ? 320 : L == 480 ? 128 : (L == 432 || L == 450 || L == 486 || L == 500 || L == 540 ||
-                                               L == 576 || L == 600 || L == 648 || L == 720 || L == 750)
+                                               L == 576 || L == 600 || L == 648 || L == 720 || L == 750 ||
+                                               L == 392 || L == 448 || L == 504 || L == 588 || L == 672 ||
+                                               L == 686 || L == 756)
                                                   ? 8 * (L / row_e(L))
                                                   : KBN_BLOCK;
 }
@@ -498,8 +514,9 @@ constexpr int row_nt(int L) {
 // where the tile still fits 64 KB of LDS
 constexpr int col_nt(int L) {
     return L == 512 ? 512 : L == 400 ? 320 : L == 480 ? 128
-           : (L == 432 || L == 450) ? 16 * (L / col_e(L))
-           : (L == 486 || L == 500 || L == 540 || L == 576 || L == 600 || L == 648 || L == 720 || L == 750)
+           : (L == 432 || L == 450 || L == 392 || L == 448 || L == 504) ? 16 * (L / col_e(L))
+           : (L == 486 || L == 500 || L == 540 || L == 576 || L == 600 || L == 648 || L == 720 || L == 750 ||
+              L == 588 || L == 672 || L == 686 || L == 756)
                ? 8 * (L / col_e(L))
                : KBN_BLOCK;
 }
@@ -567,11 +584,14 @@ hipError_t launch_rows_last(const KbnLastAdjArgs &a, const float2 *tw, hipStream
 }
 
 #define KBN_FAST_SIZES(X) \
-    X(128) X(160) X(192) X(256) X(320) X(384) X(400) X(432) X(450) X(480) X(486) X(500) X(512) \
-    X(540) X(576) X(600) X(640) X(648) X(720) X(750) X(768) X(1024)
+    X(128) X(160) X(192) X(256) X(320) X(384) X(392) X(400) X(432) X(448) X(450) X(480) X(486) X(500) \
+    X(504) X(512) X(540) X(576) X(588) X(600) X(640) X(648) X(672) X(686) X(720) X(750) X(756) X(768) X(1024)
+// the last adjoint pass keeps E accumulators besides the E values, which
+// spills for 480 (E = 60) and 504, 588, 756 (E = 42): those lengths take
+// the generic last pass
 #define KBN_FAST_LAST_SIZES(X) \
-    X(128) X(160) X(192) X(256) X(320) X(384) X(400) X(432) X(450) X(486) X(500) X(512) X(540) \
-    X(576) X(600) X(640) X(648) X(720) X(750) X(768) X(1024)
+    X(128) X(160) X(192) X(256) X(320) X(384) X(392) X(400) X(432) X(448) X(450) X(486) X(500) X(512) \
+    X(540) X(576) X(600) X(640) X(648) X(672) X(686) X(720) X(750) X(768) X(1024)
 
 }  // namespace
 
