@@ -670,10 +670,15 @@ __global__ void __launch_bounds__(512) k_spread_os(KbnGeom g, KbnSpreadArgs a) {
                 s_t[idx] = wv;
             }
             __syncthreads();
+            // loads past the batch or the channel group re-read a valid
+            // value (never used), so that they are issued without branches
+            // and several are in flight at once
+#pragma unroll 4
             for (int i = threadIdx.x; i < EB * CPT; i += nthr) {
                 const int t = i % EB;
                 const int k = i / EB;
-                if (t < n && k < nchg) s_y[t][k] = a.y[(int64_t)(ch0 + k) * a.M + s_p[t]];
+                const bool ok = t < n && k < nchg;
+                s_y[t][k] = a.y[(int64_t)(ch0 + (ok ? k : 0)) * a.M + (ok ? s_p[t] : 0)];
             }
             __syncthreads();
             for (int i = 0; i < n; ++i) {
