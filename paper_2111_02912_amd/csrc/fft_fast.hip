@@ -488,7 +488,8 @@ constexpr int row_e(int L) {
            : L == 400 ? 10 : L == 480 ? 60 : L == 432 ? 12 : L == 450 ? 30 : L == 486 ? 18
            : L == 500 ? 20 : L == 540 ? 30 : L == 576 ? 12 : L == 600 ? 30 : L == 648 ? 24
            : L == 720 ? 30 : L == 750 ? 30 : L == 392 ? 14 : L == 448 ? 28 : L == 504 ? 42
-           : L == 588 ? 42 : L == 672 ? 42 : L == 686 ? 14 : L == 756 ? 42 : 0;
+           : L == 588 ? 42 : L == 672 ? 42 : L == 686 ? 14 : L == 756 ? 42 : L == 200 ? 20
+           : L == 800 ? 20 : 0;
 }
 constexpr int col_e(int L) {
     return L == 128 ? 8 : L == 256 ? 16 : L == 512 ? 16 : L == 1024 ? 32 : L == 192 ? 12
@@ -496,7 +497,8 @@ constexpr int col_e(int L) {
            : L == 400 ? 20 : L == 480 ? 60 : L == 432 ? 24 : L == 450 ? 30 : L == 486 ? 18
            : L == 500 ? 20 : L == 540 ? 30 : L == 576 ? 24 : L == 600 ? 30 : L == 648 ? 24
            : L == 720 ? 30 : L == 750 ? 30 : L == 392 ? 28 : L == 448 ? 28 : L == 504 ? 42
-           : L == 588 ? 42 : L == 672 ? 42 : L == 686 ? 14 : L == 756 ? 42 : 0;
+           : L == 588 ? 42 : L == 672 ? 42 : L == 686 ? 14 : L == 756 ? 42 : L == 200 ? 20
+           : L == 800 ? 20 : 0;
 }
 // threads per row-pass workgroup: whole lines (L / E threads each), 8 lines
 // for the lengths whose line does not divide 256 threads
@@ -504,7 +506,7 @@ constexpr int row_nt(int L) {
     return L == 400 ? 320 : L == 480 ? 128 : (L == 432 || L == 450 || L == 486 || L == 500 || L == 540 ||
                                                L == 576 || L == 600 || L == 648 || L == 720 || L == 750 ||
                                                L == 392 || L == 448 || L == 504 || L == 588 || L == 672 ||
-                                               L == 686 || L == 756)
+                                               L == 686 || L == 756 || L == 200 || L == 800)
                                                   ? 8 * (L / row_e(L))
                                                   : KBN_BLOCK;
 }
@@ -514,9 +516,9 @@ constexpr int row_nt(int L) {
 // where the tile still fits 64 KB of LDS
 constexpr int col_nt(int L) {
     return L == 512 ? 512 : L == 400 ? 320 : L == 480 ? 128
-           : (L == 432 || L == 450 || L == 392 || L == 448 || L == 504) ? 16 * (L / col_e(L))
+           : (L == 432 || L == 450 || L == 392 || L == 448 || L == 504 || L == 200) ? 16 * (L / col_e(L))
            : (L == 486 || L == 500 || L == 540 || L == 576 || L == 600 || L == 648 || L == 720 || L == 750 ||
-              L == 588 || L == 672 || L == 686 || L == 756)
+              L == 588 || L == 672 || L == 686 || L == 756 || L == 800)
                ? 8 * (L / col_e(L))
                : KBN_BLOCK;
 }
@@ -584,14 +586,15 @@ hipError_t launch_rows_last(const KbnLastAdjArgs &a, const float2 *tw, hipStream
 }
 
 #define KBN_FAST_SIZES(X) \
-    X(128) X(160) X(192) X(256) X(320) X(384) X(392) X(400) X(432) X(448) X(450) X(480) X(486) X(500) \
-    X(504) X(512) X(540) X(576) X(588) X(600) X(640) X(648) X(672) X(686) X(720) X(750) X(756) X(768) X(1024)
+    X(128) X(160) X(192) X(200) X(256) X(320) X(384) X(392) X(400) X(432) X(448) X(450) X(480) X(486) \
+    X(500) X(504) X(512) X(540) X(576) X(588) X(600) X(640) X(648) X(672) X(686) X(720) X(750) X(756) \
+    X(768) X(800) X(1024)
 // the last adjoint pass keeps E accumulators besides the E values, which
-// spills for 480 (E = 60) and 504, 588, 756 (E = 42): those lengths take
-// the generic last pass
+// spills for 480 (E = 60), 504, 588, 756 (E = 42) and 800: those lengths
+// take the generic last pass
 #define KBN_FAST_LAST_SIZES(X) \
-    X(128) X(160) X(192) X(256) X(320) X(384) X(392) X(400) X(432) X(448) X(450) X(486) X(500) X(512) \
-    X(540) X(576) X(600) X(640) X(648) X(672) X(686) X(720) X(750) X(768) X(1024)
+    X(128) X(160) X(192) X(200) X(256) X(320) X(384) X(392) X(400) X(432) X(448) X(450) X(486) X(500) \
+    X(512) X(540) X(576) X(600) X(640) X(648) X(672) X(686) X(720) X(750) X(768) X(1024)
 
 }  // namespace
 
