@@ -480,47 +480,47 @@ __global__ void __launch_bounds__(NT) k_rows_last_adj(KbnLastAdjArgs a, const fl
 // serve one line and a workgroup holds whole lines: 400 = 2^4 5^2 takes
 // E = 20 (radices 4,4,5,5) with 20 threads per line in 320-thread
 // workgroups; 480 = 2^5 3 5 takes E = 60 (4,4,2,3,5) with 128 threads.
-// Elements per thread: every radix of the length's plan must divide it, so
-// lengths with factors 2, 3 and 5 take 30 (or a multiple).
-constexpr int row_e(int L) {
-    return L == 128 ? 8 : L == 256 ? 8 : L == 512 ? 8 : L == 1024 ? 16 : L == 192 ? 12
-           : L == 384 ? 12 : L == 640 ? 10 : L == 768 ? 24 : L == 160 ? 10 : L == 320 ? 10
-           : L == 400 ? 10 : L == 480 ? 60 : L == 432 ? 12 : L == 450 ? 30 : L == 486 ? 18
-           : L == 500 ? 20 : L == 540 ? 30 : L == 576 ? 12 : L == 600 ? 30 : L == 648 ? 24
-           : L == 720 ? 30 : L == 750 ? 30 : L == 392 ? 14 : L == 448 ? 28 : L == 504 ? 42
-           : L == 588 ? 42 : L == 672 ? 42 : L == 686 ? 14 : L == 756 ? 42 : L == 200 ? 20
-           : L == 800 ? 20 : 0;
+// Per-length configuration: elements per thread of the row and column
+// passes (every radix of the length's plan must divide them, so lengths with
+// factors 2, 3 and 5 take 30 and those with 2, 3 and 7 take 42) and, for
+// lengths whose line does not divide 256 threads, the lines (row passes) or
+// columns (column passes) a workgroup holds, within 64 KB of LDS; 0 keeps
+// the tuned thread counts of row_nt / col_nt.  Row passes are LDS-occupancy
+// bound, so they take the smaller E where a length allows two.
+struct FftLen {
+    int L, re, ce, rl, cl;
+};
+constexpr FftLen kFftLens[] = {
+    {128, 8, 8, 0, 0},     {160, 10, 20, 0, 0},   {192, 12, 12, 0, 0},   {200, 20, 20, 8, 16},
+    {256, 8, 16, 0, 0},    {270, 30, 30, 16, 16}, {288, 12, 24, 8, 16},  {300, 30, 30, 16, 16},
+    {320, 10, 20, 0, 0},   {324, 12, 12, 8, 8},   {360, 30, 30, 16, 16}, {384, 12, 24, 0, 0},
+    {392, 14, 28, 8, 16},
+    {400, 10, 20, 0, 0},   {432, 12, 24, 8, 16},  {448, 28, 28, 8, 16},  {450, 30, 30, 8, 16},
+    {480, 60, 60, 0, 0},   {486, 18, 18, 8, 8},   {500, 20, 20, 8, 8},   {504, 42, 42, 8, 16},
+    {512, 8, 16, 0, 0},    {540, 30, 30, 8, 8},   {576, 12, 24, 8, 8},   {588, 42, 42, 8, 8},
+    {600, 30, 30, 8, 8},   {640, 10, 20, 0, 0},   {648, 24, 24, 8, 8},   {672, 42, 42, 8, 8},
+    {686, 14, 14, 8, 8},   {720, 30, 30, 8, 8},   {750, 30, 30, 8, 8},   {756, 42, 42, 8, 8},
+    {768, 24, 24, 0, 0},   {800, 20, 20, 8, 8},   {1024, 16, 32, 0, 0},
+};
+constexpr FftLen fft_len(int L) {
+    for (const FftLen &f : kFftLens)
+        if (f.L == L) return f;
+    return FftLen{L, 0, 0, 0, 0};
 }
-constexpr int col_e(int L) {
-    return L == 128 ? 8 : L == 256 ? 16 : L == 512 ? 16 : L == 1024 ? 32 : L == 192 ? 12
-           : L == 384 ? 24 : L == 640 ? 20 : L == 768 ? 24 : L == 160 ? 20 : L == 320 ? 20
-           : L == 400 ? 20 : L == 480 ? 60 : L == 432 ? 24 : L == 450 ? 30 : L == 486 ? 18
-           : L == 500 ? 20 : L == 540 ? 30 : L == 576 ? 24 : L == 600 ? 30 : L == 648 ? 24
-           : L == 720 ? 30 : L == 750 ? 30 : L == 392 ? 28 : L == 448 ? 28 : L == 504 ? 42
-           : L == 588 ? 42 : L == 672 ? 42 : L == 686 ? 14 : L == 756 ? 42 : L == 200 ? 20
-           : L == 800 ? 20 : 0;
-}
-// threads per row-pass workgroup: whole lines (L / E threads each), 8 lines
-// for the lengths whose line does not divide 256 threads
+constexpr int row_e(int L) { return fft_len(L).re; }
+constexpr int col_e(int L) { return fft_len(L).ce; }
+// threads per row-pass workgroup (whole lines of L / E threads each)
 constexpr int row_nt(int L) {
-    return L == 400 ? 320 : L == 480 ? 128 : (L == 432 || L == 450 || L == 486 || L == 500 || L == 540 ||
-                                               L == 576 || L == 600 || L == 648 || L == 720 || L == 750 ||
-                                               L == 392 || L == 448 || L == 504 || L == 588 || L == 672 ||
-                                               L == 686 || L == 756 || L == 200 || L == 800)
-                                                  ? 8 * (L / row_e(L))
-                                                  : KBN_BLOCK;
+    return fft_len(L).rl ? fft_len(L).rl * (L / row_e(L)) : L == 400 ? 320 : L == 480 ? 128 : KBN_BLOCK;
 }
 // threads per column-pass workgroup (512 for L = 512: 16 columns of 32
-// threads, 64 KB of LDS, measured faster than 256 threads with E = 32);
-// 8 columns for the lengths whose column does not divide 256 threads, 16
-// where the tile still fits 64 KB of LDS
+// threads, 64 KB of LDS, measured faster than 256 threads with E = 32)
 constexpr int col_nt(int L) {
-    return L == 512 ? 512 : L == 400 ? 320 : L == 480 ? 128
-           : (L == 432 || L == 450 || L == 392 || L == 448 || L == 504 || L == 200) ? 16 * (L / col_e(L))
-           : (L == 486 || L == 500 || L == 540 || L == 576 || L == 600 || L == 648 || L == 720 || L == 750 ||
-              L == 588 || L == 672 || L == 686 || L == 756 || L == 800)
-               ? 8 * (L / col_e(L))
-               : KBN_BLOCK;
+    return fft_len(L).cl ? fft_len(L).cl * (L / col_e(L))
+           : L == 512    ? 512
+           : L == 400    ? 320
+           : L == 480    ? 128
+                         : KBN_BLOCK;
 }
 
 // workgroups of a kernel that can be resident on the current device at once
@@ -586,15 +586,16 @@ hipError_t launch_rows_last(const KbnLastAdjArgs &a, const float2 *tw, hipStream
 }
 
 #define KBN_FAST_SIZES(X) \
-    X(128) X(160) X(192) X(200) X(256) X(320) X(384) X(392) X(400) X(432) X(448) X(450) X(480) X(486) \
-    X(500) X(504) X(512) X(540) X(576) X(588) X(600) X(640) X(648) X(672) X(686) X(720) X(750) X(756) \
-    X(768) X(800) X(1024)
+    X(128) X(160) X(192) X(200) X(256) X(270) X(288) X(300) X(320) X(324) X(360) X(384) X(392) X(400) \
+    X(432) X(448) X(450) X(480) X(486) X(500) X(504) X(512) X(540) X(576) X(588) X(600) X(640) X(648) \
+    X(672) X(686) X(720) X(750) X(756) X(768) X(800) X(1024)
 // the last adjoint pass keeps E accumulators besides the E values, which
 // spills for 480 (E = 60), 504, 588, 756 (E = 42) and 800: those lengths
 // take the generic last pass
 #define KBN_FAST_LAST_SIZES(X) \
-    X(128) X(160) X(192) X(200) X(256) X(320) X(384) X(392) X(400) X(432) X(448) X(450) X(486) X(500) \
-    X(512) X(540) X(576) X(600) X(640) X(648) X(672) X(686) X(720) X(750) X(768) X(1024)
+    X(128) X(160) X(192) X(200) X(256) X(270) X(288) X(300) X(320) X(324) X(360) X(384) X(392) X(400) \
+    X(432) X(448) X(450) X(486) X(500) X(512) X(540) X(576) X(600) X(640) X(648) X(672) X(686) X(720) \
+    X(750) X(768) X(1024)
 
 }  // namespace
 
