@@ -166,3 +166,64 @@ int ndft_adjoint(int D, const int64_t *N, int64_t M, const double *omega, int nc
     }
     return 0;
 }
+
+/*
+ * Forward sum for an image that is zero outside the listed voxels:
+ *   y[c*M + m] = sum_k x[c*npix + k] exp(-i omega_m . r_{pix[k]})   for c < nch,
+ * i.e. eq. (e,ndft) with the zero terms left out.  The per-axis factors
+ * exp(-i omega_{m,d} r) are direct libm calls for every coordinate of the
+ * axis, as in ndft_forward; each listed voxel multiplies its D factors.
+ * Used for problems whose image has too many voxels for the dense sum.
+ */
+int ndft_forward_sparse(int D, const int64_t *N, int64_t M, const double *omega, int nch,
+                        const int64_t *pix, int64_t npix, const double *x, double *y) {
+    if (D < 1 || D > 3 || nch < 1 || npix < 0) return -1;
+    int64_t n3[3];
+    shape3(D, N, n3);
+    const int off = 3 - D;
+    int64_t *jj = (int64_t *)malloc(sizeof(int64_t) * 3 * (npix > 0 ? npix : 1));
+    for (int64_t k = 0; k < npix; ++k) {
+        const int64_t j = pix[k];
+        jj[3 * k + 2] = j % n3[2];
+        jj[3 * k + 1] = (j / n3[2]) % n3[1];
+        jj[3 * k] = j / (n3[1] * n3[2]);
+    }
+#pragma omp parallel
+    {
+        double *e[3];
+        for (int a = 0; a < 3; ++a) e[a] = (double *)malloc(sizeof(double) * 2 * n3[a]);
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t m = 0; m < M; ++m) {
+            for (int a = 0; a < 3; ++a) {
+                const int d = a - off;
+                const double om = d >= 0 ? omega[m * D + d] : 0.0;
+                for (int64_t j = 0; j < n3[a]; ++j) {
+                    const double ph = om * (d >= 0 ? coord(j, n3[a]) : 0.0);
+                    e[a][2 * j] = cos(ph);
+                    e[a][2 * j + 1] = -sin(ph);
+                }
+            }
+            for (int c = 0; c < nch; ++c) {
+                const double *xc = x + 2 * c * npix;
+                double sr = 0.0, si = 0.0;
+                for (int64_t k = 0; k < npix; ++k) {
+                    /* product of the three axis factors */
+                    const double *f0 = e[0] + 2 * jj[3 * k], *f1 = e[1] + 2 * jj[3 * k + 1],
+                                 *f2 = e[2] + 2 * jj[3 * k + 2];
+                    const double ar = f0[0] * f1[0] - f0[1] * f1[1];
+                    const double ai = f0[0] * f1[1] + f0[1] * f1[0];
+                    const double pr = ar * f2[0] - ai * f2[1];
+                    const double pi = ar * f2[1] + ai * f2[0];
+                    const double xr = xc[2 * k], xi = xc[2 * k + 1];
+                    sr += pr * xr - pi * xi;
+                    si += pr * xi + pi * xr;
+                }
+                y[2 * (c * M + m)] = sr;
+                y[2 * (c * M + m) + 1] = si;
+            }
+        }
+        for (int a = 0; a < 3; ++a) free(e[a]);
+    }
+    free(jj);
+    return 0;
+}

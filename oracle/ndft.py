@@ -40,6 +40,9 @@ def lib():
             fn.restype = ctypes.c_int
             fn.argtypes = [ctypes.c_int, i64p, ctypes.c_int64, dp, ctypes.c_int, dp,
                            ctypes.c_int, i64p, ctypes.c_int64, dp]
+        _lib.ndft_forward_sparse.restype = ctypes.c_int
+        _lib.ndft_forward_sparse.argtypes = [ctypes.c_int, i64p, ctypes.c_int64, dp, ctypes.c_int,
+                                             i64p, ctypes.c_int64, dp, dp]
         _lib.ndft_num_threads.restype = ctypes.c_int
     return _lib
 
@@ -119,6 +122,35 @@ def adjoint(omega, y, N, wdim: int = -1, pix=None) -> np.ndarray:
                                 P, _ptr(x.view(np.float64), ctypes.c_double))
         assert rc == 0
     return x.reshape(oshape)
+
+
+def forward_sparse(omega, vals, pix, N) -> np.ndarray:
+    """y = A(omega) x for an image x that is zero except x[pix[k]] = vals[..., k].
+
+    The sum of eq. (e,ndft) over the listed voxels only (flat row-major
+    indices, no repeats), for problems whose dense sum is too long.
+    vals: [..., P] complex; returns [..., M] complex128.
+    """
+    N = tuple(int(n) for n in N)
+    D = len(N)
+    om = np.ascontiguousarray(omega, dtype=np.float64).reshape(-1, D)
+    M = om.shape[0]
+    vals = _c128(vals)
+    lead = vals.shape[:-1]
+    nch = int(np.prod(lead)) if lead else 1
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    P = pix.shape[0]
+    assert vals.shape[-1] == P and np.unique(pix).size == P
+    vv = np.ascontiguousarray(vals.reshape(nch, P))
+    Na = np.array(N, dtype=np.int64)
+    y = np.empty((nch, M), dtype=np.complex128)
+    if nch and M:
+        rc = lib().ndft_forward_sparse(D, _ptr(Na, ctypes.c_int64), M, _ptr(om, ctypes.c_double), nch,
+                                       _ptr(pix, ctypes.c_int64), P,
+                                       _ptr(vv.view(np.float64), ctypes.c_double),
+                                       _ptr(y.view(np.float64), ctypes.c_double))
+        assert rc == 0
+    return y.reshape(lead + (M,))
 
 
 # ---------------------------------------------------------------------------
@@ -238,3 +270,26 @@ def gram(omega, x, N, smaps=None):
     """z = E^H E x for images x [B, *N]."""
     N = tuple(int(n) for n in N)
     return sense_adjoint(omega, sense_forward(omega, x, N, smaps), N, smaps)
+
+
+def gram_sparse(omega, vals, pix, N, smaps=None, out_pix=None) -> np.ndarray:
+    """z = E^H E x at the voxels out_pix, for one image x that is zero except
+    x[pix[k]] = vals[k] (vals: [P]).  Returns [len(out_pix)] complex128.
+
+    E x = A(s_c (.) x) is summed over the listed voxels only; the adjoint is
+    evaluated at the requested voxels only (Sec. II-E operator, SENSE form
+    of Sec. II-G)."""
+    N = tuple(int(n) for n in N)
+    pix = np.asarray(pix, dtype=np.int64)
+    out_pix = np.asarray(out_pix, dtype=np.int64)
+    vals = _c128(vals).reshape(-1)
+    if smaps is None:
+        sv = vals[None]
+    else:
+        s = _c128(smaps).reshape(_c128(smaps).shape[0], -1)
+        sv = s[:, pix] * vals[None]                   # [C, P]
+    y = forward_sparse(omega, sv, pix, N)            # [C, M]
+    xc = adjoint(omega, y, N, pix=out_pix)            # [C, Q]
+    if smaps is None:
+        return xc[0]
+    return np.sum(np.conj(s[:, out_pix]) * xc, axis=0)

@@ -18,6 +18,7 @@ from paper_2111_02912_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 TOL_NUFFT = 2e-5
+TOL_JAC = 1e-4
 
 
 def _say(msg):
@@ -150,8 +151,9 @@ def test_captured_plan_is_locked(dev):
 
 
 def test_multi_instance_shapes_sampled(dev):
-    """Full-size instance mix, forward and adjoint tasks from one graph;
-    sampled rows (forward) and pixels (adjoint) of three instances, among
+    """Full-size instance mix, forward, adjoint and omega-Jacobian tasks
+    from one graph (the task mix the batch benchmark times); sampled rows
+    (forward, omega-gradient) and pixels (adjoint) of three instances, among
     them the 128^3 kooshball with M = 1,048,576."""
     from paper_2111_02912_amd import batch as KB
     _say("multi-instance full shapes")
@@ -162,9 +164,11 @@ def test_multi_instance_shapes_sampled(dev):
         C, M, N = inst["coils"], inst["omega"].shape[0], tuple(inst["N"])
         y = torch.empty((1, C, M), dtype=torch.complex64, device=dev)
         xa = torch.empty((1,) + N, dtype=torch.complex64, device=dev)
+        dw = torch.empty((M, len(N)), dtype=torch.float32, device=dev)
         tasks += [KB.Task(it["plan"], KB.FORWARD, 1, C, it["x"], y, it["smaps"]),
+                  KB.Task(it["plan"], KB.JAC_OMEGA_FWD, 1, C, it["x"], dw, it["smaps"], g=it["k"]),
                   KB.Task(it["plan"], KB.ADJOINT, 1, C, it["k"], xa, it["smaps"])]
-        outs.append((y, xa))
+        outs.append((y, xa, dw))
     b = KB.KbnBatch(tasks)
     b.capture()
     b.launch()
@@ -184,6 +188,9 @@ def test_multi_instance_shapes_sampled(dev):
         xc = ndft.adjoint(om, k, N, pix=pix)  # [C, P]
         x_ex = (np.conj(s.reshape(s.shape[0], -1)[:, pix]) * xc).sum(0) if s is not None else xc[0]
         e_a = ndft.rel_l2(_np(outs[i][1]).reshape(-1)[pix], x_ex)
-        _say(f"  instance {i} N={N} M={M} C={inst['coils']}: fwd {e_f:.2e} adj {e_a:.2e}")
-        assert e_f < TOL_NUFFT and e_a < TOL_NUFFT
+        dw_ex = ndft.jac_omega_fwd(om, _np(it["x"]), _np(it["k"]), N, s, rows=rows)
+        e_j = ndft.rel_l2(_np(outs[i][2])[rows], dw_ex)
+        _say(f"  instance {i} N={N} M={M} C={inst['coils']}: fwd {e_f:.2e} adj {e_a:.2e} "
+             f"domega {e_j:.2e}")
+        assert e_f < TOL_NUFFT and e_a < TOL_NUFFT and e_j < TOL_JAC
     b.close()

@@ -178,3 +178,40 @@ def test_inverse_memory_constant_in_iterations(dev):
         omt.grad = None
     _say(f"  peak bytes above inputs / plan workspace for 5, 60, 5 iterations: {peaks}")
     assert peaks[0] == peaks[1] == peaks[2]
+
+
+def test_gram_3d_200x200x100_sampled(dev):
+    """The 3D memory case of the Jacobian test (200 x 200 x 100, 8 coils, one
+    3D spoke of 400 samples; the plan grows its sort tiles past 8 and splits
+    the workspace by coil): z on sampled pixels, dL/domega on every row and
+    dL/dx on sampled pixels against the exact operator."""
+    from paper_2111_02912_amd.autograd import gram
+    from paper_2111_02912_amd.nufft import KbNufft
+    N, C = (200, 200, 100), 8
+    _say(f"gram N={N} C={C} one spoke of 400")
+    om = W.kooshball_3d(1, 400).astype(np.float32)
+    x = W.complex_normal((1,) + N, 6501).astype(np.complex64)
+    g = W.complex_normal((1,) + N, 6502).astype(np.complex64)
+    smaps = W.sense_maps(C, N).astype(np.complex64)
+    plan = KbNufft(N, device=dev)
+    xt = _c(x, dev).requires_grad_(True)
+    omt = _f(om, dev).requires_grad_(True)
+    z = gram(xt, omt, plan, _c(smaps, dev))
+    z.backward(_c(g, dev))
+    pix = np.sort(W.rng(6503).choice(int(np.prod(N)), 48, replace=False))
+    s2 = smaps.reshape(C, -1)
+
+    def eh_at(y):  # sum_c conj(s_c) A^H y_c at pix
+        return np.sum(np.conj(s2[:, pix]) * ndft.adjoint(om, y, N, pix=pix), axis=0)
+
+    ex = ndft.sense_forward(om, x, N, smaps)  # [1, C, M]
+    eg = ndft.sense_forward(om, g, N, smaps)
+    ez = ndft.rel_l2(_np(z).reshape(-1)[pix], eh_at(ex[0]))
+    edx = ndft.rel_l2(_np(xt.grad).reshape(-1)[pix], eh_at(eg[0]))
+    dom_ex = ndft.jac_omega_fwd(om, g, ex, N, smaps) + ndft.jac_omega_fwd(om, x, eg, N, smaps)
+    eo = ndft.rel_l2(_np(omt.grad), dom_ex)
+    info = plan.info()
+    _say(f"  tiles {info.get('tile')}: rel z {ez:.2e}  dx {edx:.2e}  domega {eo:.2e}")
+    assert ez < TOL_GRAM
+    assert edx < TOL_GRAM
+    assert eo < TOL_JAC

@@ -84,6 +84,45 @@ def test_row_and_pixel_subsets():
     assert np.array_equal(ndft.adjoint(om, y, N, pix=pix), fa[:, pix])
 
 
+
+@pytest.mark.parametrize("N", [(11,), (6, 5), (5, 4, 6)])
+def test_sparse_image_forward(N):
+    """A listed-voxel image gives the dense sum of the zero-filled image, and
+    one listed voxel gives the plane wave exp(-i omega . r) in closed form."""
+    D = len(N)
+    n = int(np.prod(N))
+    om = W.uniform_random(29, D, seed=12)
+    g = W.rng(13)
+    pix = g.choice(n, max(1, n // 3), replace=False)
+    vals = _rand_c((2, pix.size), 14)
+    dense = np.zeros((2, n), dtype=np.complex128)
+    dense[:, pix] = vals
+    ys = ndft.forward_sparse(om, vals, pix, N)
+    yd = ndft.forward(om, dense.reshape((2,) + tuple(N)), N)
+    assert np.max(np.abs(ys - yd)) <= 1e-12 * np.max(np.abs(yd))
+    j = int(pix[0])
+    r = np.array(np.unravel_index(j, N), dtype=np.float64) - np.array(N) // 2
+    one = ndft.forward_sparse(om, np.ones(1), np.array([j]), N)
+    assert np.max(np.abs(one - np.exp(-1j * (om.astype(np.float64) @ r)))) <= 1e-14
+
+
+def test_sparse_gram_matches_dense():
+    """E^H E x for a listed-voxel image, at listed output voxels, equals the
+    dense Gram operator of the zero-filled image at those voxels."""
+    N = (7, 6)
+    n = int(np.prod(N))
+    om = W.uniform_random(31, 2, seed=15)
+    smaps = W.sense_maps(3, N)
+    g = W.rng(16)
+    pix = g.choice(n, 9, replace=False)
+    out = g.choice(n, 11, replace=False)
+    vals = _rand_c((9,), 17)
+    dense = np.zeros(n, dtype=np.complex128)
+    dense[pix] = vals
+    zd = ndft.gram(om, dense.reshape((1,) + N), N, smaps).reshape(-1)[out]
+    zs = ndft.gram_sparse(om, vals, pix, N, smaps, out_pix=out)
+    assert np.max(np.abs(zs - zd)) <= 1e-12 * np.max(np.abs(zd))
+
 def _loss_fwd(om, x, smaps, yobs, N):
     y = ndft.sense_forward(om, x, N, smaps)
     return float(np.sum(np.abs(y - yobs) ** 2))
