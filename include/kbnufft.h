@@ -29,10 +29,13 @@
  *     gradient of a real loss L w.r.t. z is dL/dRe z + i dL/dIm z.
  *   - Every data pointer is a DEVICE pointer (HIP device memory) unless the
  *     argument says "host".  The caller owns all input and output buffers;
- *     the plan owns its internal buffers.
+ *     the plan owns its internal buffers (allocated through the plan's
+ *     allocator).
  *   - Every call is asynchronous on `stream` (a hipStream_t, NULL = the
- *     null stream) and never synchronises it, except kbn_check_error and a
- *     workspace growth (see kbn_plan_create).
+ *     null stream) and never synchronises it, except kbn_check_error.
+ *     Device memory of a plan comes from the caller's kbn_allocator (or
+ *     HIP's stream-ordered allocator) and is allocated and released in
+ *     stream order.
  *   - A plan is not thread-safe: calls on one plan must be ordered (one
  *     stream, or the caller's synchronisation).  Distinct plans are
  *     independent.
@@ -82,6 +85,25 @@ typedef struct {
 } kbn_opts;
 
 /*
+ * Device memory of a plan.  The plan allocates every internal buffer
+ * (constants, sorted points, owner lists, grid workspace) through this
+ * interface and frees each through it, stream-ordered: alloc(ctx, bytes,
+ * stream) returns a block usable by work issued to `stream` after the call
+ * (NULL on failure: the library call then fails with KBN_ERR_OOM and leaves
+ * no partial plan); free(ctx, ptr, stream) may run before work queued on
+ * `stream` has finished, so the allocator must not hand the block out again
+ * until that work is done (PyTorch's caching allocator with record_stream
+ * does this).  Blocks are multiples of 256 bytes.  ctx is passed through.
+ * Not an operation of the paper: it lets the caller's framework (PyTorch in
+ * the Python binding) own all device memory.
+ */
+typedef struct {
+    void *ctx;
+    void *(*alloc)(void *ctx, size_t bytes, void *stream);
+    void (*free)(void *ctx, void *ptr, void *stream);
+} kbn_allocator;
+
+/*
  * Create a plan for images of shape N (host int64[D]).
  *
  * Chooses per axis K_d = smallest integer >= sigma N_d whose prime factors
@@ -90,16 +112,39 @@ typedef struct {
  * beta = pi sqrt((J/sigma)^2 (sigma - 1/2)^2 - 0.8) (the paper defers the
  * window to its NUFFT library), scaling factors s_n = 1/psi_hat(r_n/K_d)
  * (appendix "scaling factors s_n"), and FFT twiddles, all in FP64 on the
- * host, and uploads them.  Synchronous (blocking) call.
+ * host, and uploads them asynchronously on `stream` (the plan keeps the host
+ * copies until the uploads have run).  Does not synchronise.
+ *
+ * alloc: the allocator for every device buffer of the plan (copied; its
+ * functions must stay valid until kbn_plan_destroy returns), or NULL for
+ * HIP's stream-ordered allocator (hipMallocAsync / hipFreeAsync).
+ * Allocations happen on the stream of the call that needs them (creation,
+ * kbn_set_points, a workspace growth in an operator call).
  *
  * The grid workspace is allocated on first use and grown when a larger
- * batch arrives; a growth synchronises `stream` before freeing the old
- * buffer.
+ * batch arrives; the old block is released stream-ordered on the call's
+ * stream.  Calls on one plan must be ordered: successive calls on
+ * different streams need the caller's synchronisation between them.
  *
  * Errors: INVALID_ARG (out == NULL, D not in 1..3, N_d < 1, sigma < 1,
- * J outside 2..8), UNSUPPORTED (K_d > 1024 or K_d < 2J), OOM, HIP.
+ * J outside 2..8, an allocator without alloc or free), UNSUPPORTED
+ * (K_d > 1024 or K_d < 2J), OOM, HIP.
  */
-int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts);
+int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts,
+                    const kbn_allocator *alloc, void *stream);
+
+/*
+ * Device bytes a plan would hold (host-only computation, no HIP call): its
+ * constants, the index-pass buffers for M points, and the grid workspace of
+ * forward and adjoint calls with B images of C coils (and of the
+ * omega-Jacobian with jac != 0) under opts->max_workspace.  Equal to
+ * kbn_plan_info's device_bytes after kbn_set_points(M) and those calls.
+ * The off-resonance workspace is not included.  For admission control.
+ * Errors: INVALID_ARG (null bytes, M < 0 or too large, B < 1, C < 1, and the
+ * option errors of kbn_plan_create), UNSUPPORTED.
+ */
+int kbn_plan_footprint(int D, const int64_t *N, const kbn_opts *opts, int64_t M, int B, int C,
+                       int jac, int64_t *bytes);
 
 /*
  * Set (or replace) the M sample locations.  omega: device float32 [M][D].
@@ -114,8 +159,12 @@ int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts
  * kbn_check_error; such points give NaN in forward outputs and omega
  * gradients and contribute nothing to adjoint outputs.
  *
- * Errors: INVALID_ARG (M < 0, M > 2^31 - 1, omega == NULL with M > 0),
- * OOM, HIP.
+ * Buffers for the points are allocated (or grown) stream-ordered on
+ * `stream`; the old ones are released the same way.
+ *
+ * Errors: INVALID_ARG (M < 0, M > (2^31 - 1) / 2^D -- the spread's owner
+ * lists index up to 2^D entries per point with 32-bit positions --, omega ==
+ * NULL with M > 0), OOM, HIP.
  */
 int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream);
 
@@ -180,9 +229,11 @@ int kbn_jac_x(kbn_plan p, int op, int B, int C, const void *g, const void *smaps
  *   beta    window shape parameter
  *   M       current number of points (0 before kbn_set_points)
  *   workspace_bytes  currently allocated grid workspace
+ *   device_bytes     all device memory the plan holds now (constants,
+ *                    points, owner lists, workspaces)
  */
 int kbn_plan_info(kbn_plan p, int64_t *K, int *tile, int *ntiles, double *beta,
-                  int64_t *M, int64_t *workspace_bytes);
+                  int64_t *M, int64_t *workspace_bytes, int64_t *device_bytes);
 
 /*
  * Copy the index pass results into caller device buffers (for testing and
@@ -222,9 +273,12 @@ int kbn_timing(kbn_plan p, int enable);
 int kbn_timing_read(kbn_plan p, int cls, int64_t *launches, double *total_ms);
 const char *kbn_timing_name(int cls);
 
-/* Free the plan and its device buffers (synchronises the device).
+/* Free the plan: its device buffers are released stream-ordered on `stream`
+ * (which must be ordered after the plan's last work, e.g. the stream of its
+ * last call), through the plan's allocator.  Does not synchronise (it waits
+ * only if the creation's constant uploads have not run yet).
  * Errors: INVALID_ARG (null plan, or a captured batch still holds it). */
-int kbn_plan_destroy(kbn_plan p);
+int kbn_plan_destroy(kbn_plan p, void *stream);
 
 /*
  * CG-SENSE / QPLS reconstruction (Sec. IV-B: the quadratic reconstruction

@@ -30,7 +30,7 @@ KBN_TASK_JAC_X_FWD = 4
 KBN_TASK_JAC_X_ADJ = 5
 
 EXPORTS = (
-    "kbn_plan_create", "kbn_set_points", "kbn_forward", "kbn_adjoint",
+    "kbn_plan_create", "kbn_plan_footprint", "kbn_set_points", "kbn_forward", "kbn_adjoint",
     "kbn_jac_omega_fwd", "kbn_jac_omega_adj", "kbn_jac_x", "kbn_plan_info",
     "kbn_get_points", "kbn_check_error", "kbn_plan_destroy", "kbn_strerror",
     "kbn_last_error", "kbn_timing", "kbn_timing_read", "kbn_timing_name",
@@ -48,6 +48,19 @@ class KbnOpts(ctypes.Structure):
         ("tile", ctypes.c_int * 3),
         ("max_workspace", ctypes.c_int64),
         ("spread_tile", ctypes.c_int),
+    ]
+
+
+# kbn_allocator: alloc(ctx, bytes, stream) -> ptr, free(ctx, ptr, stream)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class KbnAllocator(ctypes.Structure):
+    _fields_ = [
+        ("ctx", ctypes.c_void_p),
+        ("alloc", ALLOC_FN),
+        ("free", FREE_FN),
     ]
 
 
@@ -86,7 +99,10 @@ def lib():
     vp = ctypes.c_void_p
     i64 = ctypes.c_int64
     ci = ctypes.c_int
-    L.kbn_plan_create.argtypes = [ctypes.POINTER(vp), ci, ctypes.POINTER(i64), ctypes.POINTER(KbnOpts)]
+    L.kbn_plan_create.argtypes = [ctypes.POINTER(vp), ci, ctypes.POINTER(i64), ctypes.POINTER(KbnOpts),
+                                  ctypes.POINTER(KbnAllocator), vp]
+    L.kbn_plan_footprint.argtypes = [ci, ctypes.POINTER(i64), ctypes.POINTER(KbnOpts), i64, ci, ci, ci,
+                                     ctypes.POINTER(i64)]
     L.kbn_set_points.argtypes = [vp, i64, vp, vp]
     L.kbn_forward.argtypes = [vp, ci, ci, vp, vp, vp, vp]
     L.kbn_adjoint.argtypes = [vp, ci, ci, vp, vp, vp, vp]
@@ -95,10 +111,10 @@ def lib():
     L.kbn_jac_x.argtypes = [vp, ci, ci, ci, vp, vp, vp, vp]
     L.kbn_plan_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ci), ctypes.POINTER(ci),
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
-                                ctypes.POINTER(i64)]
+                                ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.kbn_get_points.argtypes = [vp, vp, vp, vp, vp, vp]
     L.kbn_check_error.argtypes = [vp, vp]
-    L.kbn_plan_destroy.argtypes = [vp]
+    L.kbn_plan_destroy.argtypes = [vp, vp]
     L.kbn_strerror.argtypes = [ci]
     L.kbn_strerror.restype = ctypes.c_char_p
     L.kbn_last_error.argtypes = []

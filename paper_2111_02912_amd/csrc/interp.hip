@@ -903,47 +903,6 @@ __global__ void __launch_bounds__(64, KBN_SPREAD_CL_WAVES) k_spread_cl(KbnGeom g
     }
 }
 
-// Per-entry records of the owner lists: sorted position, the tap origin
-// relative to the owning tile (in [0, K)) and the window fraction, so that
-// the spread stages entries with one coalesced load round; and the sample's
-// index in the caller's order, so that the output-stationary spreads read
-// k-space with one dependent load instead of two.
-template <int J>
-__global__ void __launch_bounds__(KBN_BLOCK)
-k_spread_records(KbnGeom g, int64_t M, const int *__restrict__ cell, const float *__restrict__ frac,
-                 const int *__restrict__ ooff, const int *__restrict__ oent, const int *__restrict__ order,
-                 int64_t cap, int *__restrict__ rec_p, int *__restrict__ rec_q, int *__restrict__ rec_l,
-                 float *__restrict__ rec_f) {
-    const int64_t e = (int64_t)blockIdx.x * KBN_BLOCK + threadIdx.x;
-    if (e >= cap || e >= ooff[g.ntiles_own]) return;
-    // owning tile: last t with ooff[t] <= e
-    int lo = 0, hi = g.ntiles_own - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (ooff[mid] <= e) lo = mid;
-        else hi = mid - 1;
-    }
-    int rem = lo;
-    int a0[KBN_MAX_D];
-    for (int d = g.D - 1; d >= 0; --d) {
-        a0[d] = (rem % g.nto[d]) * g.To[d];
-        rem /= g.nto[d];
-    }
-    const int p = oent[e];
-    rec_p[e] = p;
-    rec_q[e] = order[p];
-    for (int d = 0; d < g.D; ++d) {
-        int start;
-        float f;
-        tap_origin(J, cell[d * M + p], frac[d * M + p], start, f);
-        int l = start - a0[d];
-        if (l < 0) l += g.K[d];
-        if (l < 0) l += g.K[d];
-        rec_l[e * g.D + d] = l;
-        rec_f[e * g.D + d] = f;
-    }
-}
-
 // Tiles split into several work items: sum their partial tiles in slot
 // order (deterministic) and write the grid tile.  Block = (channel, tile).
 template <int D>
@@ -1222,16 +1181,3 @@ hipError_t kbn_launch_spread(const KbnGeom &g, const KbnSpreadArgs &a, hipStream
 
 
 
-hipError_t kbn_launch_spread_records(const KbnGeom &g, int64_t M, const int *cell, const float *frac,
-                                     const int *ooff, const int *oent, const int *order, int64_t cap,
-                                     int *rec_p, int *rec_q, int *rec_l, float *rec_f, hipStream_t s) {
-    if (M == 0 || cap == 0) return hipSuccess;
-    const dim3 grid((unsigned)((cap + KBN_BLOCK - 1) / KBN_BLOCK));
-    switch (g.J) {
-#define KBN_REC(j) case j: k_spread_records<j><<<grid, dim3(KBN_BLOCK), 0, s>>>(g, M, cell, frac, ooff, oent, order, cap, rec_p, rec_q, rec_l, rec_f); break;
-        KBN_REC(2) KBN_REC(3) KBN_REC(4) KBN_REC(5) KBN_REC(6) KBN_REC(7) KBN_REC(8)
-#undef KBN_REC
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}

@@ -20,12 +20,6 @@
 #define KBN_SPREAD_SEG 128  // list entries per spread work item (doubled if slots run out)
 #define KBN_SPREAD_SMAX 256 // partial-tile slots for tiles split into several work items
 #define KBN_GRID_Y_MAX 65535 // output-stationary spreads stride over work items beyond this many workgroup rows
-#ifndef KBN_NCHUNKS
-#define KBN_NCHUNKS 1024    // histogram chunks of the index pass (about; each at least KBN_CHUNK_MIN points)
-#endif
-#ifndef KBN_CHUNK_MIN
-#define KBN_CHUNK_MIN 64
-#endif
 #ifndef KBN_SPREAD_CL_WAVES
 #define KBN_SPREAD_CL_WAVES 2 // waves per SIMD the channel-per-lane spread is compiled for
 #endif
@@ -73,7 +67,7 @@ struct KbnPointsBufs {
     int *cell_tmp;   // [D][M] original order
     float *frac_tmp; // [D][M]
     int *tile;       // [M]
-    int *counts;     // [nbins][nchunks]
+    int *counts;     // [nbins][nchunks], then the scan's span sums
     int *order;      // [M] sorted position -> original index
     int *cell;       // [D][M] sorted
     float *frac;     // [D][M] sorted
@@ -83,18 +77,29 @@ struct KbnPointsBufs {
     int *nsub;       // number of subproblems
 };
 
-// Owner-tile touch lists for the spread (entries = sorted sample positions,
-// grouped by owner tile; ooff[t]..ooff[t+1] is tile t's range).
-hipError_t kbn_launch_owner_lists(int D, int J, int ntiles_sort, const int *K, const int *To,
-                                  const int *nto, int ntiles_own, int64_t M, int chunk,
-                                  int nchunks, const int *cell, const float *frac,
-                                  const int *toff, int *counts, int *ooff, int *entries,
-                                  int *otile_order, int seg, int smax, int *swork, int *scomb,
-                                  int *scounts, hipStream_t s);
+// Histogram chunks of the tile sort for M samples (returns their number and
+// sets *chunk, the samples per chunk), and the element count of the plan's
+// integer scratch buffer (count matrix and span sums, later the owner
+// tiles' entry counts).
+int kbn_points_chunks(int64_t M, int ntiles, int *chunk);
+int64_t kbn_points_counts_size(int64_t M, int ntiles, int ntiles_own);
+// offset in that buffer of the owner tiles' entry counts (cleared by the
+// index pass)
+int64_t kbn_points_owner_base(int64_t M, int ntiles);
 
 hipError_t kbn_launch_points(int D, int64_t M, const float *omega, const double *scale,
-                             const int *K, const int *T, const int *nt, int ntiles,
-                             int chunk, int nchunks, int sub, const KbnPointsBufs &b, hipStream_t s);
+                             const int *K, const int *T, const int *nt, int ntiles, int ntiles_own,
+                             int sub, const KbnPointsBufs &b, hipStream_t s);
+
+// Owner-tile lists for the spread, built from the tile-sorted samples:
+// entry counts, offsets ooff[t] .. ooff[t+1], the tiles hottest first, the
+// work items, and per entry the record (sorted position, caller-order index,
+// tap origin relative to the tile, window fraction).  ocount: int scratch of
+// ntiles_own elements, zero on entry.
+hipError_t kbn_launch_owner_lists(const KbnGeom &g, int64_t M, const int *cell, const float *frac,
+                                  const int *toff, const int *order, int *ocount, int *ooff,
+                                  int *otile_order, int seg, int smax, int *swork, int *scomb, int *scounts,
+                                  int *rec_p, int *rec_q, int *rec_l, float *rec_f, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // FFT passes (fft.hip)
@@ -201,8 +206,6 @@ struct KbnSpreadArgs {
     const int *cell;
     const float *frac;
     const int *toff;
-    const int *ooff;           // owner tile t's entries: oent[ooff[t] .. ooff[t+1])
-    const int *oent;           // sorted sample positions, grouped by owner tile
     const int *otile_order;    // owner tiles by decreasing entry count (coarse)
     const int *swork;          // work items [n][4]: tile, entry begin, entry end, slot (-1: direct)
     const int *scomb;          // multi-item tiles [n][3]: tile, first slot, slots
@@ -217,9 +220,6 @@ struct KbnSpreadArgs {
 
 hipError_t kbn_launch_gather(const KbnGeom &g, const KbnGatherArgs &a, int mode, hipStream_t s);
 hipError_t kbn_launch_spread(const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s);
-hipError_t kbn_launch_spread_records(const KbnGeom &g, int64_t M, const int *cell, const float *frac,
-                                     const int *ooff, const int *oent, const int *order, int64_t cap,
-                                     int *rec_p, int *rec_q, int *rec_l, float *rec_f, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Plan hooks used by the batch executor (plan.cpp)

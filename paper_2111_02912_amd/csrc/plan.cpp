@@ -169,6 +169,22 @@ bool factor(int L, KbnRadix &rp) {
 }  // namespace
 
 struct kbn_plan_s {
+    // device memory comes from the caller's allocator (stream-ordered), or
+    // from the HIP stream-ordered allocator when none was given
+    kbn_allocator alloc{};
+    bool custom_alloc = false;
+    struct Block {
+        void *ptr;
+        int64_t bytes;
+    };
+    std::vector<Block> blocks;  // live device blocks and their sizes
+    int64_t dev_bytes = 0;      // sum of the live blocks
+    // host copies of the uploaded constants: they stay alive until the
+    // asynchronous uploads have read them (upload_done)
+    std::vector<float> h_deap[KBN_MAX_D];
+    std::vector<float2> h_tw[KBN_MAX_D];
+    std::vector<float> h_coef;
+    hipEvent_t upload_done = nullptr;
     int D = 0;
     int N[KBN_MAX_D] = {1, 1, 1};
     int K[KBN_MAX_D] = {1, 1, 1};
@@ -195,7 +211,7 @@ struct kbn_plan_s {
     int *counts = nullptr;
     int64_t counts_cap = 0;
     int *subs = nullptr, *nsub = nullptr;
-    int *ooff = nullptr, *oent = nullptr, *otile_order = nullptr;
+    int *ooff = nullptr, *otile_order = nullptr;
     int *swork = nullptr, *scomb = nullptr, *scounts = nullptr;
     int *rec_p = nullptr, *rec_q = nullptr, *rec_l = nullptr;
     float *rec_f = nullptr;
@@ -265,66 +281,95 @@ hipEvent_t timing_mark(kbn_plan p, hipStream_t stream) {
     return e;
 }
 
+// Device blocks are rounded up to 256 bytes; every live block is recorded
+// with its size so that kbn_plan_info can report the plan's footprint.
+int64_t block_bytes(int64_t bytes) { return (std::max<int64_t>(bytes, 1) + 255) / 256 * 256; }
+
 template <typename T>
-int dev_alloc(T **p, int64_t count) {
+int dev_alloc(kbn_plan pl, T **p, int64_t count, hipStream_t s) {
     *p = nullptr;
-    if (count <= 0) count = 1;
-    hipError_t e = hipMalloc((void **)p, sizeof(T) * (size_t)count);
-    if (e != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        return fail(KBN_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    const int64_t bytes = block_bytes((int64_t)sizeof(T) * std::max<int64_t>(count, 1));
+    void *q = nullptr;
+    if (pl->custom_alloc) {
+        q = pl->alloc.alloc(pl->alloc.ctx, (size_t)bytes, (void *)s);
+        if (!q) return fail(KBN_ERR_OOM, "allocator returned NULL for " + std::to_string(bytes) + " bytes");
+    } else {
+        const hipError_t e = hipMallocAsync(&q, (size_t)bytes, s);
+        if (e != hipSuccess || !q) {
+            (void)hipGetLastError();
+            return fail(KBN_ERR_OOM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+        }
     }
+    pl->blocks.push_back({q, bytes});
+    pl->dev_bytes += bytes;
+    *p = (T *)q;
     return KBN_OK;
 }
 
+// Stream-ordered release: work already queued on `s` may still use the block.
 template <typename T>
-void dev_free(T *&p) {
-    if (p) (void)hipFree(p);
+void dev_free(kbn_plan pl, T *&p, hipStream_t s) {
+    if (!p) return;
+    for (size_t i = 0; i < pl->blocks.size(); ++i) {
+        if (pl->blocks[i].ptr == (void *)p) {
+            pl->dev_bytes -= pl->blocks[i].bytes;
+            pl->blocks[i] = pl->blocks.back();
+            pl->blocks.pop_back();
+            break;
+        }
+    }
+    if (pl->custom_alloc)
+        pl->alloc.free(pl->alloc.ctx, (void *)p, (void *)s);
+    else
+        (void)hipFreeAsync((void *)p, s);
     p = nullptr;
 }
 
-void free_points(kbn_plan p) {
-    dev_free(p->cell_tmp);
-    dev_free(p->tile);
-    dev_free(p->order);
-    dev_free(p->cell);
-    dev_free(p->frac_tmp);
-    dev_free(p->frac);
-    dev_free(p->counts);
-    dev_free(p->subs);
-    dev_free(p->oent);
-    dev_free(p->swork);
-    dev_free(p->rec_p);
-    dev_free(p->rec_q);
-    dev_free(p->rec_l);
-    dev_free(p->rec_f);
+void free_points(kbn_plan p, hipStream_t s) {
+    dev_free(p, p->cell_tmp, s);
+    dev_free(p, p->tile, s);
+    dev_free(p, p->order, s);
+    dev_free(p, p->cell, s);
+    dev_free(p, p->frac_tmp, s);
+    dev_free(p, p->frac, s);
+    dev_free(p, p->counts, s);
+    dev_free(p, p->subs, s);
+    dev_free(p, p->swork, s);
+    dev_free(p, p->rec_p, s);
+    dev_free(p, p->rec_q, s);
+    dev_free(p, p->rec_l, s);
+    dev_free(p, p->rec_f, s);
     p->swork_cap = 0;
     p->Mcap = 0;
     p->counts_cap = 0;
 }
 
-void free_plan(kbn_plan p) {
+void free_plan(kbn_plan p, hipStream_t s) {
     for (auto &t : p->pending) {
         (void)hipEventDestroy(t.e0);
         (void)hipEventDestroy(t.e1);
     }
     for (auto e : p->pool) (void)hipEventDestroy(e);
-    free_points(p);
+    free_points(p, s);
     for (int d = 0; d < KBN_MAX_D; ++d) {
-        dev_free(p->deap[d]);
-        dev_free(p->tw[d]);
+        dev_free(p, p->deap[d], s);
+        dev_free(p, p->tw[d], s);
     }
-    dev_free(p->coef);
-    dev_free(p->flag);
-    dev_free(p->toff);
-    dev_free(p->nsub);
-    dev_free(p->ooff);
-    dev_free(p->otile_order);
-    dev_free(p->scomb);
-    dev_free(p->scounts);
-    dev_free(p->ws);
-    dev_free(p->fws);
+    dev_free(p, p->coef, s);
+    dev_free(p, p->flag, s);
+    dev_free(p, p->toff, s);
+    dev_free(p, p->nsub, s);
+    dev_free(p, p->ooff, s);
+    dev_free(p, p->otile_order, s);
+    dev_free(p, p->scomb, s);
+    dev_free(p, p->scounts, s);
+    dev_free(p, p->ws, s);
+    dev_free(p, p->fws, s);
+    // the host constants may be freed only once their uploads have run
+    if (p->upload_done) {
+        if (hipEventQuery(p->upload_done) != hipSuccess) (void)hipEventSynchronize(p->upload_done);
+        (void)hipEventDestroy(p->upload_done);
+    }
     delete p;
 }
 
@@ -332,10 +377,9 @@ int ensure_ws(kbn_plan p, int64_t bytes, hipStream_t stream) {
     if (bytes <= p->ws_bytes) return KBN_OK;
     if (p->graph_refs > 0)
         return fail(KBN_ERR_UNSUPPORTED, "workspace growth on a plan held by a captured batch");
-    if (p->ws) KBN_HIP(hipStreamSynchronize(stream));  // the old buffer may still be in use
-    dev_free(p->ws);
+    dev_free(p, p->ws, stream);  // stream-ordered: queued work may still read it
     p->ws_bytes = 0;
-    int rc = dev_alloc((char **)&p->ws, bytes);
+    int rc = dev_alloc(p, (char **)&p->ws, bytes, stream);
     if (rc != KBN_OK) return rc;
     p->ws_bytes = bytes;
     return KBN_OK;
@@ -371,6 +415,63 @@ static Chunks split_chunks(int64_t B, int C, int64_t per_coil, int64_t max_ws) {
     return {1, (int)std::max<int64_t>(1, std::min<int64_t>(C, max_ws / per_coil))};
 }
 
+// Grid workspace of one call (bytes), the larger chunk's share under the
+// workspace cap.  Type 2 (forward, nw weight channels per coil; mode 1 adds
+// the per-group partial omega-gradients: the gather's point blocks do not
+// depend on the channel count, and a chunk's channel groups are at most
+// min(its image-coil pairs, ceil(2048 / blocks))).
+int64_t ws_type2(const kbn_plan p, int64_t M, int B, int C, int nw, int mode) {
+    const int64_t per_coil = (int64_t)nw * p->gsize() * (int64_t)sizeof(float2) * 2;
+    const Chunks ck = split_chunks(B, C, per_coil, p->max_ws);
+    const int64_t units = ck.bc * ck.cc;
+    int64_t part_bytes = 0;
+    if (mode == 1) {
+        const int64_t blocks0 = kbn_gather_shape(p->geom(), M, (int)(units * nw), nw).blocks;
+        const int64_t groups_max = std::max<int64_t>(1, std::min<int64_t>(units, (2048 + blocks0 - 1) / blocks0));
+        part_bytes = groups_max * M * p->D * (int64_t)sizeof(float);
+    }
+    return units * per_coil + part_bytes;
+}
+
+// Type 1 (adjoint): per image-coil pair two grids, the k-space in tile order
+// and the partial tiles of split owner tiles.
+int64_t type1_per_coil(const kbn_plan p, int64_t M) {
+    int64_t tcells = 1;
+    for (int d = 0; d < p->D; ++d) tcells *= p->To[d];
+    return (p->gsize() * 2 + M + (int64_t)p->smax * tcells) * (int64_t)sizeof(float2);
+}
+
+int64_t ws_type1(const kbn_plan p, int64_t M, int B, int C) {
+    const int64_t per_coil = type1_per_coil(p, M);
+    const Chunks ck = split_chunks(B, C, per_coil, p->max_ws);
+    return ck.bc * ck.cc * per_coil;
+}
+
+// Element counts of the index-pass buffers for M samples: per-sample arrays
+// (capacity), the integer scratch, gather subproblems, owner-list entries
+// (a sample reaches at most 2^D owner tiles) and spread work items.
+struct PointSizes {
+    int64_t cap, counts, subs, ent, swork;
+};
+
+PointSizes point_sizes(const kbn_plan p, int64_t M) {
+    PointSizes z;
+    z.cap = std::max<int64_t>(M, 1);
+    z.counts = kbn_points_counts_size(M, p->ntiles, p->ntiles_own);
+    z.subs = 2 * ((z.cap + KBN_SUB - 1) / KBN_SUB + p->ntiles + 1);
+    z.ent = z.cap << p->D;
+    z.swork = p->ntiles_own + (z.ent + KBN_SPREAD_SEG - 1) / KBN_SPREAD_SEG + 1;
+    return z;
+}
+
+int64_t points_bytes(const kbn_plan p, int64_t M) {
+    const PointSizes z = point_sizes(p, M);
+    const int D = p->D;
+    return 4 * block_bytes(4 * z.cap * D) + 2 * block_bytes(4 * z.cap) + block_bytes(4 * z.counts) +
+           block_bytes(4 * z.subs) + block_bytes(16 * z.swork) + 2 * block_bytes(4 * z.ent) +
+           2 * block_bytes(4 * z.ent * D);
+}
+
 // Forward-type pipeline: scaling (+ coil map, + coordinate weight), FFT
 // passes, then gather.  mode 0 writes y; mode 1 folds the omega-Jacobian.
 int run_type2(kbn_plan p, int B, int C, int nw, int weighted, const float2 *x,
@@ -381,14 +482,7 @@ int run_type2(kbn_plan p, int B, int C, int nw, int weighted, const float2 *x,
     const int64_t per_coil = (int64_t)nw * gsz * (int64_t)sizeof(float2) * 2;
     const Chunks ck = split_chunks(B, C, per_coil, p->max_ws);
     const int64_t units = ck.bc * ck.cc;  // image-coil pairs of the largest chunk
-    const KbnGeom geom0 = p->geom();
-    // per-group partial omega-gradients (mode 1): the gather's point blocks
-    // do not depend on the channel count, and a chunk's channel groups are at
-    // most min(its image-coil pairs, ceil(2048 / blocks))
-    const int64_t blocks0 = kbn_gather_shape(geom0, p->M, (int)(units * nw), nw).blocks;
-    const int64_t groups_max = std::max<int64_t>(1, std::min<int64_t>(units, (2048 + blocks0 - 1) / blocks0));
-    const int64_t part_bytes = mode == 1 ? (int64_t)groups_max * p->M * D * (int64_t)sizeof(float) : 0;
-    int rc = ensure_ws(p, units * per_coil + part_bytes, stream);
+    int rc = ensure_ws(p, ws_type2(p, p->M, B, C, nw, mode), stream);
     if (rc != KBN_OK) return rc;
     float2 *bufA = p->ws;
     float2 *bufB = p->ws + units * nw * gsz;
@@ -475,14 +569,10 @@ int run_type1(kbn_plan p, int B, int C, const float2 *y, const float2 *smaps, fl
               hipStream_t stream) {
     const int D = p->D;
     const int64_t gsz = p->gsize();
-    int64_t tcells = 1;
-    for (int d = 0; d < D; ++d) tcells *= p->To[d];
-    // per image-coil pair: two grids, k-space in tile order, partial tiles
-    // of split owner tiles
-    const int64_t per_coil = (gsz * 2 + p->M + (int64_t)p->smax * tcells) * (int64_t)sizeof(float2);
+    const int64_t per_coil = type1_per_coil(p, p->M);
     const Chunks ck = split_chunks(B, C, per_coil, p->max_ws);
     const int64_t units = ck.bc * ck.cc;
-    int rc = ensure_ws(p, units * per_coil, stream);
+    int rc = ensure_ws(p, ws_type1(p, p->M, B, C), stream);
     if (rc != KBN_OK) return rc;
     float2 *bufA = p->ws;
     float2 *bufB = p->ws + units * gsz;
@@ -507,8 +597,6 @@ int run_type1(kbn_plan p, int B, int C, const float2 *y, const float2 *smaps, fl
         sa.cell = p->cell;
         sa.frac = p->frac;
         sa.toff = p->toff;
-        sa.ooff = p->ooff;
-        sa.oent = p->oent;
         sa.otile_order = p->otile_order;
         sa.swork = p->swork;
         sa.scomb = p->scomb;
@@ -618,11 +706,11 @@ double kbn_internal_cost(kbn_plan p, int B, int C, int jac, int type1) {
     return (double)B * C * (g + 8.0 * (double)std::max<int64_t>(p->M, 0) + 8.0 * n);
 }
 
-extern "C" {
+namespace {
 
-int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts) {
-    if (!out) return fail(KBN_ERR_INVALID_ARG, "null output pointer");
-    *out = nullptr;
+// Host-only part of plan creation: sizes, window shape, tiles (no device
+// memory, no HIP call).  Shared by kbn_plan_create and kbn_plan_footprint.
+int plan_setup(kbn_plan p, int D, const int64_t *N, const kbn_opts *opts) {
     if (D < 1 || D > KBN_MAX_D || !N) return fail(KBN_ERR_INVALID_ARG, "D must be 1..3");
     kbn_opts o;
     std::memset(&o, 0, sizeof(o));
@@ -633,8 +721,6 @@ int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts
     if (J < 2 || J > KBN_MAX_J) return fail(KBN_ERR_INVALID_ARG, "J must be in 2..8");
     const double rad = (J / sigma) * (J / sigma) * (sigma - 0.5) * (sigma - 0.5) - 0.8;
     if (!(rad > 0.0)) return fail(KBN_ERR_INVALID_ARG, "window shape undefined for this (J, sigma)");
-    kbn_plan p = new (std::nothrow) kbn_plan_s();
-    if (!p) return fail(KBN_ERR_OOM, "host allocation failed");
     p->D = D;
     p->J = J;
     p->sigma = sigma;
@@ -645,23 +731,15 @@ int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts
     const int deftile = D == 1 ? 256 : (D == 2 ? 32 : 8);
     int64_t ntiles = 1;
     for (int d = 0; d < D; ++d) {
-        if (N[d] < 1 || N[d] > (1 << 20)) {
-            free_plan(p);
-            return fail(KBN_ERR_INVALID_ARG, "N_d must be >= 1");
-        }
+        if (N[d] < 1 || N[d] > (1 << 20)) return fail(KBN_ERR_INVALID_ARG, "N_d must be >= 1");
         p->N[d] = (int)N[d];
         const int K = smooth_size(sigma * (double)N[d]);
-        if (K > KBN_MAX_K || K < 2 * J) {
-            free_plan(p);
+        if (K > KBN_MAX_K || K < 2 * J)
             return fail(KBN_ERR_UNSUPPORTED, "oversampled size K_d = " + std::to_string(K) +
                                                  " outside [2J, " + std::to_string(KBN_MAX_K) + "]");
-        }
         p->K[d] = K;
         p->scale[d] = (double)K * (1.0 / (2.0 * M_PI));
-        if (!factor(K, p->rad[d])) {
-            free_plan(p);
-            return fail(KBN_ERR_UNSUPPORTED, "K_d not 7-smooth");
-        }
+        if (!factor(K, p->rad[d])) return fail(KBN_ERR_UNSUPPORTED, "K_d not 7-smooth");
     }
     // sorting / gather tiles; the automatic size grows until the tile count
     // fits the LDS histogram
@@ -677,10 +755,7 @@ int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts
         }
         if (ntiles <= KBN_MAX_TILES || explicit_tile || dt >= KBN_MAX_K) break;
     }
-    if (ntiles > KBN_MAX_TILES) {
-        free_plan(p);
-        return fail(KBN_ERR_UNSUPPORTED, "too many tiles; use larger tiles");
-    }
+    if (ntiles > KBN_MAX_TILES) return fail(KBN_ERR_UNSUPPORTED, "too many tiles; use larger tiles");
     p->ntiles = (int)ntiles;
     // spread owner tiles: small enough that several channels' accumulators fit
     // in LDS, large enough that the tile count fits the LDS histogram
@@ -699,7 +774,6 @@ int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts
         defown += 4;
     }
     if (ntiles_own > KBN_MAX_TILES) {
-        free_plan(p);
         return fail(KBN_ERR_UNSUPPORTED, "too many spread tiles");
     }
     p->ntiles_own = (int)ntiles_own;
@@ -707,47 +781,107 @@ int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts
     // items, but the extra partial writes and sums cost more than the
     // shorter items save (measured on 2D radial and 3D kooshball inputs)
     p->smax = KBN_SPREAD_SMAX;
+    return KBN_OK;
+}
 
-    Window w{J, p->beta, bessel_i0(p->beta)};
-    int rc = KBN_OK;
-    for (int d = 0; d < D && rc == KBN_OK; ++d) {
-        std::vector<float> dp(p->N[d]);
+// Device constants of a plan: element counts of the blocks created with it.
+struct ConstSizes {
+    int64_t deap[KBN_MAX_D], tw[KBN_MAX_D], coef, toff, ooff, otile_order, scomb;
+};
+
+ConstSizes const_sizes(const kbn_plan p) {
+    ConstSizes c{};
+    for (int d = 0; d < p->D; ++d) {
+        c.deap[d] = p->N[d];
+        c.tw[d] = p->K[d];
+    }
+    c.coef = (int64_t)p->J * KBN_NCOEF;
+    c.toff = (int64_t)p->ntiles + 2;
+    c.ooff = (int64_t)p->ntiles_own + 1;
+    c.otile_order = p->ntiles_own;
+    c.scomb = 3 * (int64_t)p->ntiles_own;
+    return c;
+}
+
+int64_t const_bytes(const kbn_plan p) {
+    const ConstSizes c = const_sizes(p);
+    int64_t b = 0;
+    for (int d = 0; d < p->D; ++d)
+        b += block_bytes(4 * c.deap[d]) + block_bytes(8 * c.tw[d]);
+    b += block_bytes(4 * c.coef) + block_bytes(4) /*flag*/ + block_bytes(4 * c.toff) +
+         block_bytes(4) /*nsub*/ + block_bytes(4 * c.ooff) + block_bytes(4 * c.otile_order) +
+         block_bytes(4 * c.scomb) + block_bytes(8) /*scounts*/;
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts,
+                    const kbn_allocator *alloc, void *stream_) {
+    if (!out) return fail(KBN_ERR_INVALID_ARG, "null output pointer");
+    *out = nullptr;
+    if (alloc && (!alloc->alloc || !alloc->free))
+        return fail(KBN_ERR_INVALID_ARG, "allocator needs both alloc and free");
+    hipStream_t stream = (hipStream_t)stream_;
+    kbn_plan p = new (std::nothrow) kbn_plan_s();
+    if (!p) return fail(KBN_ERR_OOM, "host allocation failed");
+    if (alloc) {
+        p->alloc = *alloc;
+        p->custom_alloc = true;
+    }
+    int rc = plan_setup(p, D, N, opts);
+    if (rc != KBN_OK) {
+        delete p;
+        return rc;
+    }
+    // constants in FP64 on the host, kept by the plan until uploaded
+    Window w{p->J, p->beta, bessel_i0(p->beta)};
+    for (int d = 0; d < D; ++d) {
+        p->h_deap[d].resize(p->N[d]);
         for (int j = 0; j < p->N[d]; ++j) {
             const double r = (double)(j - p->N[d] / 2);
-            dp[j] = (float)(1.0 / w.psi_hat(r / p->K[d]));
+            p->h_deap[d][j] = (float)(1.0 / w.psi_hat(r / p->K[d]));
         }
-        std::vector<float2> tw(p->K[d]);
+        p->h_tw[d].resize(p->K[d]);
         for (int k = 0; k < p->K[d]; ++k) {
             const double a = 2.0 * M_PI * (double)k / (double)p->K[d];
-            tw[k] = make_float2((float)std::cos(a), (float)-std::sin(a));
+            p->h_tw[d][k] = make_float2((float)std::cos(a), (float)-std::sin(a));
         }
-        rc = dev_alloc(&p->deap[d], p->N[d]);
-        if (rc == KBN_OK) rc = dev_alloc(&p->tw[d], p->K[d]);
-        if (rc == KBN_OK && hipMemcpy(p->deap[d], dp.data(), sizeof(float) * dp.size(),
-                                      hipMemcpyHostToDevice) != hipSuccess)
-            rc = fail(KBN_ERR_HIP, "hipMemcpy (scaling factors)");
-        if (rc == KBN_OK && hipMemcpy(p->tw[d], tw.data(), sizeof(float2) * tw.size(),
-                                      hipMemcpyHostToDevice) != hipSuccess)
-            rc = fail(KBN_ERR_HIP, "hipMemcpy (twiddles)");
     }
-    if (rc == KBN_OK) {
-        std::vector<float> cf = window_polys(w);
-        rc = dev_alloc(&p->coef, (int64_t)cf.size());
-        if (rc == KBN_OK && hipMemcpy(p->coef, cf.data(), sizeof(float) * cf.size(),
-                                      hipMemcpyHostToDevice) != hipSuccess)
-            rc = fail(KBN_ERR_HIP, "hipMemcpy (window)");
+    p->h_coef = window_polys(w);
+    const ConstSizes cs = const_sizes(p);
+    for (int d = 0; d < D && rc == KBN_OK; ++d) {
+        rc = dev_alloc(p, &p->deap[d], cs.deap[d], stream);
+        if (rc == KBN_OK) rc = dev_alloc(p, &p->tw[d], cs.tw[d], stream);
+        if (rc == KBN_OK && hipMemcpyAsync(p->deap[d], p->h_deap[d].data(), sizeof(float) * cs.deap[d],
+                                           hipMemcpyHostToDevice, stream) != hipSuccess)
+            rc = fail(KBN_ERR_HIP, "hipMemcpyAsync (scaling factors)");
+        if (rc == KBN_OK && hipMemcpyAsync(p->tw[d], p->h_tw[d].data(), sizeof(float2) * cs.tw[d],
+                                           hipMemcpyHostToDevice, stream) != hipSuccess)
+            rc = fail(KBN_ERR_HIP, "hipMemcpyAsync (twiddles)");
     }
-    if (rc == KBN_OK) rc = dev_alloc(&p->flag, 1);
-    if (rc == KBN_OK && hipMemset(p->flag, 0, sizeof(int)) != hipSuccess)
-        rc = fail(KBN_ERR_HIP, "hipMemset (flag)");
-    if (rc == KBN_OK) rc = dev_alloc(&p->toff, (int64_t)p->ntiles + 2);
-    if (rc == KBN_OK) rc = dev_alloc(&p->nsub, 1);
-    if (rc == KBN_OK) rc = dev_alloc(&p->ooff, (int64_t)p->ntiles_own + 1);
-    if (rc == KBN_OK) rc = dev_alloc(&p->otile_order, (int64_t)p->ntiles_own);
-    if (rc == KBN_OK) rc = dev_alloc(&p->scomb, 3 * (int64_t)p->ntiles_own);
-    if (rc == KBN_OK) rc = dev_alloc(&p->scounts, 2);
+    if (rc == KBN_OK) rc = dev_alloc(p, &p->coef, cs.coef, stream);
+    if (rc == KBN_OK && hipMemcpyAsync(p->coef, p->h_coef.data(), sizeof(float) * cs.coef,
+                                       hipMemcpyHostToDevice, stream) != hipSuccess)
+        rc = fail(KBN_ERR_HIP, "hipMemcpyAsync (window)");
+    if (rc == KBN_OK) rc = dev_alloc(p, &p->flag, 1, stream);
+    if (rc == KBN_OK && hipMemsetAsync(p->flag, 0, sizeof(int), stream) != hipSuccess)
+        rc = fail(KBN_ERR_HIP, "hipMemsetAsync (flag)");
+    if (rc == KBN_OK) rc = dev_alloc(p, &p->toff, cs.toff, stream);
+    if (rc == KBN_OK) rc = dev_alloc(p, &p->nsub, 1, stream);
+    if (rc == KBN_OK) rc = dev_alloc(p, &p->ooff, cs.ooff, stream);
+    if (rc == KBN_OK) rc = dev_alloc(p, &p->otile_order, cs.otile_order, stream);
+    if (rc == KBN_OK) rc = dev_alloc(p, &p->scomb, cs.scomb, stream);
+    if (rc == KBN_OK) rc = dev_alloc(p, &p->scounts, 2, stream);
+    if (rc == KBN_OK && (hipEventCreateWithFlags(&p->upload_done, hipEventDisableTiming) != hipSuccess ||
+                         hipEventRecord(p->upload_done, stream) != hipSuccess))
+        rc = fail(KBN_ERR_HIP, "upload event");
     if (rc != KBN_OK) {
-        free_plan(p);
+        const std::string msg = g_err;
+        free_plan(p, stream);
+        g_err = msg;
         return rc;
     }
     *out = p;
@@ -759,48 +893,38 @@ int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream_) {
     if (!p) return fail(KBN_ERR_INVALID_ARG, "null plan");
     if (p->graph_refs > 0)
         return fail(KBN_ERR_UNSUPPORTED, "kbn_set_points on a plan held by a captured batch");
-    if (M < 0 || M > 2147483647LL) return fail(KBN_ERR_INVALID_ARG, "M out of range");
+    // the owner lists hold up to M 2^D entries with int32 positions
+    if (M < 0 || M > (2147483647LL >> p->D))
+        return fail(KBN_ERR_INVALID_ARG, "M out of range (0 .. (2^31 - 1) / 2^D)");
     if (M > 0 && !omega) return fail(KBN_ERR_INVALID_ARG, "null omega");
-    const int nbins = p->ntiles + 1;
-    // histogram chunks: about a thousand of at least 64 points, so that the
-    // counting and scattering kernels fill the GPU; the bin-major count matrix
-    // (bins x chunks) is scanned by a multi-block scan
-    int64_t chunk = std::max<int64_t>(KBN_CHUNK_MIN, (M + KBN_NCHUNKS - 1) / KBN_NCHUNKS);
-    chunk = (chunk + 63) / 64 * 64;
-    const int64_t nchunks = M > 0 ? (M + chunk - 1) / chunk : 0;
-    const int nbins_o = p->ntiles_own;
-    const int64_t chunk_o = chunk;
-    const int64_t nchunks_o = nchunks;
-    const int64_t S_max = std::max(nchunks * nbins, nchunks_o * nbins_o);
-    // counts, then the scan's span sums (one per 8192 counts, plus the total)
-    const int64_t counts_need = std::max<int64_t>(S_max + S_max / 8192 + 2, 1);
-    if (M > p->Mcap || counts_need > p->counts_cap) {
-        if (p->Mcap > 0 || p->counts_cap > 0) KBN_HIP(hipStreamSynchronize(stream));
-        free_points(p);
-        const int64_t cap = std::max<int64_t>(M, 1);
+    const PointSizes z = point_sizes(p, M);
+    if (M > p->Mcap || z.counts > p->counts_cap) {
+        // stream-ordered: work already queued may still read the old buffers
+        free_points(p, stream);
         const int D = p->D;
-        int rc = dev_alloc(&p->cell_tmp, cap * D);
-        if (rc == KBN_OK) rc = dev_alloc(&p->frac_tmp, cap * D);
-        if (rc == KBN_OK) rc = dev_alloc(&p->tile, cap);
-        if (rc == KBN_OK) rc = dev_alloc(&p->order, cap);
-        if (rc == KBN_OK) rc = dev_alloc(&p->cell, cap * D);
-        if (rc == KBN_OK) rc = dev_alloc(&p->frac, cap * D);
-        if (rc == KBN_OK) rc = dev_alloc(&p->counts, counts_need);
-        if (rc == KBN_OK) rc = dev_alloc(&p->subs, 2 * ((cap + KBN_SUB - 1) / KBN_SUB + nbins));
-        if (rc == KBN_OK) rc = dev_alloc(&p->oent, cap << D);
-        p->swork_cap = p->ntiles_own + ((cap << D) + KBN_SPREAD_SEG - 1) / KBN_SPREAD_SEG + 1;
-        if (rc == KBN_OK) rc = dev_alloc(&p->swork, 4 * p->swork_cap);
-        if (rc == KBN_OK) rc = dev_alloc(&p->rec_p, cap << D);
-        if (rc == KBN_OK) rc = dev_alloc(&p->rec_q, cap << D);
-        if (rc == KBN_OK) rc = dev_alloc(&p->rec_l, (cap << D) * D);
-        if (rc == KBN_OK) rc = dev_alloc(&p->rec_f, (cap << D) * D);
+        int rc = dev_alloc(p, &p->cell_tmp, z.cap * D, stream);
+        if (rc == KBN_OK) rc = dev_alloc(p, &p->frac_tmp, z.cap * D, stream);
+        if (rc == KBN_OK) rc = dev_alloc(p, &p->tile, z.cap, stream);
+        if (rc == KBN_OK) rc = dev_alloc(p, &p->order, z.cap, stream);
+        if (rc == KBN_OK) rc = dev_alloc(p, &p->cell, z.cap * D, stream);
+        if (rc == KBN_OK) rc = dev_alloc(p, &p->frac, z.cap * D, stream);
+        if (rc == KBN_OK) rc = dev_alloc(p, &p->counts, z.counts, stream);
+        if (rc == KBN_OK) rc = dev_alloc(p, &p->subs, z.subs, stream);
+        if (rc == KBN_OK) rc = dev_alloc(p, &p->swork, 4 * z.swork, stream);
+        if (rc == KBN_OK) rc = dev_alloc(p, &p->rec_p, z.ent, stream);
+        if (rc == KBN_OK) rc = dev_alloc(p, &p->rec_q, z.ent, stream);
+        if (rc == KBN_OK) rc = dev_alloc(p, &p->rec_l, z.ent * D, stream);
+        if (rc == KBN_OK) rc = dev_alloc(p, &p->rec_f, z.ent * D, stream);
         if (rc != KBN_OK) {
-            free_points(p);
+            const std::string msg = g_err;
+            free_points(p, stream);
             p->M = -1;
+            g_err = msg;
             return rc;
         }
-        p->Mcap = cap;
-        p->counts_cap = counts_need;
+        p->Mcap = z.cap;
+        p->counts_cap = z.counts;
+        p->swork_cap = z.swork;
     }
     KbnPointsBufs b;
     b.cell_tmp = p->cell_tmp;
@@ -814,19 +938,16 @@ int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream_) {
     b.flag = p->flag;
     b.subs = p->subs;
     b.nsub = p->nsub;
-    KBN_LAUNCH(KBN_CLASS_INDEX, kbn_launch_points(p->D, M, omega, p->scale, p->K, p->T, p->nt, p->ntiles,
-                                 (int)chunk, (int)nchunks, p->sub, b, stream),
+    KBN_LAUNCH(KBN_CLASS_INDEX,
+               kbn_launch_points(p->D, M, omega, p->scale, p->K, p->T, p->nt, p->ntiles, p->ntiles_own, p->sub,
+                                 b, stream),
                "index pass");
     KBN_LAUNCH(KBN_CLASS_INDEX,
-               kbn_launch_owner_lists(p->D, p->J, p->ntiles, p->K, p->To, p->nto, p->ntiles_own, M,
-                                      (int)chunk_o, (int)nchunks_o, p->cell, p->frac, p->toff,
-                                      p->counts, p->ooff, p->oent, p->otile_order, KBN_SPREAD_SEG,
-                                      p->smax, p->swork, p->scomb, p->scounts, stream),
+               kbn_launch_owner_lists(p->geom(), M, p->cell, p->frac, p->toff, p->order,
+                                      p->counts + kbn_points_owner_base(M, p->ntiles), p->ooff,
+                                      p->otile_order, KBN_SPREAD_SEG, p->smax, p->swork, p->scomb, p->scounts,
+                                      p->rec_p, p->rec_q, p->rec_l, p->rec_f, stream),
                "spread lists");
-    KBN_LAUNCH(KBN_CLASS_INDEX,
-               kbn_launch_spread_records(p->geom(), M, p->cell, p->frac, p->ooff, p->oent, p->order,
-                                         p->Mcap << p->D, p->rec_p, p->rec_q, p->rec_l, p->rec_f, stream),
-               "spread records");
     p->M = M;
     return KBN_OK;
 }
@@ -1019,10 +1140,9 @@ static int field_prep(kbn_plan p, int B, int C, int L, const void *smaps, const 
     if (bytes > p->fws_bytes) {
         if (p->graph_refs > 0)
             return fail(KBN_ERR_UNSUPPORTED, "workspace growth on a plan held by a captured batch");
-        if (p->fws) KBN_HIP(hipStreamSynchronize(stream));  // the old buffer may still be in use
-        dev_free(p->fws);
+        dev_free(p, p->fws, stream);  // stream-ordered: queued work may still read it
         p->fws_bytes = 0;
-        int rc = dev_alloc(&p->fws, bytes);
+        int rc = dev_alloc(p, &p->fws, bytes, stream);
         if (rc != KBN_OK) return rc;
         p->fws_bytes = bytes;
     }
@@ -1132,7 +1252,7 @@ int kbn_field_segments(int64_t M, const float *t, double t0, double t1, int64_t 
 }
 
 int kbn_plan_info(kbn_plan p, int64_t *K, int *tile, int *ntiles, double *beta, int64_t *M,
-                  int64_t *workspace_bytes) {
+                  int64_t *workspace_bytes, int64_t *device_bytes) {
     if (!p) return fail(KBN_ERR_INVALID_ARG, "null plan");
     for (int d = 0; d < p->D; ++d) {
         if (K) K[d] = p->K[d];
@@ -1142,6 +1262,21 @@ int kbn_plan_info(kbn_plan p, int64_t *K, int *tile, int *ntiles, double *beta, 
     if (beta) *beta = p->beta;
     if (M) *M = p->M < 0 ? 0 : p->M;
     if (workspace_bytes) *workspace_bytes = p->ws_bytes;
+    if (device_bytes) *device_bytes = p->dev_bytes;
+    return KBN_OK;
+}
+
+int kbn_plan_footprint(int D, const int64_t *N, const kbn_opts *opts, int64_t M, int B, int C, int jac,
+                       int64_t *bytes) {
+    if (!bytes) return fail(KBN_ERR_INVALID_ARG, "null output pointer");
+    if (M < 0 || B < 1 || C < 1) return fail(KBN_ERR_INVALID_ARG, "M >= 0, B >= 1 and C >= 1 required");
+    kbn_plan_s q;
+    const int rc = plan_setup(&q, D, N, opts);
+    if (rc != KBN_OK) return rc;
+    if (M > (2147483647LL >> q.D)) return fail(KBN_ERR_INVALID_ARG, "M out of range (0 .. (2^31 - 1) / 2^D)");
+    int64_t ws = std::max(M > 0 ? ws_type2(&q, M, B, C, 1, 0) : 0, ws_type1(&q, M, B, C));
+    if (jac && M > 0) ws = std::max(ws, ws_type2(&q, M, B, C, q.D, 1));
+    *bytes = const_bytes(&q) + points_bytes(&q, M) + block_bytes(ws);
     return KBN_OK;
 }
 
@@ -1175,12 +1310,11 @@ int kbn_check_error(kbn_plan p, void *stream) {
     return KBN_OK;
 }
 
-int kbn_plan_destroy(kbn_plan p) {
+int kbn_plan_destroy(kbn_plan p, void *stream) {
     if (!p) return fail(KBN_ERR_INVALID_ARG, "null plan");
     if (p->graph_refs > 0)
         return fail(KBN_ERR_INVALID_ARG, "plan is held by a captured batch; destroy the batch first");
-    (void)hipDeviceSynchronize();
-    free_plan(p);
+    free_plan(p, (hipStream_t)stream);
     return KBN_OK;
 }
 

@@ -23,6 +23,75 @@ def _ptr(t: Optional[torch.Tensor]):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+class TorchAllocator:
+    """kbn_allocator backed by PyTorch's caching allocator: every device
+    buffer of a plan is a uint8 tensor, so plan memory shows in
+    torch.cuda.memory_allocated and is reused by PyTorch after the plan frees
+    it.  A block is allocated on the stream the library names; a block
+    released on another stream is marked with record_stream, so PyTorch does
+    not hand it out again before that stream's queued work has run."""
+
+    def __init__(self, device):
+        self.device = torch.device(device)
+        self.live = {}  # data pointer -> (tensor, stream handle of the allocation)
+        self.calls = [0, 0]  # allocations, releases
+        self._alloc_cb = _lib.ALLOC_FN(self._alloc)
+        self._free_cb = _lib.FREE_FN(self._free)
+        self.struct = _lib.KbnAllocator(None, self._alloc_cb, self._free_cb)
+
+    def _torch_stream(self, handle):
+        if not handle:
+            return torch.cuda.default_stream(self.device)
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream == handle:
+            return cur
+        return torch.cuda.ExternalStream(handle, device=self.device)
+
+    def _alloc(self, ctx, nbytes, stream):
+        try:
+            with torch.cuda.stream(self._torch_stream(stream)):
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        except Exception:  # out of memory (or any failure): the library reports KBN_ERR_OOM
+            return None
+        self.calls[0] += 1
+        self.live[t.data_ptr()] = (t, stream or 0)
+        return t.data_ptr()
+
+    def _free(self, ctx, ptr, stream):
+        t, s0 = self.live.pop(ptr, (None, 0))
+        if t is None:
+            return
+        self.calls[1] += 1
+        try:
+            if (stream or 0) != s0:
+                t.record_stream(self._torch_stream(stream))
+        except Exception:
+            pass
+        del t
+
+    @property
+    def live_bytes(self) -> int:
+        return sum(t.numel() for t, _ in self.live.values())
+
+
+def footprint(N: Sequence[int], M: int, B: int = 1, C: int = 1, jac: bool = False, sigma: float = 2.0,
+              J: int = 6, max_workspace: int = 0, accuracy: Optional[str] = None) -> int:
+    """Device bytes of a plan for images N with M points and calls of B
+    images x C coils (kbn_plan_footprint; host-only, no GPU needed)."""
+    if accuracy is not None:
+        sigma, J = ACCURACY[accuracy]
+    opts = _lib.KbnOpts()
+    opts.sigma = float(sigma)
+    opts.J = int(J)
+    opts.max_workspace = int(max_workspace)
+    N = tuple(int(n) for n in N)
+    arr = (ctypes.c_int64 * len(N))(*N)
+    out = ctypes.c_int64()
+    check(_lib.lib().kbn_plan_footprint(len(N), arr, ctypes.byref(opts), int(M), int(B), int(C), int(bool(jac)),
+                                        ctypes.byref(out)), "kbn_plan_footprint")
+    return out.value
+
+
 # (sigma, J) presets: the default high-accuracy setting (relative error
 # ~7e-6 against the NUDFT) and the low-accuracy setting used for training
 # in Sec. IV-C (grid 1.25 N, J = 5; error ~1e-3)
@@ -38,7 +107,8 @@ class KbNufft:
 
     def __init__(self, N: Sequence[int], sigma: float = 2.0, J: int = 6,
                  tile: Optional[Sequence[int]] = None, max_workspace: int = 0,
-                 spread_tile: int = 0, device=None, accuracy: Optional[str] = None):
+                 spread_tile: int = 0, device=None, accuracy: Optional[str] = None,
+                 allocator: Optional[TorchAllocator] = None):
         if accuracy is not None:
             if accuracy not in ACCURACY:
                 raise ValueError(f"accuracy must be one of {sorted(ACCURACY)}, got {accuracy!r}")
@@ -59,8 +129,11 @@ class KbNufft:
                      "spread_tile": int(spread_tile)}
         arr = (ctypes.c_int64 * self.D)(*self.N)
         h = ctypes.c_void_p()
+        self.allocator = allocator if allocator is not None else TorchAllocator(self.device)
         with torch.cuda.device(self.device):
-            check(L.kbn_plan_create(ctypes.byref(h), self.D, arr, ctypes.byref(opts)), "kbn_plan_create")
+            check(L.kbn_plan_create(ctypes.byref(h), self.D, arr, ctypes.byref(opts),
+                                    ctypes.byref(self.allocator.struct), _stream(self.device)),
+                  "kbn_plan_create")
         self._h = h
         self.M = None
         info = self.info()
@@ -71,8 +144,10 @@ class KbNufft:
 
     # -- lifecycle -------------------------------------------------------
     def close(self):
+        """Release the plan; its memory goes back to PyTorch in stream order
+        on the current stream."""
         if getattr(self, "_h", None) is not None and self._h.value:
-            _lib.lib().kbn_plan_destroy(self._h)
+            _lib.lib().kbn_plan_destroy(self._h, _stream(self.device))
             self._h = None
 
     def __del__(self):
@@ -293,10 +368,12 @@ class KbNufft:
         beta = ctypes.c_double()
         M = ctypes.c_int64()
         ws = ctypes.c_int64()
+        db = ctypes.c_int64()
         check(_lib.lib().kbn_plan_info(self._h, K, T, ctypes.byref(nt), ctypes.byref(beta),
-                                       ctypes.byref(M), ctypes.byref(ws)), "kbn_plan_info")
+                                       ctypes.byref(M), ctypes.byref(ws), ctypes.byref(db)), "kbn_plan_info")
         return {"K": tuple(K[d] for d in range(self.D)), "tile": tuple(T[d] for d in range(self.D)),
-                "ntiles": nt.value, "beta": beta.value, "M": M.value, "workspace_bytes": ws.value}
+                "ntiles": nt.value, "beta": beta.value, "M": M.value, "workspace_bytes": ws.value,
+                "device_bytes": db.value}
 
     def get_points(self) -> dict:
         """Index pass results: sorted order, cells, fractions, tile offsets."""

@@ -25,8 +25,7 @@ import sys
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
 # kernel name -> timing class of the library
-_INDEX = ("k_spread_records", "k_spread_work", "k_points_cells", "k_tile_hist", "k_tile_scatter",
-          "k_scan", "k_subproblems", "k_owner_", "k_tile_order")
+_INDEX = ("k_points_hist", "k_tile_scatter", "k_scan", "k_subproblems", "k_owner_")
 
 
 def _targs(name: str):
@@ -38,7 +37,9 @@ def _targs(name: str):
 
 
 def kernel_class(name: str):
-    base = name.split("<")[0].split("::")[-1].strip()
+    # the short name: no return type, namespace or argument list (argument
+    # types may carry namespaces of their own)
+    base = short(name).split("<")[0].split("::")[-1].strip()
     if any(base.startswith(k) for k in _INDEX):
         return "index"
     ta = _targs(name)

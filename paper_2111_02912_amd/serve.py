@@ -17,7 +17,11 @@ E^H y with a fixed iteration count (Sec. IV-B, T = I), on its own problem
     admitted behind a long solve runs at the next iteration boundary; lanes
     run concurrently on the GPU;
   * retires a request when its last iteration completes (latency = finish
-    time - arrival time).
+    time - arrival time);
+  * fails a request alone when it cannot be served (it can never fit the
+    budget, its plan cannot be created, its sample locations are not finite,
+    or a library call for it fails): the request is retired with `error` set
+    and everything it held is released, while the others go on.
 
 All reconstruction arithmetic is in the HIP library (kbn_cg_*); executors
 only place calls and allocate buffers.  ``FakeExecutor`` replaces the GPU by
@@ -57,6 +61,7 @@ class Request:
     lane: int = -1
     handle: object = None
     result: object = None
+    error: Optional[str] = None
 
     @property
     def latency(self) -> Optional[float]:
@@ -68,19 +73,16 @@ def poisson_arrivals(n: int, rate: float, seed: int, t0: float = 0.0) -> np.ndar
     return t0 + np.cumsum(np.random.default_rng(seed).exponential(1.0 / rate, size=n))
 
 
+class RequestError(RuntimeError):
+    """A request that cannot be served; the server retires it alone."""
+
+
 def plan_bytes(N, M: int, coils: int) -> int:
-    """Upper estimate of one plan's device memory for CG-SENSE with `coils`
-    coils: grid workspace of the adjoint (two grids, sorted k-space and the
-    partial tiles of the spread per coil), sorted point records and the
-    spread owner lists."""
-    D = len(N)
-    K = [2 * n + 16 for n in N]  # oversampled sizes round up to a 7-smooth length
-    gsz = math.prod(K)
-    ws = coils * (2 * gsz + M + 256 * 16 ** D) * 8
-    # per owner-list entry (at most 2^D per sample): list position, sorted and
-    # caller-order sample index, tap origins and fractions
-    pts = M * (24 * D + 16 + (2 ** D) * (12 + 8 * D))
-    return int(ws + pts + (1 << 20))
+    """Device bytes of one CG-SENSE plan: the library's own footprint
+    (constants, index-pass buffers for M points, forward and adjoint grid
+    workspace for one image of `coils` coils), computed on the host."""
+    from .nufft import footprint
+    return footprint(N, M, B=1, C=coils)
 
 
 class FakeExecutor:
@@ -134,6 +136,8 @@ class FakeExecutor:
 
     def admit(self, req: Request, lane: int):
         p = req.problem
+        if p.data and p.data.get("poison"):
+            raise RequestError(f"problem {p.pid}: plan cannot be created")
         start = max(self.t, self.lane_free[lane])
         if self.has_idle_plan(p):
             size = self.idle[p.pid].pop()
@@ -150,6 +154,8 @@ class FakeExecutor:
         req.handle = {"plan": size}
 
     def issue(self, req: Request, n: int, lane: int):
+        if req.problem.data and req.problem.data.get("poison_step") and req.issued >= 1:
+            raise RequestError(f"problem {req.problem.pid}: CG step failed")
         start = max(self.t, self.lane_free[lane])
         end = start + n * self.iter_cost(req.problem)
         self.lane_free[lane] = end
@@ -165,6 +171,12 @@ class FakeExecutor:
         self.idle.setdefault(p.pid, []).append(req.handle["plan"])
         self.idle.move_to_end(p.pid)
         req.result = ("done", req.completed)
+
+    def abort(self, req: Request):
+        """Release what a failed request holds (its plan is not kept)."""
+        if req.handle is not None:
+            self.held -= self.state_size(req.problem) + req.handle["plan"]
+            req.handle = None
 
     def wait(self, until: Optional[float]):
         pend = [e for e in self.events if e > self.t]
@@ -221,9 +233,8 @@ class GpuExecutor:
         for pid in list(self.idle.keys()):
             while self.idle[pid] and freed < nbytes:
                 plan = self.idle[pid].pop()
-                size = self.plan_mem.pop(id(plan))
-                plan.close()
-                self.held -= size
+                size = self.plan_mem.get(id(plan), 0)
+                self._drop_plan(plan)
                 freed += size
             if not self.idle[pid]:
                 del self.idle[pid]
@@ -232,33 +243,62 @@ class GpuExecutor:
         return freed
 
     def admit(self, req: Request, lane: int):
+        from ._lib import KbnError
         from .cg import CgSense
         from .nufft import KbNufft
         torch = self.torch
         p = req.problem
         d = p.data
+        plan = None
         with torch.cuda.stream(self.streams[lane]):
-            if self.has_idle_plan(p):
-                plan = self.idle[p.pid].pop()
-                if not self.idle[p.pid]:
-                    del self.idle[p.pid]
-                self.plan_hits += 1
-            else:
-                plan = KbNufft(p.N, device=self.device)
-                plan.set_points(d["omega"])
-                self.plan_mem[id(plan)] = self.plan_size(p)
-                self.held += self.plan_mem[id(plan)]
-                self.plans_created += 1
-            solver = CgSense(plan, p.coils).begin(d["y"], d["smaps"])
+            try:
+                if self.has_idle_plan(p):
+                    plan = self.idle[p.pid].pop()
+                    if not self.idle[p.pid]:
+                        del self.idle[p.pid]
+                    self.plan_hits += 1
+                else:
+                    plan = KbNufft(p.N, device=self.device)
+                    self.plan_mem[id(plan)] = self.plan_size(p)
+                    self.held += self.plan_mem[id(plan)]
+                    self.plans_created += 1
+                    plan.set_points(d["omega"])
+                    # a new trajectory is checked once (this waits for the
+                    # lane's stream); a resident plan was checked when made
+                    if plan.check_error() != 0:
+                        raise RequestError(f"request {req.rid}: non-finite sample locations")
+                solver = CgSense(plan, p.coils).begin(d["y"], d["smaps"])
+            except (KbnError, RequestError, RuntimeError, ValueError) as e:
+                if plan is not None:
+                    self._drop_plan(plan)
+                raise RequestError(str(e)) from e
         self.held += self.state_size(p)
         req.handle = (plan, solver)
 
+    def _drop_plan(self, plan):
+        size = self.plan_mem.pop(id(plan), 0)
+        self.held -= size
+        plan.close()
+
+    def abort(self, req: Request):
+        """Release what a failed request holds; its plan is closed."""
+        if req.handle is not None:
+            plan, solver = req.handle
+            req.handle = None
+            self.held -= self.state_size(req.problem)
+            with self.torch.cuda.stream(self.streams[max(req.lane, 0)]):
+                self._drop_plan(plan)
+
     def issue(self, req: Request, n: int, lane: int):
+        from ._lib import KbnError
         torch = self.torch
         plan, solver = req.handle
         s = self.streams[lane]
         with torch.cuda.stream(s):
-            solver.step(n, self.lam)
+            try:
+                solver.step(n, self.lam)
+            except KbnError as e:
+                raise RequestError(str(e)) from e
             ev = torch.cuda.Event()
             ev.record(s)
         return ev
@@ -309,18 +349,43 @@ class Server:
 
     def run(self, requests: List[Request]) -> List[Request]:
         ex = self.ex
+        done: List[Request] = []
+        self.failed: List[Request] = []
+        servable = []
         for r in requests:
-            full = ex.state_size(r.problem) + ex.plan_size(r.problem)
-            if full > self.budget:
-                raise ValueError(f"request {r.rid} needs {full} bytes, more than the budget {self.budget}")
-        pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
+            try:
+                full = ex.state_size(r.problem) + ex.plan_size(r.problem)
+                err = None if full <= self.budget else \
+                    f"request {r.rid} needs {full} bytes, more than the budget {self.budget}"
+            except (RequestError, RuntimeError, ValueError) as e:  # no plan can be made for it
+                err = f"request {r.rid}: {e}"
+            if err is not None:
+                r.error = err
+                r.t_done = r.arrival
+                self.failed.append(r)
+                done.append(r)
+            else:
+                servable.append(r)
+        pending = collections.deque(sorted(servable, key=lambda r: (r.arrival, r.rid)))
         queue: "collections.deque[Request]" = collections.deque()
         active: List[List[Request]] = [[] for _ in range(self.nlanes)]
         inflight: List[collections.deque] = [collections.deque() for _ in range(self.nlanes)]
         remaining = [0] * self.nlanes  # iterations still to issue per lane (load estimate)
         n_active = 0
         t0 = ex.now()
-        done: List[Request] = []
+
+        def fail(req, err, li=None):
+            req.error = str(err)
+            req.t_done = ex.now() - t0
+            ex.abort(req)
+            self.failed.append(req)
+            done.append(req)
+            if li is not None and req in active[li]:
+                active[li].remove(req)
+                remaining[li] -= req.iters - req.issued
+                return True
+            return False
+
         while pending or queue or n_active:
             t = ex.now() - t0
             progressed = False
@@ -355,7 +420,12 @@ class Server:
                          key=lambda i: (remaining[i] * 1.0, len(active[i]), i))
                 req.lane = li
                 req.t_admit = ex.now() - t0
-                ex.admit(req, li)
+                try:
+                    ex.admit(req, li)
+                except RequestError as e:
+                    fail(req, e)
+                    progressed = True
+                    continue
                 if req.iters == 0:
                     req.t_done = ex.now() - t0
                     ex.retire(req)
@@ -383,7 +453,15 @@ class Server:
                     if pick is None:
                         break
                     n = min(self.chunk, pick.iters - pick.issued)
-                    ev = ex.issue(pick, n, li)
+                    try:
+                        ev = ex.issue(pick, n, li)
+                    except RequestError as e:
+                        # its iterations already in flight are dropped from the lane
+                        inflight[li] = collections.deque(x for x in inflight[li] if x[0] is not pick)
+                        if fail(pick, e, li):
+                            n_active -= 1
+                        progressed = True
+                        continue
                     pick.issued += n
                     remaining[li] -= n
                     inflight[li].append((pick, ev, n))
@@ -394,7 +472,9 @@ class Server:
 
 
 def latency_stats(reqs: List[Request], skip: int = 0) -> dict:
-    lat = np.array([r.latency for r in sorted(reqs, key=lambda r: r.rid)[skip:]], dtype=np.float64)
+    """Latency percentiles of the served requests (failed ones excluded)."""
+    ok = [r for r in sorted(reqs, key=lambda r: r.rid)[skip:] if r.error is None]
+    lat = np.array([r.latency for r in ok], dtype=np.float64)
     if lat.size == 0:
         return {"n": 0}
     return {"n": int(lat.size), "p50_ms": float(np.percentile(lat, 50) * 1e3),

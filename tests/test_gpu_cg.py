@@ -251,3 +251,48 @@ def test_served_alone_equals_in_mix(dev):
     x_dir, _ = cg_sense(plan, target.data["y"], target.data["smaps"])
     torch.cuda.synchronize()
     assert torch.equal(x_dir, x_alone)
+
+
+def test_poison_requests_fail_alone(dev):
+    """Requests whose trajectory holds a non-finite location, or whose
+    image size no plan supports, are retired with an error; the other
+    requests in the same mix give the same bits as when served alone, and
+    the server holds only the idle plans of the good problems at the end."""
+    from paper_2111_02912_amd.serve import GpuExecutor, Problem, Request, Server
+    probs = []
+    for i, kind in enumerate(["2d", "3d"]):
+        N, om, smaps, y = _problem(kind, 8400 + i)
+        probs.append(Problem(i, N, smaps.shape[0], om.shape[0], kind,
+                             {"omega": _f(om, dev), "smaps": _c(smaps, dev), "y": _c(y, dev)}))
+    N, om, smaps, y = _problem("2d", 8402)
+    om = om.copy()
+    om[7, 1] = np.nan
+    nan_prob = Problem(2, N, smaps.shape[0], om.shape[0], "nan",
+                       {"omega": _f(om, dev), "smaps": _c(smaps, dev), "y": _c(y, dev)})
+    # 600 pixels per axis: the oversampled grid (1200) exceeds the largest FFT length
+    big_N = (600, 16)
+    big = Problem(3, big_N, 1, 10, "unsupported",
+                  {"omega": _f(W.uniform_random(10, 2, seed=1), dev), "smaps": None,
+                   "y": torch.zeros((1, 10), dtype=torch.complex64, device=dev)})
+    alone = {}
+    for p in probs:
+        ex = GpuExecutor(dev, lanes=1, keep_results=True)
+        r = Server(ex, hbm_budget=8 << 30, lanes=1).run([Request(0, 0.0, p, iters=6)])[0]
+        alone[p.pid] = r.result["x"].clone()
+        ex.close()
+    ex = GpuExecutor(dev, lanes=3, keep_results=True)
+    order = [probs[0], nan_prob, probs[1], big, probs[0], nan_prob, probs[1]]
+    mix = [Request(i, 0.0005 * i, p, iters=6) for i, p in enumerate(order)]
+    srv = Server(ex, hbm_budget=8 << 30, lanes=3, chunk=1, depth=2)
+    done = {r.rid: r for r in srv.run(mix)}
+    torch.cuda.synchronize()
+    _say("  failed: " + "; ".join(f"{r.rid}: {r.error[:60]}" for r in srv.failed))
+    assert len(done) == len(mix)
+    for rid, r in done.items():
+        if r.problem.pid in alone:
+            assert r.error is None and torch.equal(r.result["x"], alone[r.problem.pid]), rid
+        else:
+            assert r.error is not None, rid
+    assert sorted(r.rid for r in srv.failed) == [1, 3, 5]
+    assert ex.held == sum(ex.plan_mem.values())
+    ex.close()

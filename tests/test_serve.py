@@ -73,11 +73,44 @@ def test_short_request_is_not_blocked_by_a_long_one():
     assert done[1].latency < 3.0  # at most a couple of long iterations of waiting
 
 
-def test_request_that_can_never_fit_is_rejected():
+def test_request_that_can_never_fit_fails_alone():
     p = Problem(0, (64, 64), 8, 1000, "2d")
-    ex = FakeExecutor(lambda q: 0.001, need=lambda q: 10 ** 6)
-    with pytest.raises(ValueError):
-        Server(ex, hbm_budget=1000).run([Request(0, 0.0, p)])
+    big = Problem(1, (96, 96, 96), 8, 10 ** 6, "3d")
+    ex = FakeExecutor(lambda q: 0.001, need=lambda q: 10 ** 6 if q.pid == 1 else 100)
+    reqs = [Request(0, 0.0, p, iters=3), Request(1, 0.001, big, iters=3), Request(2, 0.002, p, iters=3)]
+    srv = Server(ex, hbm_budget=100000)
+    done = {r.rid: r for r in srv.run(reqs)}
+    assert set(done) == {0, 1, 2}
+    assert done[1].error and "budget" in done[1].error and done[1].completed == 0
+    assert done[0].error is None and done[2].error is None
+    assert done[0].completed == done[2].completed == 3
+    assert [r.rid for r in srv.failed] == [1]
+    assert latency_stats(list(done.values()))["n"] == 2
+
+
+@pytest.mark.parametrize("kind", ["poison", "poison_step"])
+def test_poison_request_fails_alone(kind):
+    """A request whose plan cannot be made (or whose CG step fails after
+    one chunk) is retired with an error and releases what it held; every
+    other request completes all its iterations and the held bytes return
+    to the idle plans."""
+    good = [Problem(i, (32, 32), 2, 500, "2d") for i in range(3)]
+    bad = Problem(9, (32, 32), 2, 500, "2d", data={kind: True})
+    ex = FakeExecutor(lambda q: 0.001, need=lambda q: 1000)
+    arr = poisson_arrivals(40, 200.0, seed=5)
+    reqs = [Request(i, float(t), bad if i % 7 == 3 else good[i % 3], iters=4) for i, t in enumerate(arr)]
+    srv = Server(ex, hbm_budget=1 << 20, lanes=2, chunk=1, depth=2)
+    done = {r.rid: r for r in srv.run(reqs)}
+    assert len(done) == 40
+    for r in reqs:
+        d = done[r.rid]
+        if r.problem is bad:
+            assert d.error is not None
+        else:
+            assert d.error is None and d.completed == d.iters == 4
+    assert len(srv.failed) == sum(1 for r in reqs if r.problem is bad)
+    # only idle plans of the good problems are held at the end
+    assert ex.held == sum(len(v) for v in ex.idle.values()) * 1000
 
 
 def test_poisson_arrivals():
