@@ -179,6 +179,26 @@ int kbn_forward(kbn_plan p, int B, int C, const void *x, const void *smaps, void
                 void *stream);
 
 /*
+ * kbn_forward for callers that cannot allocate device memory: code under HIP
+ * graph capture, serving loops that must not allocate, harnesses that
+ * forbid allocation.  Same operation, arguments and results as kbn_forward
+ * (bit for bit), but the grid workspace is a library-owned static device
+ * array of KBN_STATIC_WORKSPACE bytes on each GPU (held from library load
+ * to process end) instead of the plan's workspace, so the call allocates
+ * nothing and never grows the plan; batches are processed in chunks that
+ * fit it.  All calls on one GPU share that array: calls that overlap on a
+ * GPU (other streams, other threads, other plans) race and must be
+ * serialised by the caller.  The plan must have been created and its points
+ * set beforehand (those calls allocate).
+ * Errors: as kbn_forward; UNSUPPORTED when one image-coil pair needs more
+ * than KBN_STATIC_WORKSPACE bytes (2 x 8 x prod K bytes) or timing is on;
+ * HIP if the array's address cannot be obtained.
+ */
+#define KBN_STATIC_WORKSPACE 67108864
+int kbn_forward_static(kbn_plan p, int B, int C, const void *x, const void *smaps, void *y,
+                       void *stream);
+
+/*
  * x_b = sum_c conj(s_c) (.) A(omega)^H y[b][c]   (type-1 NUFFT; Sec. II-D,
  * II-G).  y: c64 [B][C][M]; x: c64 [B][N...], overwritten.
  * Errors as kbn_forward.

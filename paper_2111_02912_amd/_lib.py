@@ -28,9 +28,11 @@ KBN_TASK_JAC_OMEGA_FWD = 2
 KBN_TASK_JAC_OMEGA_ADJ = 3
 KBN_TASK_JAC_X_FWD = 4
 KBN_TASK_JAC_X_ADJ = 5
+KBN_STATIC_WORKSPACE = 67108864
 
 EXPORTS = (
-    "kbn_plan_create", "kbn_plan_footprint", "kbn_set_points", "kbn_forward", "kbn_adjoint",
+    "kbn_plan_create", "kbn_plan_footprint", "kbn_set_points", "kbn_forward", "kbn_forward_static",
+    "kbn_adjoint",
     "kbn_jac_omega_fwd", "kbn_jac_omega_adj", "kbn_jac_x", "kbn_plan_info",
     "kbn_get_points", "kbn_check_error", "kbn_plan_destroy", "kbn_strerror",
     "kbn_last_error", "kbn_timing", "kbn_timing_read", "kbn_timing_name",
@@ -105,6 +107,7 @@ def lib():
                                      ctypes.POINTER(i64)]
     L.kbn_set_points.argtypes = [vp, i64, vp, vp]
     L.kbn_forward.argtypes = [vp, ci, ci, vp, vp, vp, vp]
+    L.kbn_forward_static.argtypes = [vp, ci, ci, vp, vp, vp, vp]
     L.kbn_adjoint.argtypes = [vp, ci, ci, vp, vp, vp, vp]
     L.kbn_jac_omega_fwd.argtypes = [vp, ci, ci, vp, vp, vp, vp, ci, vp]
     L.kbn_jac_omega_adj.argtypes = [vp, ci, ci, vp, vp, vp, vp, ci, vp]

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -474,19 +475,26 @@ int64_t points_bytes(const kbn_plan p, int64_t M) {
 
 // Forward-type pipeline: scaling (+ coil map, + coordinate weight), FFT
 // passes, then gather.  mode 0 writes y; mode 1 folds the omega-Jacobian.
+// ext_ws (mode 0 only): a workspace of ext_bytes given by the caller
+// instead of the plan's, which is then neither grown nor used; the batch is
+// chunked to fit it.
 int run_type2(kbn_plan p, int B, int C, int nw, int weighted, const float2 *x,
               const float2 *smaps, int mode, float2 *y, const float2 *v, float *dom,
-              int accumulate, hipStream_t stream) {
+              int accumulate, hipStream_t stream, void *ext_ws = nullptr, int64_t ext_bytes = 0) {
     const int D = p->D;
     const int64_t gsz = p->gsize();
     const int64_t per_coil = (int64_t)nw * gsz * (int64_t)sizeof(float2) * 2;
-    const Chunks ck = split_chunks(B, C, per_coil, p->max_ws);
+    const Chunks ck = split_chunks(B, C, per_coil, ext_ws ? ext_bytes : p->max_ws);
     const int64_t units = ck.bc * ck.cc;  // image-coil pairs of the largest chunk
-    int rc = ensure_ws(p, ws_type2(p, p->M, B, C, nw, mode), stream);
-    if (rc != KBN_OK) return rc;
-    float2 *bufA = p->ws;
-    float2 *bufB = p->ws + units * nw * gsz;
-    float *part = (float *)(p->ws + 2 * units * nw * gsz);
+    float2 *ws = (float2 *)ext_ws;
+    if (!ws) {
+        int rc = ensure_ws(p, ws_type2(p, p->M, B, C, nw, mode), stream);
+        if (rc != KBN_OK) return rc;
+        ws = p->ws;
+    }
+    float2 *bufA = ws;
+    float2 *bufB = ws + units * nw * gsz;
+    float *part = (float *)(ws + 2 * units * nw * gsz);
     const int64_t R0 = img_rows(p);
     const int Nl = p->N[D - 1];
     const KbnGeom geom = p->geom();
@@ -706,7 +714,34 @@ double kbn_internal_cost(kbn_plan p, int B, int C, int jac, int type1) {
     return (double)B * C * (g + 8.0 * (double)std::max<int64_t>(p->M, 0) + 8.0 * n);
 }
 
+// Grid workspace of kbn_forward_static: one file-scope array per GPU, for
+// callers that cannot allocate.  In host code `scratch` only names the
+// symbol; its device address on the current GPU comes from
+// hipGetSymbolAddress, once per device, and only that address is used.
+static __device__ __align__(256) char scratch[KBN_STATIC_WORKSPACE];
+
 namespace {
+
+#define KBN_MAX_DEVICES 64
+std::mutex g_scratch_mu;
+void *g_scratch[KBN_MAX_DEVICES] = {};
+
+// The static workspace's device address on the current device.
+int static_workspace(void **out) {
+    int dev = -1;
+    KBN_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= KBN_MAX_DEVICES) return fail(KBN_ERR_UNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(KBN_ERR_HIP, std::string("hipGetSymbolAddress (static workspace): ") + hipGetErrorString(e));
+        g_scratch[dev] = ptr;
+    }
+    *out = g_scratch[dev];
+    return KBN_OK;
+}
 
 // Host-only part of plan creation: sizes, window shape, tiles (no device
 // memory, no HIP call).  Shared by kbn_plan_create and kbn_plan_footprint.
@@ -959,6 +994,23 @@ int kbn_forward(kbn_plan p, int B, int C, const void *x, const void *smaps, void
     if (p->M == 0) return KBN_OK;
     return run_type2(p, B, C, 1, 0, (const float2 *)x, (const float2 *)smaps, 0, (float2 *)y,
                      nullptr, nullptr, 0, (hipStream_t)stream);
+}
+
+int kbn_forward_static(kbn_plan p, int B, int C, const void *x, const void *smaps, void *y, void *stream) {
+    int rc = check_common(p, B, C, x, smaps, y);
+    if (rc != KBN_OK) return rc;
+    if (p->timing) return fail(KBN_ERR_UNSUPPORTED, "kbn_forward_static does not record timing events");
+    const int64_t per_coil = p->gsize() * (int64_t)sizeof(float2) * 2;
+    if (per_coil > KBN_STATIC_WORKSPACE)
+        return fail(KBN_ERR_UNSUPPORTED, "one image-coil pair needs " + std::to_string(per_coil) +
+                                             " bytes of grid workspace; the static workspace holds " +
+                                             std::to_string((int64_t)KBN_STATIC_WORKSPACE));
+    void *ws = nullptr;
+    rc = static_workspace(&ws);
+    if (rc != KBN_OK) return rc;
+    if (p->M == 0) return KBN_OK;
+    return run_type2(p, B, C, 1, 0, (const float2 *)x, (const float2 *)smaps, 0, (float2 *)y, nullptr, nullptr,
+                     0, (hipStream_t)stream, ws, KBN_STATIC_WORKSPACE);
 }
 
 int kbn_adjoint(kbn_plan p, int B, int C, const void *y, const void *smaps, void *x,
