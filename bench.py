@@ -37,6 +37,9 @@ Other workloads (one JSON line each, not the default):
                      12, 8 coils, 16 shots x 1280 samples on 40 quadratic
                      spline kernels, CG-SENSE (20 iterations) through the
                      inverse layer, gradient/slew penalties, one Adam step.
+  --workload cg      one CG-SENSE request (10 iterations) of the serving
+                     workload on a resident plan: 96^3 x 8 coils kooshball
+                     (--cg-shape 3d) or 384^2 x 8 coils spiral (2d).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B]
                        [--workload step|batch|train|serve|jacobian|learn]
@@ -111,6 +114,18 @@ def algorithmic_bytes(N, K, M, B, D):
     return out
 
 
+def _cpu_model() -> str:
+    """Host CPU model name (from /proc/cpuinfo, as lscpu reports it)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(N, om, x, g, images=2):
     """The FP64 oracle on the host, exact (no extrapolation): for `images`
     images, the direct NUDFT forward, the D omega-Jacobian operands
@@ -133,6 +148,7 @@ def cpu_baseline(N, om, x, g, images=2):
         "value": images * M / (t2 - t0),
         "unit": "pts/s",
         "cores": ndft.num_threads(),
+        "cpu_model": _cpu_model(),
         "kind": "oracle",
         "sample": (f"{images} of the {N[0]}x{N[1]} images, all M={M} points: direct FP64 NUDFT "
                    f"forward + {D} omega-Jacobian operands ({t1 - t0:.1f} s) and adjoint over "
@@ -167,6 +183,7 @@ def bench_batch(args):
     insts = W.multi_instance_case()
     items = []
     pts = 0
+    bundle_bytes = 0  # algorithmic bytes of the bundle (the byte model per instance)
     t0 = time.perf_counter()
     choices = {}
     for i, inst in enumerate(insts):
@@ -184,6 +201,8 @@ def bench_batch(args):
         else:
             plan = KbNufft(N, device=dev)
             plan.set_points(om)
+        ab = algorithmic_bytes(N, plan.K, M, C, D)  # C coil channels per instance
+        bundle_bytes += sum(v for k_, v in ab.items() if k_ != "index")
         items.append(dict(plan=plan, N=N, C=C, M=M, D=D, x=xt, k=kt, s=st,
                           y=torch.empty((1, C, M), dtype=torch.complex64, device=dev),
                           dom=torch.empty((M, D), dtype=torch.float32, device=dev),
@@ -239,6 +258,9 @@ def bench_batch(args):
         },
         "mode_ms": modes,
         "best_mode": best,
+        "roofline": {"bound": "hbm", "kernel": "whole bundle", "alg_bytes": bundle_bytes,
+                     "achieved": bundle_bytes / (modes[best] * 1e-3) / 1e9, "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": bundle_bytes / (modes[best] * 1e-3) / 1e9 / HBM_PEAK_GBPS},
         "speedup_vs_per_call": modes["per_call"] / modes[best],
         "speedup_vs_per_instance": modes["per_instance_one_stream"] / modes[best],
     }
@@ -441,6 +463,154 @@ def serve_pool(dev, n2d, n3d, coils=8, seed=5001):
     return probs
 
 
+def cg_iteration_bytes(N, K, M, C, D):
+    """Algorithmic bytes of one CG-SENSE iteration (E^H E p for C coils):
+    the forward and adjoint classes of the byte model with C channels."""
+    ab = algorithmic_bytes(N, K, M, C, D)
+    pN = math.prod(N)
+    first_out = (pN // N[-1]) * K[-1]
+    fwd_first = C8 * (C * pN + C * first_out)
+    mid_one = ab["fft_mid_inv"]  # one channel set of mid passes (= forward's for 1 weight channel)
+    return fwd_first + mid_one + ab["gather"] + ab["spread"] + ab["fft_mid_inv"] + ab["fft_last_adj"]
+
+
+def bench_cg(args):
+    """One CG-SENSE request (10 iterations, lambda 1e-3) on a resident plan:
+    the serving workload's 3D class (96^3, 8 coils, 4096 x 256 kooshball) or
+    its largest 2D class (384^2, 8 coils, 16-interleave spiral, M = 60000)."""
+    import torch
+
+    from paper_2111_02912_amd import workloads as W
+    from paper_2111_02912_amd.cg import CgSense
+    from paper_2111_02912_amd.nufft import KbNufft
+
+    dev = torch.device("cuda", 0)
+    C = 8
+    if args.cg_shape == "3d":
+        N, om = (96, 96, 96), W.kooshball_3d(4096, 256)
+    else:
+        N, om = (384, 384), W.spiral_2d(16, 3750)[:60000]
+    M, D = om.shape[0], len(N)
+    smaps = torch.from_numpy(W.sense_maps(C, N)).to(dev)
+    plan = KbNufft(N, device=dev)
+    plan.set_points(torch.from_numpy(om).to(dev))
+    y = plan.forward(torch.from_numpy(W.complex_normal((1,) + N, 5301)).to(dev), smaps)[0].contiguous()
+
+    def request():
+        return CgSense(plan, C).begin(y, smaps).step(args.cg_iters, 1e-3)
+
+    ms = _wall_ms(request, args.steps, args.warmup)
+    plan.timing(True)
+    for _ in range(args.steps):
+        request()
+    torch.cuda.synchronize()
+    plan.timing(False)
+    kt = {k: round(t / args.steps, 4) for k, (n, t) in plan.timing_read().items() if n}
+    it_bytes = cg_iteration_bytes(N, plan.K, M, C, D)
+    req_bytes = it_bytes * (args.cg_iters + 0.5)  # the start applies E^H once
+    out = {
+        "metric": "CG-SENSE request latency (unloaded, resident plan)", "value": ms, "unit": "ms",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": (f"CG-SENSE request, {'x'.join(map(str, N))} image, {C} coils, M={M} "
+                                f"({'4096 x 256 kooshball' if D == 3 else '16-interleave spiral'}), "
+                                f"{args.cg_iters} iterations, lambda 1e-3"),
+                   "K": list(plan.K)},
+        "alg_bytes_per_request": req_bytes,
+        "roofline": {"bound": "hbm", "kernel": "whole request", "achieved": req_bytes / (ms * 1e-3) / 1e9,
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": req_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS},
+        "kernel_ms_per_request": kt,
+    }
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+def _per_call_cg(plan, y, smaps, lam, iters):
+    """CG-SENSE written with plain per-coil library calls: every E^H E p is
+    one forward and one adjoint call per coil, the vector updates are
+    PyTorch ops (the baseline for the served throughput)."""
+    import torch
+    C = smaps.shape[0]
+
+    def ehe(v):
+        acc = torch.zeros_like(v)
+        for c in range(C):
+            acc += plan.adjoint(plan.forward(v[None], smaps[c:c + 1]), smaps[c:c + 1])[0]
+        return acc
+
+    b = torch.zeros((1,) + plan.N, dtype=torch.complex64, device=plan.device)[0]
+    for c in range(C):
+        b += plan.adjoint(y[c:c + 1][None].contiguous(), smaps[c:c + 1])[0]
+    x = torch.zeros_like(b)
+    r = b.clone()
+    pv = r.clone()
+    rr = torch.vdot(r.flatten(), r.flatten()).real
+    for _ in range(iters):
+        q = ehe(pv) + lam * pv
+        alpha = rr / torch.vdot(pv.flatten(), q.flatten()).real
+        x += alpha * pv
+        r -= alpha * q
+        rr_new = torch.vdot(r.flatten(), r.flatten()).real
+        pv = r + (rr_new / rr) * pv
+        rr = rr_new
+    return x
+
+
+def serve_capacity(dev, p2, p3, n, frac_3d, iters, lanes, hbm_gb, seed=5201):
+    """Throughput at saturation (every request queued at t = 0) of the
+    continuous-batching server, against the same requests run one at a time
+    with the library's CG calls (all coils per call) and with plain per-coil
+    calls, resident plans in both."""
+    import numpy as np
+    import torch
+
+    from paper_2111_02912_amd.cg import CgSense
+    from paper_2111_02912_amd.nufft import KbNufft
+    from paper_2111_02912_amd.serve import GpuExecutor, Request, Server
+
+    g = np.random.default_rng(seed)
+    probs = []
+    for _ in range(n):
+        pool = p3 if g.random() < frac_3d else p2
+        probs.append(pool[int(g.integers(len(pool)))])
+    # served, all arriving at once; the plans are made resident by a warm pass
+    ex = GpuExecutor(dev, lanes=lanes, lam=1e-3)
+    srv = lambda: Server(ex, hbm_budget=int(hbm_gb * (1 << 30)), lanes=lanes, chunk=1, depth=2,
+                         max_active=64)
+    srv().run([Request(i, 0.0, p, iters=iters) for i, p in enumerate({q.pid: q for q in probs}.values())])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = srv().run([Request(i, 0.0, p, iters=iters) for i, p in enumerate(probs)])
+    torch.cuda.synchronize()
+    served_s = time.perf_counter() - t0
+    ex.close()
+    plans = {}
+    for p in probs:
+        if p.pid not in plans:
+            pl = KbNufft(p.N, device=dev)
+            pl.set_points(p.data["omega"])
+            plans[p.pid] = pl
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p in probs:
+        CgSense(plans[p.pid], p.coils).begin(p.data["y"], p.data["smaps"]).step(iters, 1e-3)
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for p in probs:
+        _per_call_cg(plans[p.pid], p.data["y"], p.data["smaps"], 1e-3, iters)
+    torch.cuda.synchronize()
+    percall_s = time.perf_counter() - t0
+    for pl in plans.values():
+        pl.close()
+    return {"requests": n, "frac_3d": frac_3d, "served_rps": n / served_s, "sequential_rps": n / seq_s,
+            "per_call_rps": n / percall_s, "speedup_vs_per_call": percall_s / served_s,
+            "speedup_vs_sequential": seq_s / served_s,
+            "failed": sum(1 for r in done if r.error is not None)}
+
+
 def bench_serve(args):
     import numpy as np
     import torch
@@ -471,7 +641,7 @@ def bench_serve(args):
     wall = time.perf_counter() - t1
     done.sort(key=lambda r: r.rid)
     meas = done[args.warm_requests:]
-    rel = np.array([float(r.result["rel"].item()) for r in meas])
+    rel = np.array([float(r.result["rel"].item()) for r in meas if r.error is None])
     st = latency_stats(meas)
     per = {k: latency_stats([r for r in meas if r.problem.kind == k]) for k in ("2d", "3d")}
     # unloaded latency of one request of each class
@@ -485,6 +655,10 @@ def bench_serve(args):
         solo[k] = {"N": list(pool[0].N), "M": pool[0].M, "cold_ms": r1[0].latency * 1e3,
                    "resident_ms": r2[0].latency * 1e3}
         ex1.close()
+    capacity = None
+    if args.capacity_requests > 0:
+        capacity = serve_capacity(dev, p2, p3, args.capacity_requests, args.frac_3d, args.cg_iters,
+                                  args.lanes, args.hbm_gb)
     out = {
         "metric": "served CG-SENSE recon latency p50 (p99 alongside)",
         "value": st["p50_ms"],
@@ -512,6 +686,8 @@ def bench_serve(args):
         "wall_s": wall, "plans_created": ex.plans_created, "resident_plan_hits": ex.plan_hits,
         "peak_active": srv.peak_active, "peak_bytes_gb": srv.peak_bytes / 2 ** 30,
         "residual_median": float(np.median(rel)), "residual_max": float(rel.max()),
+        "failed_requests": len(srv.failed),
+        "capacity": capacity,
     }
     ex.close()
     print(json.dumps(out), flush=True)
@@ -525,8 +701,10 @@ def main():
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-images", type=int, default=2)
-    ap.add_argument("--workload", choices=("step", "batch", "train", "serve", "jacobian", "learn"),
+    ap.add_argument("--workload", choices=("step", "batch", "train", "serve", "jacobian", "learn", "cg"),
                     default="step")
+    ap.add_argument("--cg-shape", choices=("3d", "2d"), default="3d",
+                    help="cg workload: the 96^3 or the 384^2 serving problem")
     ap.add_argument("--requests", type=int, default=2000, help="serve workload: measured requests")
     ap.add_argument("--warm-requests", type=int, default=100, help="serve workload: unmeasured first requests")
     ap.add_argument("--rate", type=float, default=50.0, help="serve workload: arrivals per second")
@@ -537,6 +715,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=1, help="serve workload: CG iterations per issue")
     ap.add_argument("--cg-iters", type=int, default=10)
     ap.add_argument("--hbm-gb", type=float, default=64.0)
+    ap.add_argument("--capacity-requests", type=int, default=100,
+                    help="serve workload: requests of the saturation / per-call comparison (0: skip)")
     ap.add_argument("--streams", type=int, default=4, help="batch workload: streams")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="batch workload: default tiles instead of tuned ones")
@@ -550,17 +730,23 @@ def main():
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); "
               "the path shards by image, coil and instance with no communication", file=sys.stderr)
         sys.exit(2)
-    if args.workload == "batch":
-        return bench_batch(args)
-    if args.workload == "serve":
-        return bench_serve(args)
-    if args.workload == "train":
-        return bench_train(args)
-    if args.workload == "jacobian":
-        return bench_jacobian(args)
-    if args.workload == "learn":
-        return bench_learn(args)
+    run = {"batch": bench_batch, "serve": bench_serve, "train": bench_train, "jacobian": bench_jacobian,
+           "learn": bench_learn, "cg": bench_cg}.get(args.workload, bench_step)
+    run(args)
+    if args.copy_calib:
+        # a known-size reference dispatch for hardware byte counters
+        import torch
+        dev = torch.device("cuda", 0)
+        n = args.copy_calib // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
+
+def bench_step(args):
+    """The headline step (see the module docstring)."""
     import numpy as np
     import torch
 
@@ -654,7 +840,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "2D KB-NUFFT step: index pass + forward + omega-Jacobian + adjoint",
+            "workload": (f"2D KB-NUFFT step, {N[0]}x{N[1]} images, batch {B}, M={M}: index pass + "
+                         "forward + omega-Jacobian + adjoint"),
             "N": list(N), "K": list(p.K), "M": M, "batch": B, "sigma": p.opts["sigma"], "J": p.opts["J"],
             "trajectory": "64 golden-angle radial spokes x 512 samples, uniform +-pi/256 jitter",
             "images": "complex64, re/im i.i.d. N(0,1)",
@@ -665,13 +852,6 @@ def main():
         "kernels": kernels,
     }
     print(json.dumps(out), flush=True)
-    if args.copy_calib:
-        n = args.copy_calib // 8
-        src = torch.ones(n, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":
