@@ -263,7 +263,7 @@ __global__ void __launch_bounds__(NT) k_cols(KbnMidPassArgs a, const float2 *__r
     using F = Fft<L, E, INV>;
     static_assert(NT % F::TL == 0, "a workgroup holds whole lines");
     constexpr int LINES = NT / F::TL;
-    __shared__ float2 lds[L * LINES];
+    extern __shared__ float2 lds[];  // [L][LINES], dynamic (may exceed 64 KiB)
     const int l = threadIdx.x % LINES;
     const int u = threadIdx.x / LINES;
     const int ntile = (a.inner + LINES - 1) / LINES;
@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(NT) k_cols_pf(KbnMidPassArgs a, const float2 *
     using F = Fft<L, E, INV>;
     static_assert(NT % F::TL == 0, "a workgroup holds whole lines");
     constexpr int LINES = NT / F::TL;
-    __shared__ float2 lds[L * LINES];
+    extern __shared__ float2 lds[];  // [L][LINES], dynamic
     const int l = threadIdx.x % LINES;
     const int u = threadIdx.x / LINES;
     const int ntile = (a.inner + LINES - 1) / LINES;
@@ -484,8 +484,10 @@ __global__ void __launch_bounds__(NT) k_rows_last_adj(KbnLastAdjArgs a, const fl
 // passes (every radix of the length's plan must divide them, so lengths with
 // factors 2, 3 and 5 take 30 and those with 2, 3 and 7 take 42) and, for
 // lengths whose line does not divide 256 threads, the lines (row passes) or
-// columns (column passes) a workgroup holds, within 64 KB of LDS; 0 keeps
-// the tuned thread counts of row_nt / col_nt.  Row passes are LDS-occupancy
+// columns (column passes) a workgroup holds, within 64 KB of LDS (80 KB for
+// the 16 columns of 640, which read whole 128-byte row segments: 28% faster
+// than 8 columns, while 768 with 16 columns, 96 KB, fits one workgroup per
+// CU and loses); 0 keeps the tuned thread counts of row_nt / col_nt.  Row passes are LDS-occupancy
 // bound, so they take the smaller E where a length allows two.
 struct FftLen {
     int L, re, ce, rl, cl;
@@ -498,7 +500,7 @@ constexpr FftLen kFftLens[] = {
     {400, 10, 20, 0, 0},   {432, 12, 24, 8, 16},  {448, 28, 28, 8, 16},  {450, 30, 30, 8, 16},
     {480, 60, 60, 0, 0},   {486, 18, 18, 8, 8},   {500, 20, 20, 8, 8},   {504, 42, 42, 8, 16},
     {512, 8, 16, 0, 0},    {540, 30, 30, 8, 8},   {576, 12, 24, 8, 8},   {588, 42, 42, 8, 8},
-    {600, 30, 30, 8, 8},   {640, 10, 20, 0, 0},   {648, 24, 24, 8, 8},   {672, 42, 42, 8, 8},
+    {600, 30, 30, 8, 8},   {640, 10, 20, 0, 16},  {648, 24, 24, 8, 8},   {672, 42, 42, 8, 8},
     {686, 14, 14, 8, 8},   {720, 30, 30, 8, 8},   {750, 30, 30, 8, 8},   {756, 42, 42, 8, 8},
     {768, 24, 24, 0, 0},   {800, 20, 20, 8, 8},   {1024, 16, 32, 0, 0},
 };
@@ -525,9 +527,9 @@ constexpr int col_nt(int L) {
 
 // workgroups of a kernel that can be resident on the current device at once
 template <class K>
-int64_t resident_blocks(K kernel, int nt) {
+int64_t resident_blocks(K kernel, int nt, size_t lds) {
     int nb = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, nt, 0) != hipSuccess || nb < 1) nb = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, nt, lds) != hipSuccess || nb < 1) nb = 1;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
         cus = 1;
@@ -539,28 +541,46 @@ int64_t resident_blocks(K kernel, int nt) {
 // the longer lengths keep more elements per thread and would spill
 constexpr bool col_pf(int L) { return L == 128 || L == 256 || L == 512; }
 
+// a kernel whose dynamic LDS exceeds the default 64 KiB opts in (once)
+template <class K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+    if (bytes <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 template <int L>
 hipError_t launch_cols(const KbnMidPassArgs &a, const float2 *tw, int inverse, hipStream_t s) {
     constexpr int E = col_e(L);
     constexpr int NT = col_nt(L);
     constexpr int LINES = NT / (L / E);
+    constexpr size_t LDS = sizeof(float2) * L * LINES;
     const int64_t ntile = (a.inner + LINES - 1) / LINES;
     const int64_t total = a.outer * ntile;
     if (total <= 0) return hipSuccess;
     if constexpr (col_pf(L)) {
-        static const int64_t cap_fwd = resident_blocks(k_cols_pf<L, E, false, NT>, NT);
-        static const int64_t cap_inv = resident_blocks(k_cols_pf<L, E, true, NT>, NT);
+        static const hipError_t ok = [] {
+            const hipError_t e = allow_lds(k_cols_pf<L, E, false, NT>, LDS);
+            return e != hipSuccess ? e : allow_lds(k_cols_pf<L, E, true, NT>, LDS);
+        }();
+        if (ok != hipSuccess) return ok;
+        static const int64_t cap_fwd = resident_blocks(k_cols_pf<L, E, false, NT>, NT, LDS);
+        static const int64_t cap_inv = resident_blocks(k_cols_pf<L, E, true, NT>, NT, LDS);
         const dim3 grid((unsigned)std::min<int64_t>(total, inverse ? cap_inv : cap_fwd));
         if (inverse)
-            k_cols_pf<L, E, true, NT><<<grid, dim3(NT), 0, s>>>(a, tw);
+            k_cols_pf<L, E, true, NT><<<grid, dim3(NT), LDS, s>>>(a, tw);
         else
-            k_cols_pf<L, E, false, NT><<<grid, dim3(NT), 0, s>>>(a, tw);
+            k_cols_pf<L, E, false, NT><<<grid, dim3(NT), LDS, s>>>(a, tw);
     } else {
+        static const hipError_t ok = [] {
+            const hipError_t e = allow_lds(k_cols<L, E, false, NT>, LDS);
+            return e != hipSuccess ? e : allow_lds(k_cols<L, E, true, NT>, LDS);
+        }();
+        if (ok != hipSuccess) return ok;
         const dim3 grid((unsigned)total);
         if (inverse)
-            k_cols<L, E, true, NT><<<grid, dim3(NT), 0, s>>>(a, tw);
+            k_cols<L, E, true, NT><<<grid, dim3(NT), LDS, s>>>(a, tw);
         else
-            k_cols<L, E, false, NT><<<grid, dim3(NT), 0, s>>>(a, tw);
+            k_cols<L, E, false, NT><<<grid, dim3(NT), LDS, s>>>(a, tw);
     }
     return hipGetLastError();
 }

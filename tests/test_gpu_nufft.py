@@ -337,13 +337,15 @@ def test_bench_configuration_sampled(dev):
 @pytest.mark.parametrize("N", [(64, 96), (160, 128), (48, 40, 64), (256, 130), (80, 200), (240, 160),
                                (200, 64), (40, 100, 80), (216, 225), (243, 250), (270, 288), (300, 324), (360, 375),
                                (225, 216), (375, 360), (216, 24, 250), (196, 224), (252, 294), (336, 343),
-                               (378, 196), (100, 400), (400, 100), (135, 144), (150, 162), (180, 144)])
+                               (378, 196), (100, 400), (400, 100), (135, 144), (150, 162), (180, 144),
+                               (320, 384), (384, 320)])
 def test_specialised_fft_matches_generic(N, dev, monkeypatch):
     """The compile-time specialised FFT passes and the generic ones agree, and
     both match the oracle (K = 128, 192, 320, 256, 96->generic, 160, 400,
     480, 200->generic ...; 432, 450, 486, 500, 540, 576, 600, 648, 720, 750
     on either axis, 432 x 48 x 500 in 3D; with radix 7: 392, 448, 504, 588,
-    672, 686, 756; 200 and 800; 270, 288, 300, 324, 360)."""
+    672, 686, 756; 200 and 800; 270, 288, 300, 324, 360; 640 and 768 with
+    16 columns per column-pass workgroup)."""
     _say(f"specialised vs generic FFT N={N}")
     D = len(N)
     om = W.uniform_random(2500, D, seed=91)
