@@ -156,11 +156,14 @@ def cpu_baseline(N, om, x, g, images=2):
     }
 
 
-def _wall_ms(fn, steps, warmup):
+def _wall_ms(fn, steps, warmup, pause_ms=0.0):
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    if pause_ms > 0:
+        # an idle gap on the GPU timeline that marks where the timed steps begin
+        time.sleep(pause_ms * 1e-3)
     t0 = time.perf_counter()
     for _ in range(steps):
         fn()
@@ -223,19 +226,24 @@ def bench_batch(args):
                         KB.Task(it["plan"], KB.JAC_OMEGA_FWD, 1, 1, it["x"], it["dom"], sc,
                                 g=it["k"][:, c:c + 1], accumulate=c > 0),
                         KB.Task(it["plan"], KB.ADJOINT, 1, 1, it["k"][:, c:c + 1], it["xc"][c:c + 1], sc)]
+    want = set(args.modes.split(","))
     modes = {}
-    b = KB.KbnBatch(percall, nstreams=1)
-    modes["per_call"] = _wall_ms(b.run, args.steps, args.warmup)
-    b.close()
-    b = KB.KbnBatch(batched, nstreams=1)
-    modes["per_instance_one_stream"] = _wall_ms(b.run, args.steps, args.warmup)
-    b.close()
+    if "per_call" in want:
+        b = KB.KbnBatch(percall, nstreams=1)
+        modes["per_call"] = _wall_ms(b.run, args.steps, args.warmup)
+        b.close()
+    if "per_instance_one_stream" in want:
+        b = KB.KbnBatch(batched, nstreams=1)
+        modes["per_instance_one_stream"] = _wall_ms(b.run, args.steps, args.warmup)
+        b.close()
     b = KB.KbnBatch(batched, nstreams=args.streams)
-    modes["streams"] = _wall_ms(b.run, args.steps, args.warmup)
-    b.capture()
-    modes["graph"] = _wall_ms(b.launch, args.steps, args.warmup)
+    if "streams" in want:
+        modes["streams"] = _wall_ms(b.run, args.steps, args.warmup)
+    if "graph" in want:
+        b.capture()
+        modes["graph"] = _wall_ms(b.launch, args.steps, args.warmup, args.pause_ms)
     b.close()
-    best = min(("streams", "graph"), key=lambda m: modes[m])
+    best = min((m for m in ("streams", "graph") if m in modes), key=lambda m: modes[m])
     out = {
         "metric": "multi-instance bundle nonuniform pts/s (fwd+adj+omega-Jacobian)",
         "value": pts / (modes[best] * 1e-3),
@@ -261,8 +269,9 @@ def bench_batch(args):
         "roofline": {"bound": "hbm", "kernel": "whole bundle", "alg_bytes": bundle_bytes,
                      "achieved": bundle_bytes / (modes[best] * 1e-3) / 1e9, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": bundle_bytes / (modes[best] * 1e-3) / 1e9 / HBM_PEAK_GBPS},
-        "speedup_vs_per_call": modes["per_call"] / modes[best],
-        "speedup_vs_per_instance": modes["per_instance_one_stream"] / modes[best],
+        "speedup_vs_per_call": modes["per_call"] / modes[best] if "per_call" in modes else None,
+        "speedup_vs_per_instance": (modes["per_instance_one_stream"] / modes[best]
+                                    if "per_instance_one_stream" in modes else None),
     }
     print(json.dumps(out), flush=True)
 
@@ -718,6 +727,11 @@ def main():
     ap.add_argument("--capacity-requests", type=int, default=100,
                     help="serve workload: requests of the saturation / per-call comparison (0: skip)")
     ap.add_argument("--streams", type=int, default=4, help="batch workload: streams")
+    ap.add_argument("--modes", default="per_call,per_instance_one_stream,streams,graph",
+                    help="batch workload: modes to time (comma list; streams or graph must be one)")
+    ap.add_argument("--pause-ms", type=float, default=0.0,
+                    help="batch workload: host pause before the timed graph replays (marks them "
+                         "on a kernel trace)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="batch workload: default tiles instead of tuned ones")
     ap.add_argument("--accuracy", choices=("high", "low"), default="high",

@@ -4,6 +4,15 @@
   python -m paper_2111_02912_amd.profsummary bench BENCH_OUTPUT --cmd "..." --title "..."
   python -m paper_2111_02912_amd.profsummary pmc FETCH_CSV WRITE_CSV --calib-bytes N
          --cmd-fetch "..." --cmd-write "..." [--json OUT.json]
+  python -m paper_2111_02912_amd.profsummary timeline KERNEL_TRACE_CSV --cmd "..."
+         [--after-gap-ms 20] [--steps K]
+
+The timeline mode reads a kernel trace, keeps the dispatches after the
+last idle gap of at least --after-gap-ms (a host pause placed before the
+timed steps), and reports where the GPU is busy and where it idles: the
+union of kernel intervals, the time with 0, 1, 2, 3+ kernels in flight, the
+busy time per kernel class and the longest idle gaps with the kernels on
+either side.
 
 The pmc mode scales each kernel's FETCH_SIZE / WRITE_SIZE (KiB per dispatch)
 by the ratio "known bytes / counter reading" of the calibration copy kernel
@@ -145,6 +154,95 @@ def pmc(fetch_csv, write_csv, calib_bytes, cmd_f, cmd_w, json_out=None, steps=1)
     return "\n".join(out) + "\n"
 
 
+def _dims(r, name):
+    """'x' or 'x*y*z' of a size column (one column or one per axis)."""
+    if name in r:
+        return r[name]
+    d = [r.get(f"{name}_{a}", "") for a in "XYZ"]
+    d = [v for v in d if v not in ("", "1", "0")]
+    return "*".join(d) if d else "1"
+
+
+def timeline(path: str, cmd: str, after_gap_ms: float = 20.0, steps: int = 1) -> str:
+    rows = []
+    shape = {}
+    for r in csv.DictReader(open(path)):
+        key = (int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short(r["Kernel_Name"]))
+        rows.append(key)
+        shape[key] = (_dims(r, "Grid_Size"), _dims(r, "Workgroup_Size"), r.get("LDS_Block_Size", "?"))
+    rows.sort()
+    if not rows:
+        return "no dispatches\n"
+    # the timed window starts after the last long idle gap
+    first = 0
+    end_so_far = rows[0][1]
+    for i in range(1, len(rows)):
+        if rows[i][0] - end_so_far >= after_gap_ms * 1e6:
+            first = i
+        end_so_far = max(end_so_far, rows[i][1])
+    win = rows[first:]
+    t0 = win[0][0]
+    t1 = max(e for _, e, _ in win)
+    span = t1 - t0
+    # sweep: time with n kernels in flight, idle gaps
+    ev = sorted([(s, 1) for s, _, _ in win] + [(e, -1) for _, e, _ in win])
+    level = 0
+    last = t0
+    at = collections.Counter()
+    gaps = []
+    for t, d in ev:
+        if t > last:
+            at[min(level, 3)] += t - last
+            if level == 0:
+                gaps.append((t - last, last, t))
+        level += d
+        last = t
+    busy = span - at[0]
+    # busy time per class (intervals of the class, merged)
+    per = collections.defaultdict(list)
+    for s_, e_, n in win:
+        per[kernel_class(n) or n.split("<")[0]].append((s_, e_))
+    cls_busy = {}
+    for c, iv in per.items():
+        iv.sort()
+        tot, cs, ce = 0, iv[0][0], iv[0][1]
+        for s_, e_ in iv[1:]:
+            if s_ > ce:
+                tot += ce - cs
+                cs, ce = s_, e_
+            else:
+                ce = max(ce, e_)
+        cls_busy[c] = (tot + ce - cs, len(iv))
+
+    def near(t, before):
+        # kernel ending at t (before) or starting at t (after)
+        for s_, e_, n in win:
+            if (before and e_ == t) or (not before and s_ == t):
+                return n[:40]
+        return "?"
+
+    out = ["# rocprofv3 --kernel-trace timeline of the timed window", f"# command: {cmd}",
+           f"# source hash: {sources_hash()}",
+           f"# window: dispatches after the last idle gap >= {after_gap_ms} ms ({len(win)} dispatches, "
+           f"{steps} step(s))", "",
+           f"window {span / 1e6:.3f} ms ({span / 1e6 / steps:.3f} ms per step); GPU busy {busy / 1e6:.3f} ms "
+           f"({100 * busy / span:.1f} %), idle {at[0] / 1e6:.3f} ms ({100 * at[0] / span:.1f} %)",
+           "kernels in flight: " + ", ".join(f"{k if k < 3 else '3+'}: {100 * at[k] / span:.1f} %"
+                                            for k in range(4)), "",
+           f"{'class':28s} {'dispatches':>10s} {'busy_ms':>9s} {'pct_of_window':>14s}"]
+    for c, (t, n) in sorted(cls_busy.items(), key=lambda kv: -kv[1][0]):
+        out.append(f"{c[:28]:28s} {n:10d} {t / 1e6:9.3f} {100 * t / span:14.1f}")
+    gaps.sort(reverse=True)
+    out += ["", f"idle gaps: {len(gaps)}, longest:", f"{'gap_us':>8s}  after -> before"]
+    for g, a, b in gaps[:10]:
+        out.append(f"{g / 1e3:8.1f}  {near(a, True)} -> {near(b, False)}")
+    out += ["", "longest dispatches (grid size, workgroup size, LDS bytes):"]
+    for r in sorted(win, key=lambda r: r[0] - r[1])[:15]:
+        gs, ws, lds = shape[r]
+        out.append(f"{(r[1] - r[0]) / 1e3:8.1f} us  {r[2][:50]:50s} grid {gs} wg {ws} lds {lds}")
+    return "\n".join(out) + "\n"
+
+
 def _fmt(v, indent=2):
     pad = " " * indent
     if isinstance(v, dict):
@@ -205,11 +303,18 @@ def main():
     p.add_argument("--cmd-write", required=True)
     p.add_argument("--json")
     p.add_argument("--steps", type=int, default=1, help="steps (incl. warm-up) in the counted run")
+    t = sub.add_parser("timeline")
+    t.add_argument("csv")
+    t.add_argument("--cmd", required=True)
+    t.add_argument("--after-gap-ms", type=float, default=20.0)
+    t.add_argument("--steps", type=int, default=1, help="steps in the timed window")
     a = ap.parse_args()
     if a.mode == "bench":
         sys.stdout.write(bench(a.json, a.cmd, a.title))
     elif a.mode == "stats":
         sys.stdout.write(stats(a.csv, a.cmd))
+    elif a.mode == "timeline":
+        sys.stdout.write(timeline(a.csv, a.cmd, a.after_gap_ms, a.steps))
     else:
         sys.stdout.write(pmc(a.fetch_csv, a.write_csv, a.calib_bytes, a.cmd_fetch, a.cmd_write, a.json,
                              a.steps))
