@@ -243,7 +243,13 @@ def bench_batch(args):
         b.capture()
         modes["graph"] = _wall_ms(b.launch, args.steps, args.warmup, args.pause_ms)
     b.close()
-    best = min((m for m in ("streams", "graph") if m in modes), key=lambda m: modes[m])
+    if "fused" in want:
+        # interpolation of the whole bundle in one launch per phase and kernel
+        # shape (fused batches run eagerly)
+        b = KB.KbnBatch(batched, nstreams=args.streams, fuse=True)
+        modes["fused"] = _wall_ms(b.run, args.steps, args.warmup, args.pause_ms)
+        b.close()
+    best = min((m for m in ("streams", "graph", "fused") if m in modes), key=lambda m: modes[m])
     out = {
         "metric": "multi-instance bundle nonuniform pts/s (fwd+adj+omega-Jacobian)",
         "value": pts / (modes[best] * 1e-3),
@@ -727,11 +733,12 @@ def main():
     ap.add_argument("--capacity-requests", type=int, default=100,
                     help="serve workload: requests of the saturation / per-call comparison (0: skip)")
     ap.add_argument("--streams", type=int, default=4, help="batch workload: streams")
-    ap.add_argument("--modes", default="per_call,per_instance_one_stream,streams,graph",
-                    help="batch workload: modes to time (comma list; streams or graph must be one)")
+    ap.add_argument("--modes", default="per_call,per_instance_one_stream,streams,graph,fused",
+                    help="batch workload: modes to time (comma list; one of streams, graph, fused "
+                         "must be in it)")
     ap.add_argument("--pause-ms", type=float, default=0.0,
-                    help="batch workload: host pause before the timed graph replays (marks them "
-                         "on a kernel trace)")
+                    help="batch workload: host pause before the timed graph replays or fused runs "
+                         "(marks them on a kernel trace)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="batch workload: default tiles instead of tuned ones")
     ap.add_argument("--accuracy", choices=("high", "low"), default="high",

@@ -463,9 +463,44 @@ int kbn_batch_run(kbn_batch b, void *stream);
  * the batch is destroyed its plans refuse kbn_set_points, workspace
  * growth, kbn_timing and kbn_plan_destroy.  Replays read the task inputs
  * as they are at replay time.
- * Errors: INVALID_ARG (a plan has timing on), the task calls' errors, HIP.
+ * Errors: INVALID_ARG (a plan has timing on), UNSUPPORTED (fused batch),
+ * the task calls' errors, HIP.
  */
 int kbn_batch_capture(kbn_batch b, void *stream);
+
+/*
+ * Fused mode (on != 0; before kbn_batch_capture): the tasks run in phases
+ * around their interpolation, so that the interpolation of the whole batch
+ * takes one launch per phase and kernel shape instead of one per task:
+ *   1. on the batch's streams, each forward-type task's FFT passes (scaling,
+ *      coil maps, coordinate weights, oversampled FFT; Sec. II, the
+ *      approximation of A(omega) x as interpolation of an oversampled FFT);
+ *   2. one staged gather launch for all FORWARD / JAC_X_ADJ tasks of one
+ *      dimension and window width J, one for all JAC_OMEGA tasks (the
+ *      Jacobian expressions evaluated as extra NUFFTs of x weighted by the
+ *      coordinate grids, folded with the upstream gradient), and one
+ *      output-stationary spread launch for all ADJOINT / JAC_X_FWD tasks
+ *      with the same owner-tile shape and channels per thread (the
+ *      transpose of the interpolation, A(omega)^H y);
+ *   3. each task's epilogue on its stream: the omega-gradient's sum over
+ *      channel groups, or the adjoint's split-tile sums and inverse FFT
+ *      passes.
+ * A task that needs several workspace chunks, has no points, or whose
+ * interpolation takes another kernel (an unstaged gather, the
+ * channel-per-lane or scatter spread) runs whole in phase 1.  Results are
+ * bitwise those of the single calls.  Because the phases of different tasks
+ * interleave, fused tasks must be independent even within one plan: no task
+ * may read another task's output, and only JAC_OMEGA tasks with accumulate
+ * set may share an output (their sums run in list order on one stream).
+ * Each phased task holds device memory of its own (its grids, through its
+ * plan's allocator, counted in kbn_plan_info) while the batch is fused; the
+ * first run after kbn_set_points on a plan of the batch rebuilds the phases
+ * and waits for `stream`.  on = 0 returns to per-task issue and frees them.
+ * A fused batch runs with kbn_batch_run only: kbn_batch_capture refuses it
+ * (UNSUPPORTED).
+ * Errors: INVALID_ARG (null batch, batch already captured), HIP.
+ */
+int kbn_batch_fuse(kbn_batch b, int on);
 
 /* Replay the captured graph on `stream` (asynchronous).
  * Errors: INVALID_ARG (not captured), HIP. */

@@ -36,7 +36,7 @@ EXPORTS = (
     "kbn_jac_omega_fwd", "kbn_jac_omega_adj", "kbn_jac_x", "kbn_plan_info",
     "kbn_get_points", "kbn_check_error", "kbn_plan_destroy", "kbn_strerror",
     "kbn_last_error", "kbn_timing", "kbn_timing_read", "kbn_timing_name",
-    "kbn_batch_create", "kbn_batch_run", "kbn_batch_capture", "kbn_batch_launch",
+    "kbn_batch_create", "kbn_batch_run", "kbn_batch_capture", "kbn_batch_fuse", "kbn_batch_launch",
     "kbn_batch_destroy", "kbn_cg_work_bytes", "kbn_cg_begin", "kbn_cg_step",
     "kbn_cg_begin_image", "kbn_field_forward", "kbn_field_adjoint", "kbn_field_jac_omega_fwd",
     "kbn_field_jac_omega_adj", "kbn_field_segments",
@@ -129,6 +129,7 @@ def lib():
     L.kbn_batch_create.argtypes = [ctypes.POINTER(vp), ci, ctypes.POINTER(KbnTask), ci]
     L.kbn_batch_run.argtypes = [vp, vp]
     L.kbn_batch_capture.argtypes = [vp, vp]
+    L.kbn_batch_fuse.argtypes = [vp, ci]
     L.kbn_batch_launch.argtypes = [vp, vp]
     L.kbn_batch_destroy.argtypes = [vp]
     L.kbn_cg_work_bytes.argtypes = [vp, ci, ci, ctypes.POINTER(i64)]

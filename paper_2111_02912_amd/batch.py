@@ -54,7 +54,10 @@ class Task:
 
 
 class KbnBatch:
-    def __init__(self, tasks: List[Task], nstreams: int = 0):
+    """``fuse=True``: interpolation of all tasks in one launch per phase and
+    kernel shape (kbn_batch_fuse); the tasks must then be independent."""
+
+    def __init__(self, tasks: List[Task], nstreams: int = 0, fuse: bool = False):
         if not tasks:
             raise ValueError("empty task list")
         self.tasks = list(tasks)
@@ -64,6 +67,8 @@ class KbnBatch:
         check(_lib.lib().kbn_batch_create(ctypes.byref(h), len(tasks), arr, int(nstreams)),
               "kbn_batch_create")
         self._h = h
+        if fuse:
+            check(_lib.lib().kbn_batch_fuse(self._h, 1), "kbn_batch_fuse")
 
     def run(self):
         """Issue every task once on the current stream's timeline."""

@@ -36,15 +36,16 @@ namespace {
 // ones are interpolated (each thread keeps the grid offsets of its region
 // cells, computed once), so the grid reads overlap the interpolation.  Subproblems
 // of the extra tile id ntiles hold the flagged points, whose outputs are NaN.
+// Body of one workgroup: subproblem s, channel group gy (the kernel's
+// blockIdx.x and blockIdx.y), regions staged in reg4.
 template <int D, int J, int MODE, int CP, bool LA>
-__global__ void __launch_bounds__(KBN_BLOCK) k_gather_staged(KbnGeom g, KbnGatherArgs a, int cg) {
+__device__ __forceinline__ void gather_staged_wg(const KbnGeom &g, const KbnGatherArgs &a, int cg, int s, int gy,
+                                                 float4 *reg4) {
     constexpr int H = CP / 2;  // float4 (channel pairs) per region cell
-    extern __shared__ float4 reg4[];
-    const int s = blockIdx.x;
     if (s >= *a.nsub) return;
     const int tile = a.subs[2 * s];
     const int p0 = a.subs[2 * s + 1];
-    const int ch0 = blockIdx.y * cg;
+    const int ch0 = gy * cg;
     const int ch1 = min(ch0 + cg, a.nch);
     const float qnan = __builtin_nanf("");
     if (tile == g.ntiles) {  // flagged points
@@ -54,7 +55,7 @@ __global__ void __launch_bounds__(KBN_BLOCK) k_gather_staged(KbnGeom g, KbnGathe
             if (MODE == 0) {
                 for (int ch = ch0; ch < ch1; ++ch) a.y[(int64_t)ch * a.M + q] = make_float2(qnan, qnan);
             } else {
-                float *part = a.part + (int64_t)blockIdx.y * a.M * D;
+                float *part = a.part + (int64_t)gy * a.M * D;
                 for (int d = 0; d < D; ++d) part[(int64_t)q * D + d] = qnan;
             }
         }
@@ -284,10 +285,35 @@ __global__ void __launch_bounds__(KBN_BLOCK) k_gather_staged(KbnGeom g, KbnGathe
         __syncthreads();
     }
     if (MODE == 1 && act) {
-        float *part = a.part + (int64_t)blockIdx.y * a.M * D;
+        float *part = a.part + (int64_t)gy * a.M * D;
 #pragma unroll
         for (int d = 0; d < D; ++d) part[(int64_t)q * D + d] = jac[d];
     }
+}
+
+template <int D, int J, int MODE, int CP, bool LA>
+__global__ void __launch_bounds__(KBN_BLOCK) k_gather_staged(KbnGeom g, KbnGatherArgs a, int cg) {
+    extern __shared__ float4 reg4[];
+    gather_staged_wg<D, J, MODE, CP, LA>(g, a, cg, blockIdx.x, blockIdx.y, reg4);
+}
+
+// The staged gathers of several plans in one launch: workgroup w belongs to
+// the job i with start[i] <= w < start[i + 1] and is that job's workgroup
+// (w - start[i]) mod blocks of channel group (w - start[i]) / blocks.
+template <int D, int J, int MODE, int CP, bool LA>
+__global__ void __launch_bounds__(KBN_BLOCK)
+k_gather_multi(const KbnGatherJob *__restrict__ jobs, const int64_t *__restrict__ start, int njobs) {
+    extern __shared__ float4 reg4[];
+    const int64_t w = blockIdx.x;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    const KbnGatherJob &j = jobs[lo];
+    const int64_t local = w - start[lo];
+    gather_staged_wg<D, J, MODE, CP, LA>(j.g, j.a, j.cg, (int)(local % j.blocks), (int)(local / j.blocks), reg4);
 }
 
 // Direct gather (no staging): one thread per sorted point reads its taps from
@@ -582,8 +608,10 @@ __global__ void __launch_bounds__(KBN_BLOCK) k_spread(KbnGeom g, KbnSpreadArgs a
 // there are no atomics and no read-modify-write of shared memory, and the sum
 // order (list order) is fixed.  The tile is written once at the end, to the
 // grid or to the work item's partial slot.
+// Body of one workgroup: channel group gx, work items wy, wy + ny, ...
+// (the kernel's blockIdx.x, blockIdx.y and gridDim.y).
 template <int D, int J, int CPT, int EB>
-__global__ void __launch_bounds__(512) k_spread_os(KbnGeom g, KbnSpreadArgs a) {
+__device__ __forceinline__ void spread_os_wg(const KbnGeom &g, const KbnSpreadArgs &a, int gx, int wy, int ny) {
     __shared__ float2 s_y[EB][CPT];
     __shared__ int s_p[EB];
     // 2D: per staged entry the tap origin relative to the tile and the J
@@ -608,11 +636,11 @@ __global__ void __launch_bounds__(512) k_spread_os(KbnGeom g, KbnSpreadArgs a) {
             t /= g.To[d];
         }
     }
-    const int ch0 = blockIdx.x * CPT;
+    const int ch0 = gx * CPT;
     const int nchg = min(CPT, a.nch - ch0);
     // work items in dispatch order (hottest tiles first); a grid smaller
     // than the work list strides over it
-    for (int wk = blockIdx.y; wk < nwork; wk += gridDim.y) {
+    for (int wk = wy; wk < nwork; wk += ny) {
         const int tile = a.swork[4 * wk];
         const int slot = a.swork[4 * wk + 3];
         int a0[D], te[D];
@@ -734,6 +762,30 @@ __global__ void __launch_bounds__(512) k_spread_os(KbnGeom g, KbnSpreadArgs a) {
             }
         }
     }
+}
+
+template <int D, int J, int CPT, int EB>
+__global__ void __launch_bounds__(512) k_spread_os(KbnGeom g, KbnSpreadArgs a) {
+    spread_os_wg<D, J, CPT, EB>(g, a, blockIdx.x, blockIdx.y, gridDim.y);
+}
+
+// The output-stationary spreads of several plans in one launch (same
+// owner-tile shape, so one workgroup size): workgroup row y belongs to the
+// job i with ystart[i] <= y < ystart[i + 1], which strides over its work
+// items with ny rows; columns past the job's channel groups stop at once.
+template <int D, int J, int CPT, int EB>
+__global__ void __launch_bounds__(512)
+k_spread_os_multi(const KbnSpreadJob *__restrict__ jobs, const int *__restrict__ ystart, int njobs) {
+    const int y = blockIdx.y;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ystart[mid] <= y) lo = mid;
+        else hi = mid - 1;
+    }
+    const KbnSpreadJob &j = jobs[lo];
+    if ((int)blockIdx.x >= j.ngr) return;
+    spread_os_wg<D, J, CPT, EB>(j.g, j.a, blockIdx.x, y - ystart[lo], j.ny);
 }
 
 // Output-stationary spread with one channel per lane, for 2D 8 x 8 owner
@@ -998,6 +1050,15 @@ KbnGatherShape kbn_gather_shape(const KbnGeom &g, int64_t M, int nch, int nw) {
 
 namespace {
 
+// the epilogue of the omega-Jacobian gather: the channel groups' partial
+// gradients summed in group order
+hipError_t reduce_parts(const KbnGeom &g, const KbnGatherArgs &a, int groups, hipStream_t s) {
+    const int64_t n = a.M * g.D;
+    k_reduce_parts<<<dim3((unsigned)((n + KBN_BLOCK - 1) / KBN_BLOCK)), dim3(KBN_BLOCK), 0, s>>>(
+        a.domega, a.part, n, groups, a.accumulate);
+    return hipGetLastError();
+}
+
 template <int D, int J>
 hipError_t gather_dj(const KbnGeom &g, const KbnGatherArgs &a, int mode, hipStream_t s) {
     if (a.M == 0 || a.nch == 0) return hipSuccess;
@@ -1018,10 +1079,22 @@ hipError_t gather_dj(const KbnGeom &g, const KbnGatherArgs &a, int mode, hipStre
             k_gather<D, J, 1><<<grid, dim3(KBN_BLOCK), 0, s>>>(g, a, sh.cg);
     }
     if (mode == 1) {
-        const int64_t n = a.M * g.D;
-        k_reduce_parts<<<dim3((unsigned)((n + KBN_BLOCK - 1) / KBN_BLOCK)), dim3(KBN_BLOCK), 0, s>>>(
-            a.domega, a.part, n, sh.groups, a.accumulate);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return reduce_parts(g, a, sh.groups, s);
     }
+    return hipGetLastError();
+}
+
+template <int D, int J>
+hipError_t gather_multi_dj(int mode, const KbnGatherJob *jobs, const int64_t *start, int njobs, int64_t total,
+                           size_t lds, hipStream_t s) {
+    constexpr bool LA = D == 3;
+    const dim3 grid((unsigned)total);
+    if (mode == 0)
+        k_gather_multi<D, J, 0, 2, LA><<<grid, dim3(KBN_BLOCK), lds, s>>>(jobs, start, njobs);
+    else
+        k_gather_multi<D, J, 1, 2, LA><<<grid, dim3(KBN_BLOCK), lds, s>>>(jobs, start, njobs);
     return hipGetLastError();
 }
 
@@ -1054,85 +1127,102 @@ SpreadShape spread_shape(const KbnGeom &g, int nch) {
 }
 
 template <int D, int J>
+hipError_t launch_os(const KbnSpreadSel &sel, dim3 grid, const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s) {
+    const dim3 blk((unsigned)sel.tcells);
+    if constexpr (D == 3) {
+        switch (sel.cpt) {
+            case 1: k_spread_os<D, J, 1, 64><<<grid, blk, sel.lds, s>>>(g, a); break;
+            case 2: k_spread_os<D, J, 2, 64><<<grid, blk, sel.lds, s>>>(g, a); break;
+            case 4: k_spread_os<D, J, 4, 64><<<grid, blk, sel.lds, s>>>(g, a); break;
+            case 8: k_spread_os<D, J, 8, 64><<<grid, blk, sel.lds, s>>>(g, a); break;
+            case 16: k_spread_os<D, J, 16, 64><<<grid, blk, sel.lds, s>>>(g, a); break;
+            default: k_spread_os<D, J, 32, 32><<<grid, blk, sel.lds, s>>>(g, a); break;
+        }
+    } else {
+        switch (sel.cpt) {
+            case 1: k_spread_os<D, J, 1, 32><<<grid, blk, sel.lds, s>>>(g, a); break;
+            case 2: k_spread_os<D, J, 2, 32><<<grid, blk, sel.lds, s>>>(g, a); break;
+            case 4: k_spread_os<D, J, 4, 32><<<grid, blk, sel.lds, s>>>(g, a); break;
+            case 8: k_spread_os<D, J, 8, 32><<<grid, blk, sel.lds, s>>>(g, a); break;
+            case 16: k_spread_os<D, J, 16, 32><<<grid, blk, sel.lds, s>>>(g, a); break;
+            default: k_spread_os<D, J, 32, 32><<<grid, blk, sel.lds, s>>>(g, a); break;
+        }
+    }
+    return hipGetLastError();
+}
+
+template <int D, int J>
+hipError_t launch_os_multi(const KbnSpreadSel &sel, dim3 grid, const KbnSpreadJob *jobs, const int *ystart,
+                           int njobs, hipStream_t s) {
+    const dim3 blk((unsigned)sel.tcells);
+    if constexpr (D == 3) {
+        switch (sel.cpt) {
+            case 1: k_spread_os_multi<D, J, 1, 64><<<grid, blk, sel.lds, s>>>(jobs, ystart, njobs); break;
+            case 2: k_spread_os_multi<D, J, 2, 64><<<grid, blk, sel.lds, s>>>(jobs, ystart, njobs); break;
+            case 4: k_spread_os_multi<D, J, 4, 64><<<grid, blk, sel.lds, s>>>(jobs, ystart, njobs); break;
+            case 8: k_spread_os_multi<D, J, 8, 64><<<grid, blk, sel.lds, s>>>(jobs, ystart, njobs); break;
+            case 16: k_spread_os_multi<D, J, 16, 64><<<grid, blk, sel.lds, s>>>(jobs, ystart, njobs); break;
+            default: k_spread_os_multi<D, J, 32, 32><<<grid, blk, sel.lds, s>>>(jobs, ystart, njobs); break;
+        }
+    } else {
+        switch (sel.cpt) {
+            case 1: k_spread_os_multi<D, J, 1, 32><<<grid, blk, sel.lds, s>>>(jobs, ystart, njobs); break;
+            case 2: k_spread_os_multi<D, J, 2, 32><<<grid, blk, sel.lds, s>>>(jobs, ystart, njobs); break;
+            case 4: k_spread_os_multi<D, J, 4, 32><<<grid, blk, sel.lds, s>>>(jobs, ystart, njobs); break;
+            case 8: k_spread_os_multi<D, J, 8, 32><<<grid, blk, sel.lds, s>>>(jobs, ystart, njobs); break;
+            case 16: k_spread_os_multi<D, J, 16, 32><<<grid, blk, sel.lds, s>>>(jobs, ystart, njobs); break;
+            default: k_spread_os_multi<D, J, 32, 32><<<grid, blk, sel.lds, s>>>(jobs, ystart, njobs); break;
+        }
+    }
+    return hipGetLastError();
+}
+
+// the partial tiles of owner tiles split over several work items, summed
+// in item order
+template <int D>
+hipError_t spread_combine(const KbnSpreadSel &sel, const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s) {
+    if (a.ncomb_max <= 0) return hipSuccess;
+    if (sel.path == KBN_SPREAD_PATH_CL) {
+        const int ny = std::max(1, std::min(a.ncomb_max, 8 * 256 * 4 / a.nch + 1));
+        k_spread_combine<D><<<dim3((unsigned)a.nch, (unsigned)ny), dim3(64), 0, s>>>(g, a);
+    } else if (sel.path == KBN_SPREAD_PATH_OS) {
+        const int cb = std::min(KBN_BLOCK, (sel.tcells + 63) / 64 * 64);
+        const int ny = std::max(1, std::min(a.ncomb_max, 8 * 256 * 4 / a.nch + 1));
+        k_spread_combine<D><<<dim3((unsigned)a.nch, (unsigned)ny), dim3(cb), 0, s>>>(g, a);
+    } else {
+        k_spread_combine<D><<<dim3((unsigned)a.nch, (unsigned)a.ncomb_max), dim3(KBN_BLOCK), 0, s>>>(g, a);
+    }
+    return hipGetLastError();
+}
+
+template <int D, int J>
 hipError_t spread_dj(const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s) {
     if (a.nch == 0) return hipSuccess;
-    const SpreadShape sh = spread_shape(g, a.nch);
-    const int ngroup = sh.nwave * sh.cw;
-    const int ng = (a.nch + ngroup - 1) / ngroup;
-    int tcells = 1;
-    for (int d = 0; d < D; ++d) tcells *= g.To[d];
-    static const bool os_on = [] {
-        const char *e = std::getenv("KBN_SPREAD_OS");
-        return !(e && e[0] == '0');
-    }();
-    static const bool cl_on = [] {
-        const char *e = std::getenv("KBN_SPREAD_CL");
-        return !(e && e[0] == '0');
-    }();
-    // channel-per-lane spread: one wave per (owner tile, 64 channels) at two
-    // waves per SIMD, so it needs enough tiles x channel groups to fill the
-    // chip's 2048 wave slots twice; below that the cell-per-lane kernel is
-    // faster (both give the same sums)
-    const int64_t cl_waves = (int64_t)g.ntiles_own * ((a.nch + 63) / 64);
-    if (D == 2 && os_on && cl_on && g.To[0] == 8 && g.To[1] == 8 && a.nch >= 64 && cl_waves >= 4096 &&
-        64 * a.M * (int64_t)sizeof(float2) < ((int64_t)1 << 31)) {
+    const KbnSpreadSel sel = kbn_spread_select(g, a);
+    hipError_t e = hipSuccess;
+    if (sel.path == KBN_SPREAD_PATH_CL) {
         dim3 grid_cl((unsigned)((a.nch + 63) / 64), (unsigned)std::min(a.nwork_max, KBN_GRID_Y_MAX));
         k_spread_cl<J, KBN_SPREAD_CL_EB><<<grid_cl, dim3(64), 0, s>>>(g, a);
-        if (a.ncomb_max > 0) {
-            const int ny = std::max(1, std::min(a.ncomb_max, 8 * 256 * 4 / a.nch + 1));
-            k_spread_combine<D><<<dim3((unsigned)a.nch, (unsigned)ny), dim3(64), 0, s>>>(g, a);
+        e = hipGetLastError();
+    } else if (sel.path == KBN_SPREAD_PATH_OS) {
+        e = launch_os<D, J>(sel, dim3((unsigned)sel.ngr, (unsigned)sel.ny), g, a, s);
+    } else {
+        const SpreadShape sh = spread_shape(g, a.nch);
+        const int ngroup = sh.nwave * sh.cw;
+        const int ng = (a.nch + ngroup - 1) / ngroup;
+        if (a.M > 0) {  // the scatter kernel reads k-space values in tile order
+            dim3 pgrid((unsigned)((a.M + KBN_BLOCK - 1) / KBN_BLOCK), (unsigned)a.nch);
+            k_permute<<<pgrid, dim3(KBN_BLOCK), 0, s>>>(a.y, a.ys, a.order, a.M);
         }
-        return hipGetLastError();
+        dim3 grid((unsigned)ng, (unsigned)a.nwork_max);  // one workgroup row per work item
+        if (sh.A == 1 || D == 1)
+            k_spread<D, J, 1><<<grid, dim3(64 * sh.nwave), sh.lds, s>>>(g, a, sh.cw, sh.nwave);
+        else
+            k_spread<D, J, (D >= 2 ? 2 : 1)><<<grid, dim3(64 * sh.nwave), sh.lds, s>>>(g, a, sh.cw, sh.nwave);
+        e = hipGetLastError();
     }
-    if (D >= 2 && tcells <= 512 && os_on) {
-        const int want = std::min(a.nch, 32);
-        int cpt = 1;
-        while (cpt < want) cpt *= 2;
-        const int ngr = (a.nch + cpt - 1) / cpt;
-        dim3 grid_os((unsigned)ngr, (unsigned)std::min(a.nwork_max, KBN_GRID_Y_MAX));
-        dim3 blk((unsigned)tcells);
-        int tmax = 1;
-        for (int d = 0; d < D; ++d) tmax = std::max(tmax, g.To[d]);
-        const int ebv = D == 3 ? (cpt <= 16 ? 64 : 32) : 32;  // entries per batch of the chosen kernel
-        const size_t tlds = D == 3 ? sizeof(float) * (size_t)ebv * D * tmax : 0;
-        if (D == 3) {
-            switch (cpt) {
-                case 1: k_spread_os<D, J, 1, 64><<<grid_os, blk, tlds, s>>>(g, a); break;
-                case 2: k_spread_os<D, J, 2, 64><<<grid_os, blk, tlds, s>>>(g, a); break;
-                case 4: k_spread_os<D, J, 4, 64><<<grid_os, blk, tlds, s>>>(g, a); break;
-                case 8: k_spread_os<D, J, 8, 64><<<grid_os, blk, tlds, s>>>(g, a); break;
-                case 16: k_spread_os<D, J, 16, 64><<<grid_os, blk, tlds, s>>>(g, a); break;
-                default: k_spread_os<D, J, 32, 32><<<grid_os, blk, tlds, s>>>(g, a); break;
-            }
-        } else {
-            switch (cpt) {
-                case 1: k_spread_os<D, J, 1, 32><<<grid_os, blk, tlds, s>>>(g, a); break;
-                case 2: k_spread_os<D, J, 2, 32><<<grid_os, blk, tlds, s>>>(g, a); break;
-                case 4: k_spread_os<D, J, 4, 32><<<grid_os, blk, tlds, s>>>(g, a); break;
-                case 8: k_spread_os<D, J, 8, 32><<<grid_os, blk, tlds, s>>>(g, a); break;
-                case 16: k_spread_os<D, J, 16, 32><<<grid_os, blk, tlds, s>>>(g, a); break;
-                default: k_spread_os<D, J, 32, 32><<<grid_os, blk, tlds, s>>>(g, a); break;
-            }
-        }
-        if (a.ncomb_max > 0) {
-            const int cb = std::min(KBN_BLOCK, (tcells + 63) / 64 * 64);
-            const int ny = std::max(1, std::min(a.ncomb_max, 8 * 256 * 4 / a.nch + 1));
-            k_spread_combine<D><<<dim3((unsigned)a.nch, (unsigned)ny), dim3(cb), 0, s>>>(g, a);
-        }
-        return hipGetLastError();
-    }
-    if (a.M > 0) {  // the scatter kernel reads k-space values in tile order
-        dim3 pgrid((unsigned)((a.M + KBN_BLOCK - 1) / KBN_BLOCK), (unsigned)a.nch);
-        k_permute<<<pgrid, dim3(KBN_BLOCK), 0, s>>>(a.y, a.ys, a.order, a.M);
-    }
-    dim3 grid((unsigned)ng, (unsigned)a.nwork_max);  // one workgroup row per work item
-    if (sh.A == 1 || D == 1)
-        k_spread<D, J, 1><<<grid, dim3(64 * sh.nwave), sh.lds, s>>>(g, a, sh.cw, sh.nwave);
-    else
-        k_spread<D, J, (D >= 2 ? 2 : 1)><<<grid, dim3(64 * sh.nwave), sh.lds, s>>>(g, a, sh.cw, sh.nwave);
-    if (a.ncomb_max > 0)
-        k_spread_combine<D><<<dim3((unsigned)a.nch, (unsigned)a.ncomb_max), dim3(KBN_BLOCK), 0, s>>>(g, a);
-    return hipGetLastError();
+    if (e != hipSuccess) return e;
+    return spread_combine<D>(sel, g, a, s);
 }
 
 template <int D>
@@ -1149,6 +1239,20 @@ hipError_t gather_d(const KbnGeom &g, const KbnGatherArgs &a, int mode, hipStrea
 }
 
 template <int D>
+hipError_t gather_multi_d(int J, int mode, const KbnGatherJob *jobs, const int64_t *start, int njobs, int64_t total,
+                          size_t lds, hipStream_t s) {
+    switch (J) {
+        case 2: return gather_multi_dj<D, 2>(mode, jobs, start, njobs, total, lds, s);
+        case 3: return gather_multi_dj<D, 3>(mode, jobs, start, njobs, total, lds, s);
+        case 4: return gather_multi_dj<D, 4>(mode, jobs, start, njobs, total, lds, s);
+        case 5: return gather_multi_dj<D, 5>(mode, jobs, start, njobs, total, lds, s);
+        case 6: return gather_multi_dj<D, 6>(mode, jobs, start, njobs, total, lds, s);
+        case 7: return gather_multi_dj<D, 7>(mode, jobs, start, njobs, total, lds, s);
+        default: return gather_multi_dj<D, 8>(mode, jobs, start, njobs, total, lds, s);
+    }
+}
+
+template <int D>
 hipError_t spread_d(const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s) {
     switch (g.J) {
         case 2: return spread_dj<D, 2>(g, a, s);
@@ -1161,13 +1265,87 @@ hipError_t spread_d(const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s) {
     }
 }
 
+template <int D>
+hipError_t spread_os_multi_d(const KbnSpreadSel &sel, int J, dim3 grid, const KbnSpreadJob *jobs, const int *ystart,
+                             int njobs, hipStream_t s) {
+    switch (J) {
+        case 2: return launch_os_multi<D, 2>(sel, grid, jobs, ystart, njobs, s);
+        case 3: return launch_os_multi<D, 3>(sel, grid, jobs, ystart, njobs, s);
+        case 4: return launch_os_multi<D, 4>(sel, grid, jobs, ystart, njobs, s);
+        case 5: return launch_os_multi<D, 5>(sel, grid, jobs, ystart, njobs, s);
+        case 6: return launch_os_multi<D, 6>(sel, grid, jobs, ystart, njobs, s);
+        case 7: return launch_os_multi<D, 7>(sel, grid, jobs, ystart, njobs, s);
+        default: return launch_os_multi<D, 8>(sel, grid, jobs, ystart, njobs, s);
+    }
+}
+
 }  // namespace
+
+// Which spread kernel a call takes, with its launch shape: the
+// channel-per-lane kernel (2D 8 x 8 owner tiles, at least 64 channels and
+// enough tiles x channel groups to fill the chip's wave slots twice), the
+// output-stationary one (2D/3D owner tiles of at most 512 cells), else the
+// scatter kernel.  All give the same sums for finite data.
+KbnSpreadSel kbn_spread_select(const KbnGeom &g, const KbnSpreadArgs &a) {
+    static const bool os_on = [] {
+        const char *e = std::getenv("KBN_SPREAD_OS");
+        return !(e && e[0] == '0');
+    }();
+    static const bool cl_on = [] {
+        const char *e = std::getenv("KBN_SPREAD_CL");
+        return !(e && e[0] == '0');
+    }();
+    KbnSpreadSel sel;
+    const int D = g.D;
+    int tcells = 1, tmax = 1;
+    for (int d = 0; d < D; ++d) {
+        tcells *= g.To[d];
+        tmax = std::max(tmax, g.To[d]);
+    }
+    sel.tcells = tcells;
+    const int64_t cl_waves = (int64_t)g.ntiles_own * ((a.nch + 63) / 64);
+    if (D == 2 && os_on && cl_on && g.To[0] == 8 && g.To[1] == 8 && a.nch >= 64 && cl_waves >= 4096 &&
+        64 * a.M * (int64_t)sizeof(float2) < ((int64_t)1 << 31)) {
+        sel.path = KBN_SPREAD_PATH_CL;
+        return sel;
+    }
+    if (D >= 2 && tcells <= 512 && os_on) {
+        sel.path = KBN_SPREAD_PATH_OS;
+        const int want = std::min(a.nch, 32);
+        int cpt = 1;
+        while (cpt < want) cpt *= 2;
+        sel.cpt = cpt;
+        sel.ngr = (a.nch + cpt - 1) / cpt;
+        sel.ny = std::min(a.nwork_max, KBN_GRID_Y_MAX);
+        // entries per batch of the chosen kernel, and the 3D weight tables
+        sel.ebv = D == 3 ? (cpt <= 16 ? 64 : 32) : 32;
+        sel.lds = D == 3 ? sizeof(float) * (size_t)sel.ebv * D * tmax : 0;
+        return sel;
+    }
+    sel.path = KBN_SPREAD_PATH_GENERIC;
+    return sel;
+}
 
 hipError_t kbn_launch_gather(const KbnGeom &g, const KbnGatherArgs &a, int mode, hipStream_t s) {
     switch (g.D) {
         case 1: return gather_d<1>(g, a, mode, s);
         case 2: return gather_d<2>(g, a, mode, s);
         default: return gather_d<3>(g, a, mode, s);
+    }
+}
+
+hipError_t kbn_launch_gather_reduce(const KbnGeom &g, const KbnGatherArgs &a, hipStream_t s) {
+    if (a.M == 0 || a.nch == 0) return hipSuccess;
+    return reduce_parts(g, a, kbn_gather_shape(g, a.M, a.nch, a.nw).groups, s);
+}
+
+hipError_t kbn_launch_gather_multi(int D, int J, int mode, const KbnGatherJob *jobs, const int64_t *start, int njobs,
+                                   int64_t total, size_t lds, hipStream_t s) {
+    if (njobs == 0 || total == 0) return hipSuccess;
+    switch (D) {
+        case 1: return gather_multi_d<1>(J, mode, jobs, start, njobs, total, lds, s);
+        case 2: return gather_multi_d<2>(J, mode, jobs, start, njobs, total, lds, s);
+        default: return gather_multi_d<3>(J, mode, jobs, start, njobs, total, lds, s);
     }
 }
 
@@ -1179,5 +1357,19 @@ hipError_t kbn_launch_spread(const KbnGeom &g, const KbnSpreadArgs &a, hipStream
     }
 }
 
+hipError_t kbn_launch_spread_os_multi(const KbnSpreadSel &sel, int D, int J, int maxngr, const KbnSpreadJob *jobs,
+                                      const int *ystart, int njobs, int total_y, hipStream_t s) {
+    if (njobs == 0 || total_y == 0) return hipSuccess;
+    const dim3 grid((unsigned)maxngr, (unsigned)total_y);
+    if (D == 2) return spread_os_multi_d<2>(sel, J, grid, jobs, ystart, njobs, s);
+    return spread_os_multi_d<3>(sel, J, grid, jobs, ystart, njobs, s);
+}
 
-
+hipError_t kbn_launch_spread_combine(const KbnSpreadSel &sel, const KbnGeom &g, const KbnSpreadArgs &a,
+                                     hipStream_t s) {
+    switch (g.D) {
+        case 1: return spread_combine<1>(sel, g, a, s);
+        case 2: return spread_combine<2>(sel, g, a, s);
+        default: return spread_combine<3>(sel, g, a, s);
+    }
+}

@@ -221,6 +221,48 @@ struct KbnSpreadArgs {
 hipError_t kbn_launch_gather(const KbnGeom &g, const KbnGatherArgs &a, int mode, hipStream_t s);
 hipError_t kbn_launch_spread(const KbnGeom &g, const KbnSpreadArgs &a, hipStream_t s);
 
+// Interpolation of several plans in one launch (the batch's fused phases).
+// A job is one plan's call: its geometry and arguments as the single-call
+// launch takes them, copied to device memory by the caller.
+struct KbnGatherJob {
+    KbnGeom g;
+    KbnGatherArgs a;
+    int cg;      // channels per group (kbn_gather_shape)
+    int blocks;  // subproblem workgroups per channel group
+};
+// staged gathers of jobs that share D and J; start[i] = first workgroup of
+// job i (blocks x groups each), start[njobs] = total; lds = the largest
+// job's region bytes.  Mode 1 leaves each job's epilogue to
+// kbn_launch_gather_reduce.
+hipError_t kbn_launch_gather_multi(int D, int J, int mode, const KbnGatherJob *jobs, const int64_t *start, int njobs,
+                                   int64_t total, size_t lds, hipStream_t s);
+hipError_t kbn_launch_gather_reduce(const KbnGeom &g, const KbnGatherArgs &a, hipStream_t s);
+
+#define KBN_SPREAD_PATH_GENERIC 0
+#define KBN_SPREAD_PATH_OS 1
+#define KBN_SPREAD_PATH_CL 2
+struct KbnSpreadSel {
+    int path = KBN_SPREAD_PATH_GENERIC;
+    int cpt = 0, ebv = 0, tcells = 0;  // output-stationary: channels per thread, entries per batch, cells
+    size_t lds = 0;                    // its dynamic LDS
+    int ngr = 0, ny = 0;               // its grid: channel groups x work-item rows
+};
+KbnSpreadSel kbn_spread_select(const KbnGeom &g, const KbnSpreadArgs &a);
+struct KbnSpreadJob {
+    KbnGeom g;
+    KbnSpreadArgs a;
+    int ngr;  // channel groups
+    int ny;   // workgroup rows striding over the work items
+};
+// output-stationary spreads of jobs whose kbn_spread_select agree on D, J,
+// cpt, ebv and the owner tile (so one workgroup size); ystart[i] = first
+// row of job i, grid maxngr x total_y.  Each job's split tiles are then
+// summed by kbn_launch_spread_combine.
+hipError_t kbn_launch_spread_os_multi(const KbnSpreadSel &sel, int D, int J, int maxngr, const KbnSpreadJob *jobs,
+                                      const int *ystart, int njobs, int total_y, hipStream_t s);
+hipError_t kbn_launch_spread_combine(const KbnSpreadSel &sel, const KbnGeom &g, const KbnSpreadArgs &a,
+                                     hipStream_t s);
+
 // ---------------------------------------------------------------------------
 // Plan hooks used by the batch executor (plan.cpp)
 // ---------------------------------------------------------------------------
@@ -229,6 +271,33 @@ void kbn_internal_graph_ref(kbn_plan p, int delta);  // captured graphs holding 
 int kbn_internal_fail(int code, const char *msg);    // sets the thread's last error
 // estimated bytes moved by one call (jac: D channels per coil; type1: adjoint type)
 double kbn_internal_cost(kbn_plan p, int B, int C, int jac, int type1);
+uint64_t kbn_internal_epoch(kbn_plan p);  // changes with every kbn_set_points
+// device memory through the plan's allocator, counted in its footprint
+int kbn_internal_alloc(kbn_plan p, void **ptr, int64_t bytes, hipStream_t s);
+void kbn_internal_free(kbn_plan p, void *ptr, hipStream_t s);
+
+// One batch task split into phases around its interpolation (the batch's
+// fused mode): kind 0 = forward-type (gather), 1 = omega-Jacobian (gather
+// with the gradient epilogue), 2 = adjoint-type (spread), -1 = issued whole.
+struct KbnPhased {
+    kbn_plan p = nullptr;
+    int op = 0, kind = -1;
+    int B = 0, C = 0, nw = 1, weighted = 0, accumulate = 0;
+    const float2 *x = nullptr, *smaps = nullptr, *v = nullptr, *ky = nullptr;
+    float2 *y = nullptr, *img = nullptr;
+    float *dom = nullptr;
+    char *ws = nullptr;  // the task's own grids (and gradient parts / k-space copy / partial tiles)
+    float2 *bufA = nullptr, *bufB = nullptr;
+    KbnGatherJob gj;     // kinds 0, 1
+    int groups = 0;
+    size_t lds = 0;
+    KbnSpreadJob sj;     // kind 2
+    KbnSpreadSel sel;
+};
+int kbn_internal_phase_prepare(const kbn_task &t, KbnPhased *ph, hipStream_t s);
+int kbn_internal_phase_pre(KbnPhased *ph, hipStream_t s);
+int kbn_internal_phase_post(KbnPhased *ph, hipStream_t s);
+void kbn_internal_phase_release(KbnPhased *ph, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // CG-SENSE vector kernels (cg.hip)

@@ -226,6 +226,9 @@ struct kbn_plan_s {
     // captured batch graphs that hold this plan's buffer addresses; while
     // non-zero the plan refuses anything that would move or resize them
     int graph_refs = 0;
+    // bumped by every kbn_set_points: descriptors of phased batch calls that
+    // hold this plan's point buffers and M are rebuilt when it changes
+    uint64_t epoch = 0;
     // partial-tile slots for owner tiles split into several spread work items
     int smax = KBN_SPREAD_SMAX;
     int sub = KBN_SUB;  // samples per gather subproblem
@@ -473,15 +476,97 @@ int64_t points_bytes(const kbn_plan p, int64_t M) {
            2 * block_bytes(4 * z.ent * D);
 }
 
-// Forward-type pipeline: scaling (+ coil map, + coordinate weight), FFT
-// passes, then gather.  mode 0 writes y; mode 1 folds the omega-Jacobian.
-// ext_ws (mode 0 only): a workspace of ext_bytes given by the caller
-// instead of the plan's, which is then neither grown nor used; the batch is
-// chunked to fit it.
+// FFT passes of one forward-type chunk (nb images from b0, ncc coils from
+// c0, nw weight channels per coil): scaling (+ coil map, + coordinate
+// weight) and the last-axis pass into bufA, then the strided passes
+// alternating between the buffers; *grid is the buffer that holds the
+// oversampled spectra at the end.
+int t2_passes(kbn_plan p, int nw, int weighted, const float2 *x, const float2 *smaps, int64_t b0, int c0,
+              int64_t nb, int ncc, float2 *bufA, float2 *bufB, float2 **grid, hipStream_t stream) {
+    const int D = p->D;
+    const int64_t R0 = img_rows(p);
+    const int Nl = p->N[D - 1];
+    const int64_t nch = nb * ncc * nw;
+    KbnFirstPassArgs fa;
+    fa.x = x + b0 * R0 * Nl;
+    fa.smaps = smaps ? smaps + (int64_t)c0 * R0 * Nl : nullptr;
+    fa.out = bufA;
+    fa.nlines = nch * R0;
+    fa.R0 = (int)R0;
+    fa.Nl = Nl;
+    fa.C = ncc;
+    fa.nw = nw;
+    fa.weighted = weighted;
+    fa.D = D;
+    for (int d = 0; d < KBN_MAX_D; ++d) {
+        fa.N[d] = p->N[d];
+        fa.deap[d] = p->deap[d];
+    }
+    if (p->fast_fft && kbn_fast_fft_size(p->K[D - 1]))
+        KBN_LAUNCH(KBN_CLASS_FFT_FIRST, kbn_launch_fast_first(fa, p->K[D - 1], p->tw[D - 1], stream),
+                   "first pass");
+    else
+        KBN_LAUNCH(KBN_CLASS_FFT_FIRST,
+                   kbn_launch_first_pass(fa, p->rad[D - 1], p->tw[D - 1], p->maxe, stream),
+                   "first pass");
+    float2 *cur = bufA, *nxt = bufB;
+    for (int d = D - 2; d >= 0; --d) {
+        int64_t outer = nch, inner = 1;
+        for (int e = 0; e < d; ++e) outer *= p->N[e];
+        for (int e = d + 1; e < D; ++e) inner *= p->K[e];
+        KbnMidPassArgs ma;
+        ma.in = cur;
+        ma.out = nxt;
+        ma.outer = outer;
+        ma.nin = p->N[d];
+        ma.nout = p->K[d];
+        ma.inner = (int)inner;
+        ma.pad_in = 1;
+        ma.crop_out = 0;
+        if (p->fast_fft && kbn_fast_fft_size(p->K[d]))
+            KBN_LAUNCH(KBN_CLASS_FFT_MID_FWD, kbn_launch_fast_mid(ma, p->K[d], p->tw[d], 0, stream),
+                       "mid pass");
+        else
+            KBN_LAUNCH(KBN_CLASS_FFT_MID_FWD,
+                       kbn_launch_mid_pass(ma, p->rad[d], p->tw[d], 0, p->maxe, stream), "mid pass");
+        std::swap(cur, nxt);
+    }
+    *grid = cur;
+    return KBN_OK;
+}
+
+// Gather arguments of one forward-type chunk of nch channels (k-space
+// offset k0 of its first image-coil pair).
+KbnGatherArgs t2_gather_args(kbn_plan p, int64_t nch, int ncc, int nw, int mode, const float2 *grid, int64_t k0,
+                             float2 *y, const float2 *v, float *dom, float *part, int accumulate) {
+    KbnGatherArgs ga;
+    ga.grid = grid;
+    ga.gsize = p->gsize();
+    ga.nch = (int)nch;
+    ga.C = ncc;
+    ga.nw = nw;
+    ga.M = p->M;
+    ga.order = p->order;
+    ga.cell = p->cell;
+    ga.frac = p->frac;
+    ga.toff = p->toff;
+    ga.subs = p->subs;
+    ga.nsub = p->nsub;
+    ga.y = mode == 0 ? y + k0 : nullptr;
+    ga.v = mode == 1 ? v + k0 : nullptr;
+    ga.domega = dom;
+    ga.part = part;
+    ga.accumulate = accumulate;
+    return ga;
+}
+
+// Forward-type pipeline: FFT passes, then gather.  mode 0 writes y; mode 1
+// folds the omega-Jacobian.  ext_ws (mode 0 only): a workspace of ext_bytes
+// given by the caller instead of the plan's, which is then neither grown
+// nor used; the batch is chunked to fit it.
 int run_type2(kbn_plan p, int B, int C, int nw, int weighted, const float2 *x,
               const float2 *smaps, int mode, float2 *y, const float2 *v, float *dom,
               int accumulate, hipStream_t stream, void *ext_ws = nullptr, int64_t ext_bytes = 0) {
-    const int D = p->D;
     const int64_t gsz = p->gsize();
     const int64_t per_coil = (int64_t)nw * gsz * (int64_t)sizeof(float2) * 2;
     const Chunks ck = split_chunks(B, C, per_coil, ext_ws ? ext_bytes : p->max_ws);
@@ -495,79 +580,115 @@ int run_type2(kbn_plan p, int B, int C, int nw, int weighted, const float2 *x,
     float2 *bufA = ws;
     float2 *bufB = ws + units * nw * gsz;
     float *part = (float *)(ws + 2 * units * nw * gsz);
-    const int64_t R0 = img_rows(p);
-    const int Nl = p->N[D - 1];
     const KbnGeom geom = p->geom();
     for (int64_t b0 = 0; b0 < B; b0 += ck.bc)
     for (int c0 = 0; c0 < C; c0 += ck.cc) {
         const int64_t nb = std::min<int64_t>(ck.bc, B - b0);
         const int ncc = std::min(ck.cc, C - c0);
         const int64_t nch = nb * ncc * nw;
-        const int64_t k0 = (b0 * C + c0) * p->M;  // k-space offset of the chunk
-        KbnFirstPassArgs fa;
-        fa.x = x + b0 * R0 * Nl;
-        fa.smaps = smaps ? smaps + (int64_t)c0 * R0 * Nl : nullptr;
-        fa.out = bufA;
-        fa.nlines = nch * R0;
-        fa.R0 = (int)R0;
-        fa.Nl = Nl;
-        fa.C = ncc;
-        fa.nw = nw;
-        fa.weighted = weighted;
-        fa.D = D;
-        for (int d = 0; d < KBN_MAX_D; ++d) {
-            fa.N[d] = p->N[d];
-            fa.deap[d] = p->deap[d];
-        }
-        if (p->fast_fft && kbn_fast_fft_size(p->K[D - 1]))
-            KBN_LAUNCH(KBN_CLASS_FFT_FIRST, kbn_launch_fast_first(fa, p->K[D - 1], p->tw[D - 1], stream),
-                       "first pass");
-        else
-            KBN_LAUNCH(KBN_CLASS_FFT_FIRST,
-                       kbn_launch_first_pass(fa, p->rad[D - 1], p->tw[D - 1], p->maxe, stream),
-                       "first pass");
-        float2 *cur = bufA, *nxt = bufB;
-        for (int d = D - 2; d >= 0; --d) {
-            int64_t outer = nch, inner = 1;
-            for (int e = 0; e < d; ++e) outer *= p->N[e];
-            for (int e = d + 1; e < D; ++e) inner *= p->K[e];
-            KbnMidPassArgs ma;
-            ma.in = cur;
-            ma.out = nxt;
-            ma.outer = outer;
-            ma.nin = p->N[d];
-            ma.nout = p->K[d];
-            ma.inner = (int)inner;
-            ma.pad_in = 1;
-            ma.crop_out = 0;
-            if (p->fast_fft && kbn_fast_fft_size(p->K[d]))
-                KBN_LAUNCH(KBN_CLASS_FFT_MID_FWD, kbn_launch_fast_mid(ma, p->K[d], p->tw[d], 0, stream),
-                           "mid pass");
-            else
-                KBN_LAUNCH(KBN_CLASS_FFT_MID_FWD,
-                           kbn_launch_mid_pass(ma, p->rad[d], p->tw[d], 0, p->maxe, stream), "mid pass");
-            std::swap(cur, nxt);
-        }
-        KbnGatherArgs ga;
-        ga.grid = cur;
-        ga.gsize = gsz;
-        ga.nch = (int)nch;
-        ga.C = ncc;
-        ga.nw = nw;
-        ga.M = p->M;
-        ga.order = p->order;
-        ga.cell = p->cell;
-        ga.frac = p->frac;
-        ga.toff = p->toff;
-        ga.subs = p->subs;
-        ga.nsub = p->nsub;
-        ga.y = mode == 0 ? y + k0 : nullptr;
-        ga.v = mode == 1 ? v + k0 : nullptr;
-        ga.domega = dom;
-        ga.part = part;
-        ga.accumulate = (accumulate || b0 > 0 || c0 > 0) ? 1 : 0;
+        float2 *grid = nullptr;
+        int rc = t2_passes(p, nw, weighted, x, smaps, b0, c0, nb, ncc, bufA, bufB, &grid, stream);
+        if (rc != KBN_OK) return rc;
+        const KbnGatherArgs ga = t2_gather_args(p, nch, ncc, nw, mode, grid, (b0 * C + c0) * p->M, y, v, dom, part,
+                                                (accumulate || b0 > 0 || c0 > 0) ? 1 : 0);
         KBN_LAUNCH(mode == 0 ? KBN_CLASS_GATHER : KBN_CLASS_GATHER_JAC, kbn_launch_gather(geom, ga, mode, stream), "gather");
     }
+    return KBN_OK;
+}
+
+// Spread arguments of one adjoint chunk of nch image-coil pairs (k-space
+// from y_chunk) into the grids at bufA, with its k-space copy bufY and
+// partial tiles bufP.
+KbnSpreadArgs t1_spread_args(kbn_plan p, int64_t nch, const float2 *y_chunk, float2 *bufA, float2 *bufY,
+                             float2 *bufP) {
+    KbnSpreadArgs sa;
+    sa.y = y_chunk;
+    sa.ys = bufY;
+    sa.grid = bufA;
+    sa.gsize = p->gsize();
+    sa.nch = (int)nch;
+    sa.M = p->M;
+    sa.order = p->order;
+    sa.cell = p->cell;
+    sa.frac = p->frac;
+    sa.toff = p->toff;
+    sa.otile_order = p->otile_order;
+    sa.swork = p->swork;
+    sa.scomb = p->scomb;
+    sa.scounts = p->scounts;
+    sa.partial = bufP;
+    sa.rec_p = p->rec_p;
+    sa.rec_q = p->rec_q;
+    sa.rec_l = p->rec_l;
+    sa.rec_f = p->rec_f;
+    sa.nwork_max = (int)p->swork_cap;
+    sa.ncomb_max = std::min<int>(p->ntiles_own, p->smax / 2);
+    return sa;
+}
+
+// Inverse FFT passes of one adjoint chunk whose spread grids are in bufA:
+// strided passes with cropping, then the last-axis pass with cropping,
+// scaling and conj(coil map), summed over the chunk's coils into x.
+int t1_passes(kbn_plan p, int64_t b0, int c0, int64_t nb, int ncc, const float2 *smaps, float2 *x, float2 *bufA,
+              float2 *bufB, hipStream_t stream) {
+    const int D = p->D;
+    const int64_t R0 = img_rows(p);
+    const int Nl = p->N[D - 1];
+    const int64_t nch = nb * ncc;
+    float2 *cur = bufA, *nxt = bufB;
+    for (int d = 0; d + 1 < D; ++d) {
+        int64_t outer = nch, inner = 1;
+        for (int e = 0; e < d; ++e) outer *= p->N[e];
+        for (int e = d + 1; e < D; ++e) inner *= p->K[e];
+        KbnMidPassArgs ma;
+        ma.in = cur;
+        ma.out = nxt;
+        ma.outer = outer;
+        ma.nin = p->K[d];
+        ma.nout = p->N[d];
+        ma.inner = (int)inner;
+        ma.pad_in = 0;
+        ma.crop_out = 1;
+        if (p->fast_fft && kbn_fast_fft_size(p->K[d]))
+            KBN_LAUNCH(KBN_CLASS_FFT_MID_INV, kbn_launch_fast_mid(ma, p->K[d], p->tw[d], 1, stream),
+                       "mid pass");
+        else
+            KBN_LAUNCH(KBN_CLASS_FFT_MID_INV,
+                       kbn_launch_mid_pass(ma, p->rad[d], p->tw[d], 1, p->maxe, stream), "mid pass");
+        std::swap(cur, nxt);
+    }
+    // With few image rows per coil, the coil loop inside each line would
+    // leave the GPU idle: then every (image, coil) line is transformed on
+    // its own into the free buffer and the coils are summed afterwards.
+    // The choice depends only on the image shape and coil count, so the
+    // same problem gives the same bits whatever the batch size.
+    const bool split = ncc > 1 && R0 < 2048;
+    KbnLastAdjArgs la;
+    la.in = cur;
+    la.smaps = smaps ? smaps + (int64_t)c0 * R0 * Nl : nullptr;
+    la.x = split ? nxt : x + b0 * R0 * Nl;
+    la.nlines = split ? nb * ncc * R0 : nb * R0;
+    la.R0 = (int)R0;
+    la.Nl = Nl;
+    la.C = split ? 1 : ncc;
+    la.cmod = split ? ncc : 0;
+    la.accumulate = (!split && c0 > 0) ? 1 : 0;  // later coil runs add to the image
+    la.D = D;
+    for (int d = 0; d < KBN_MAX_D; ++d) {
+        la.N[d] = p->N[d];
+        la.deap[d] = p->deap[d];
+    }
+    if (p->fast_fft && kbn_fast_last_size(p->K[D - 1]))
+        KBN_LAUNCH(KBN_CLASS_FFT_LAST_ADJ, kbn_launch_fast_last(la, p->K[D - 1], p->tw[D - 1], stream),
+                   "last adjoint pass");
+    else
+        KBN_LAUNCH(KBN_CLASS_FFT_LAST_ADJ,
+                   kbn_launch_last_adj(la, p->rad[D - 1], p->tw[D - 1], p->maxe, stream),
+                   "last adjoint pass");
+    if (split)
+        KBN_LAUNCH(KBN_CLASS_FFT_LAST_ADJ,
+                   kbn_launch_coil_sum(nxt, nb, ncc, R0 * Nl, x + b0 * R0 * Nl, c0 > 0 ? 1 : 0, stream),
+                   "coil sum");
     return KBN_OK;
 }
 
@@ -575,7 +696,6 @@ int run_type2(kbn_plan p, int B, int C, int nw, int weighted, const float2 *x,
 // conj(coil map) summed over coils.
 int run_type1(kbn_plan p, int B, int C, const float2 *y, const float2 *smaps, float2 *x,
               hipStream_t stream) {
-    const int D = p->D;
     const int64_t gsz = p->gsize();
     const int64_t per_coil = type1_per_coil(p, p->M);
     const Chunks ck = split_chunks(B, C, per_coil, p->max_ws);
@@ -586,91 +706,16 @@ int run_type1(kbn_plan p, int B, int C, const float2 *y, const float2 *smaps, fl
     float2 *bufB = p->ws + units * gsz;
     float2 *bufY = p->ws + 2 * units * gsz;
     float2 *bufP = bufY + units * p->M;
-    const int64_t R0 = img_rows(p);
-    const int Nl = p->N[D - 1];
     const KbnGeom geom = p->geom();
     for (int64_t b0 = 0; b0 < B; b0 += ck.bc)
     for (int c0 = 0; c0 < C; c0 += ck.cc) {
         const int64_t nb = std::min<int64_t>(ck.bc, B - b0);
         const int ncc = std::min(ck.cc, C - c0);
         const int64_t nch = nb * ncc;
-        KbnSpreadArgs sa;
-        sa.y = y + (b0 * C + c0) * p->M;
-        sa.ys = bufY;
-        sa.grid = bufA;
-        sa.gsize = gsz;
-        sa.nch = (int)nch;
-        sa.M = p->M;
-        sa.order = p->order;
-        sa.cell = p->cell;
-        sa.frac = p->frac;
-        sa.toff = p->toff;
-        sa.otile_order = p->otile_order;
-        sa.swork = p->swork;
-        sa.scomb = p->scomb;
-        sa.scounts = p->scounts;
-        sa.partial = bufP;
-        sa.rec_p = p->rec_p;
-        sa.rec_q = p->rec_q;
-        sa.rec_l = p->rec_l;
-        sa.rec_f = p->rec_f;
-        sa.nwork_max = (int)p->swork_cap;
-        sa.ncomb_max = std::min<int>(p->ntiles_own, p->smax / 2);
+        const KbnSpreadArgs sa = t1_spread_args(p, nch, y + (b0 * C + c0) * p->M, bufA, bufY, bufP);
         KBN_LAUNCH(KBN_CLASS_SPREAD, kbn_launch_spread(geom, sa, stream), "spread");
-        float2 *cur = bufA, *nxt = bufB;
-        for (int d = 0; d + 1 < D; ++d) {
-            int64_t outer = nch, inner = 1;
-            for (int e = 0; e < d; ++e) outer *= p->N[e];
-            for (int e = d + 1; e < D; ++e) inner *= p->K[e];
-            KbnMidPassArgs ma;
-            ma.in = cur;
-            ma.out = nxt;
-            ma.outer = outer;
-            ma.nin = p->K[d];
-            ma.nout = p->N[d];
-            ma.inner = (int)inner;
-            ma.pad_in = 0;
-            ma.crop_out = 1;
-            if (p->fast_fft && kbn_fast_fft_size(p->K[d]))
-                KBN_LAUNCH(KBN_CLASS_FFT_MID_INV, kbn_launch_fast_mid(ma, p->K[d], p->tw[d], 1, stream),
-                           "mid pass");
-            else
-                KBN_LAUNCH(KBN_CLASS_FFT_MID_INV,
-                           kbn_launch_mid_pass(ma, p->rad[d], p->tw[d], 1, p->maxe, stream), "mid pass");
-            std::swap(cur, nxt);
-        }
-        // With few image rows per coil, the coil loop inside each line would
-        // leave the GPU idle: then every (image, coil) line is transformed on
-        // its own into the free buffer and the coils are summed afterwards.
-        // The choice depends only on the image shape and coil count, so the
-        // same problem gives the same bits whatever the batch size.
-        const bool split = ncc > 1 && R0 < 2048;
-        KbnLastAdjArgs la;
-        la.in = cur;
-        la.smaps = smaps ? smaps + (int64_t)c0 * R0 * Nl : nullptr;
-        la.x = split ? nxt : x + b0 * R0 * Nl;
-        la.nlines = split ? nb * ncc * R0 : nb * R0;
-        la.R0 = (int)R0;
-        la.Nl = Nl;
-        la.C = split ? 1 : ncc;
-        la.cmod = split ? ncc : 0;
-        la.accumulate = (!split && c0 > 0) ? 1 : 0;  // later coil runs add to the image
-        la.D = D;
-        for (int d = 0; d < KBN_MAX_D; ++d) {
-            la.N[d] = p->N[d];
-            la.deap[d] = p->deap[d];
-        }
-        if (p->fast_fft && kbn_fast_last_size(p->K[D - 1]))
-            KBN_LAUNCH(KBN_CLASS_FFT_LAST_ADJ, kbn_launch_fast_last(la, p->K[D - 1], p->tw[D - 1], stream),
-                       "last adjoint pass");
-        else
-            KBN_LAUNCH(KBN_CLASS_FFT_LAST_ADJ,
-                       kbn_launch_last_adj(la, p->rad[D - 1], p->tw[D - 1], p->maxe, stream),
-                       "last adjoint pass");
-        if (split)
-            KBN_LAUNCH(KBN_CLASS_FFT_LAST_ADJ,
-                       kbn_launch_coil_sum(nxt, nb, ncc, R0 * Nl, x + b0 * R0 * Nl, c0 > 0 ? 1 : 0, stream),
-                       "coil sum");
+        rc = t1_passes(p, b0, c0, nb, ncc, smaps, x, bufA, bufB, stream);
+        if (rc != KBN_OK) return rc;
     }
     return KBN_OK;
 }
@@ -712,6 +757,149 @@ double kbn_internal_cost(kbn_plan p, int B, int C, int jac, int type1) {
     double n = 1.0;
     for (int d = 0; d < p->D; ++d) n *= p->N[d];
     return (double)B * C * (g + 8.0 * (double)std::max<int64_t>(p->M, 0) + 8.0 * n);
+}
+
+uint64_t kbn_internal_epoch(kbn_plan p) { return p->epoch; }
+
+int kbn_internal_alloc(kbn_plan p, void **ptr, int64_t bytes, hipStream_t s) {
+    return dev_alloc(p, (char **)ptr, bytes, s);
+}
+void kbn_internal_free(kbn_plan p, void *ptr, hipStream_t s) {
+    char *q = (char *)ptr;
+    dev_free(p, q, s);
+}
+
+// A task in phases: validated as its call, with a workspace of its own so
+// that the interpolation of many tasks can run in one launch between the
+// tasks' FFT passes.  Tasks that need several chunks, have no points, or
+// whose interpolation would take another kernel stay whole (kind -1).
+int kbn_internal_phase_prepare(const kbn_task &t, KbnPhased *ph, hipStream_t s) {
+    *ph = KbnPhased();
+    ph->p = t.plan;
+    ph->op = t.op;
+    kbn_plan p = t.plan;
+    int rc = KBN_OK;
+    switch (t.op) {
+    case KBN_TASK_FORWARD:
+    case KBN_TASK_JAC_X_ADJ:
+        rc = check_common(p, t.B, t.C, t.a, t.smaps, t.out);
+        ph->kind = 0;
+        ph->nw = 1;
+        ph->weighted = 0;
+        ph->x = (const float2 *)t.a;
+        ph->y = (float2 *)t.out;
+        break;
+    case KBN_TASK_JAC_OMEGA_FWD:
+    case KBN_TASK_JAC_OMEGA_ADJ: {
+        const bool fwd = t.op == KBN_TASK_JAC_OMEGA_FWD;
+        // fwd: image a, upstream k-space g; adj: k-space a, upstream image g
+        rc = fwd ? check_common(p, t.B, t.C, t.a, t.smaps, t.g) : check_common(p, t.B, t.C, t.g, t.smaps, t.a);
+        if (rc == KBN_OK && !t.out && p->M > 0) rc = fail(KBN_ERR_INVALID_ARG, "null domega");
+        ph->kind = 1;
+        ph->nw = p->D;
+        ph->weighted = 1;
+        ph->x = (const float2 *)(fwd ? t.a : t.g);
+        ph->v = (const float2 *)(fwd ? t.g : t.a);
+        ph->dom = (float *)t.out;
+        ph->accumulate = t.accumulate;
+        break;
+    }
+    case KBN_TASK_ADJOINT:
+    case KBN_TASK_JAC_X_FWD:
+        rc = check_common(p, t.B, t.C, t.out, t.smaps, t.a);
+        ph->kind = 2;
+        ph->ky = (const float2 *)t.a;
+        ph->img = (float2 *)t.out;
+        break;
+    default:
+        return fail(KBN_ERR_INVALID_ARG, "unknown task op");
+    }
+    if (rc != KBN_OK) return rc;
+    ph->B = t.B;
+    ph->C = t.C;
+    ph->smaps = (const float2 *)t.smaps;
+    const KbnGeom geom = p->geom();
+    const int64_t gsz = p->gsize();
+    const int64_t units = (int64_t)t.B * t.C;
+    if (p->M == 0) {
+        ph->kind = -1;
+        return KBN_OK;
+    }
+    if (ph->kind <= 1) {
+        const int64_t per_coil = (int64_t)ph->nw * gsz * (int64_t)sizeof(float2) * 2;
+        const Chunks ck = split_chunks(t.B, t.C, per_coil, p->max_ws);
+        const int64_t nch = units * ph->nw;
+        const KbnGatherShape sh = kbn_gather_shape(geom, p->M, (int)nch, ph->nw);
+        if (ck.bc != t.B || ck.cc != t.C || !sh.staged) {
+            ph->kind = -1;
+            return KBN_OK;
+        }
+        const int64_t grids = 2 * nch * gsz * (int64_t)sizeof(float2);
+        const int64_t part = ph->kind == 1 ? (int64_t)sh.groups * p->M * p->D * (int64_t)sizeof(float) : 0;
+        rc = kbn_internal_alloc(p, (void **)&ph->ws, grids + part, s);
+        if (rc != KBN_OK) return rc;
+        ph->bufA = (float2 *)ph->ws;
+        ph->bufB = ph->bufA + nch * gsz;
+        float *partp = (float *)(ph->bufA + 2 * nch * gsz);
+        // the grid the passes end in: the last axis pass writes bufA and each
+        // strided pass swaps the buffers
+        float2 *grid = (p->D - 1) % 2 == 0 ? ph->bufA : ph->bufB;
+        ph->gj.g = geom;
+        ph->gj.a = t2_gather_args(p, nch, t.C, ph->nw, ph->kind, grid, 0, ph->y, ph->v, ph->dom, partp,
+                                  ph->accumulate ? 1 : 0);
+        ph->gj.cg = sh.cg;
+        ph->gj.blocks = (int)sh.blocks;
+        ph->groups = sh.groups;
+        ph->lds = sh.lds;
+        return KBN_OK;
+    }
+    const int64_t per_coil = type1_per_coil(p, p->M);
+    const Chunks ck = split_chunks(t.B, t.C, per_coil, p->max_ws);
+    KbnSpreadArgs probe = t1_spread_args(p, units, ph->ky, nullptr, nullptr, nullptr);
+    const KbnSpreadSel sel = kbn_spread_select(geom, probe);
+    if (ck.bc != t.B || ck.cc != t.C || sel.path != KBN_SPREAD_PATH_OS) {
+        ph->kind = -1;
+        return KBN_OK;
+    }
+    rc = kbn_internal_alloc(p, (void **)&ph->ws, units * per_coil, s);
+    if (rc != KBN_OK) return rc;
+    ph->bufA = (float2 *)ph->ws;
+    ph->bufB = ph->bufA + units * gsz;
+    float2 *bufY = ph->bufA + 2 * units * gsz;
+    float2 *bufP = bufY + units * p->M;
+    ph->sj.g = geom;
+    ph->sj.a = t1_spread_args(p, units, ph->ky, ph->bufA, bufY, bufP);
+    ph->sj.ngr = sel.ngr;
+    ph->sj.ny = sel.ny;
+    ph->sel = sel;
+    return KBN_OK;
+}
+
+// Before the interpolation: the FFT passes of a forward-type task.
+int kbn_internal_phase_pre(KbnPhased *ph, hipStream_t stream) {
+    if (ph->kind < 0 || ph->kind > 1) return KBN_OK;
+    kbn_plan p = ph->p;
+    float2 *grid = nullptr;
+    return t2_passes(p, ph->nw, ph->weighted, ph->x, ph->smaps, 0, 0, ph->B, ph->C, ph->bufA, ph->bufB, &grid,
+                     stream);
+}
+
+// After the interpolation: the omega-gradient's sum over channel groups, or
+// the adjoint's split-tile sums and inverse FFT passes.
+int kbn_internal_phase_post(KbnPhased *ph, hipStream_t stream) {
+    kbn_plan p = ph->p;
+    if (ph->kind == 1)
+        KBN_LAUNCH(KBN_CLASS_GATHER_JAC, kbn_launch_gather_reduce(ph->gj.g, ph->gj.a, stream), "gradient sum");
+    if (ph->kind == 2) {
+        KBN_LAUNCH(KBN_CLASS_SPREAD, kbn_launch_spread_combine(ph->sel, ph->sj.g, ph->sj.a, stream), "spread combine");
+        return t1_passes(p, 0, 0, ph->B, ph->C, ph->smaps, ph->img, ph->bufA, ph->bufB, stream);
+    }
+    return KBN_OK;
+}
+
+void kbn_internal_phase_release(KbnPhased *ph, hipStream_t s) {
+    if (ph->ws) kbn_internal_free(ph->p, ph->ws, s);
+    ph->ws = nullptr;
 }
 
 // Grid workspace of kbn_forward_static: one file-scope array per GPU, for
@@ -932,6 +1120,7 @@ int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream_) {
     if (M < 0 || M > (2147483647LL >> p->D))
         return fail(KBN_ERR_INVALID_ARG, "M out of range (0 .. (2^31 - 1) / 2^D)");
     if (M > 0 && !omega) return fail(KBN_ERR_INVALID_ARG, "null omega");
+    ++p->epoch;
     const PointSizes z = point_sizes(p, M);
     if (M > p->Mcap || z.counts > p->counts_cap) {
         // stream-ordered: work already queued may still read the old buffers

@@ -102,19 +102,31 @@ def _assert_equal(outs, refs, what):
             assert torch.equal(o[k], r[k]), f"{what}: instance {i} output {k} differs"
 
 
-@pytest.mark.parametrize("nstreams", [1, 4])
-def test_batch_equals_single_calls(nstreams, dev):
+@pytest.mark.parametrize("nstreams,fuse", [(1, False), (4, False), (1, True), (4, True)])
+def test_batch_equals_single_calls(nstreams, fuse, dev):
     from paper_2111_02912_amd import batch as KB
-    _say(f"batch eager + graph, nstreams={nstreams}")
+    _say(f"batch eager + graph, nstreams={nstreams}, fused={fuse}")
     items = _instances(dev, SMALL, 5000)
     refs = [_single_calls(it) for it in items]
     tasks, outs = _all_op_tasks(items, dev)
-    b = KB.KbnBatch(tasks, nstreams=nstreams)
+    b = KB.KbnBatch(tasks, nstreams=nstreams, fuse=fuse)
     b.run()
     _assert_equal(outs, refs, "eager batch")
     for o in outs:
         for t in o.values():
             t.fill_(float("nan"))
+    if fuse:
+        # fused batches run eagerly: a second run rewrites every output, and
+        # capture is refused on the host (the captured fused issue ended the
+        # process in the graph runtime, so it stays switched off)
+        b.run()
+        _assert_equal(outs, refs, "second eager run")
+        from paper_2111_02912_amd._lib import KbnError, KBN_ERR_UNSUPPORTED
+        with pytest.raises(KbnError) as e:
+            b.capture()
+        assert e.value.code == KBN_ERR_UNSUPPORTED
+        b.close()
+        return
     b.capture()
     _assert_equal(outs, refs, "capture pass")
     for rep in range(3):
@@ -133,6 +145,38 @@ def test_batch_equals_single_calls(nstreams, dev):
         x_ex = ndft.sense_adjoint(inst["omega"], _np(it["k"]), inst["N"], s)
         assert ndft.rel_l2(_np(r["y"]), y_ex) < TOL_NUFFT
         assert ndft.rel_l2(_np(r["xa"]), x_ex) < TOL_NUFFT
+
+
+def test_fused_batch_follows_new_points(dev):
+    """A fused batch rebuilds its phases when a plan's points change (here
+    with a different M) and still equals the single calls; on = 0 returns
+    to per-task issue with the same results."""
+    from paper_2111_02912_amd import _lib
+    from paper_2111_02912_amd import batch as KB
+    _say("fused batch after set_points")
+    items = _instances(dev, dict(SMALL, n2d=3, shape3d=None), 5200)
+    tasks, outs = _all_op_tasks(items, dev)
+    b = KB.KbnBatch(tasks, nstreams=2, fuse=True)
+    b.run()
+    _assert_equal(outs, [_single_calls(it) for it in items], "fused, first points")
+    held = items[0]["plan"].info()["device_bytes"]
+    # new trajectory on plan 0 with more points: same output buffers cannot
+    # hold them, so keep M and move the points instead
+    it = items[0]
+    om = W.uniform_random(it["inst"]["omega"].shape[0], len(it["inst"]["N"]), seed=5299)
+    it["plan"].set_points(_f(om, dev))
+    b.run()
+    _assert_equal(outs, [_single_calls(it) for it in items], "fused, new points")
+    assert items[0]["plan"].info()["device_bytes"] == held
+    check = _lib.check
+    check(_lib.lib().kbn_batch_fuse(b._h, 0), "kbn_batch_fuse")
+    for o in outs:
+        for t in o.values():
+            t.fill_(float("nan"))
+    b.run()
+    _assert_equal(outs, [_single_calls(it) for it in items], "unfused again")
+    assert items[0]["plan"].info()["device_bytes"] < held
+    b.close()
 
 
 def test_captured_plan_is_locked(dev):
@@ -173,6 +217,22 @@ def test_multi_instance_shapes_sampled(dev):
     b.capture()
     b.launch()
     torch.cuda.synchronize()
+    # the fused batch (one interpolation launch per phase and kernel shape,
+    # run eagerly) gives the same bits as the per-task graph
+    fused_outs = [tuple(torch.full_like(t, float("nan")) for t in o) for o in outs]
+    ftasks = []
+    for it, (y, xa, dw) in zip(items, fused_outs):
+        C = it["inst"]["coils"]
+        ftasks += [KB.Task(it["plan"], KB.FORWARD, 1, C, it["x"], y, it["smaps"]),
+                   KB.Task(it["plan"], KB.JAC_OMEGA_FWD, 1, C, it["x"], dw, it["smaps"], g=it["k"]),
+                   KB.Task(it["plan"], KB.ADJOINT, 1, C, it["k"], xa, it["smaps"])]
+    fb = KB.KbnBatch(ftasks, fuse=True)
+    fb.run()
+    torch.cuda.synchronize()
+    for i, (o, f) in enumerate(zip(outs, fused_outs)):
+        for a, c, name in zip(o, f, ("y", "xa", "domega")):
+            assert torch.equal(a, c), f"fused bundle: instance {i} {name} differs"
+    fb.close()
     g = W.rng(6100)
     for i in (0, 5, len(items) - 1):
         it = items[i]
