@@ -295,6 +295,10 @@ int issue_fused(kbn_batch b, hipStream_t from) {
         hipStream_t s = g.kind == 2 ? b->sstream : b->gstream;
         if (g.kind <= 1)
             for (int ti : g.members) KBN_BHIP(hipStreamWaitEvent(s, b->pre_done[ti], 0), "hipStreamWaitEvent");
+        for (int ti : g.members) {
+            if (rc == KBN_OK) rc = kbn_internal_points_wait(b->tasks[ti].plan, s);
+        }
+        if (rc != KBN_OK) break;
         rc = launch_group(g, s);
         if (rc == KBN_OK && hipEventRecord(g.done, s) != hipSuccess)
             rc = kbn_internal_fail(KBN_ERR_HIP, "hipEventRecord");
@@ -428,6 +432,9 @@ int kbn_batch_capture(kbn_batch b, void *stream) {
     int rc = issue(b, s);
     if (rc != KBN_OK) return rc;
     KBN_BHIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    // the eager pass waited for every plan's index pass: note it, so that the
+    // captured calls need not wait on events from outside the capture
+    for (kbn_plan p : b->plans) kbn_internal_points_settle(p);
     KBN_BHIP(hipStreamBeginCapture(b->origin, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     rc = issue(b, b->origin);
     hipGraph_t g = nullptr;

@@ -87,9 +87,10 @@ int64_t kbn_points_counts_size(int64_t M, int ntiles, int ntiles_own);
 // index pass)
 int64_t kbn_points_owner_base(int64_t M, int ntiles);
 
+// omega_read (may be null): recorded on s once omega has been read
 hipError_t kbn_launch_points(int D, int64_t M, const float *omega, const double *scale,
                              const int *K, const int *T, const int *nt, int ntiles, int ntiles_own,
-                             int sub, const KbnPointsBufs &b, hipStream_t s);
+                             int sub, const KbnPointsBufs &b, hipStream_t s, hipEvent_t omega_read);
 
 // Owner-tile lists for the spread, built from the tile-sorted samples:
 // entry counts, offsets ooff[t] .. ooff[t+1], the tiles hottest first, the
@@ -272,6 +273,10 @@ int kbn_internal_fail(int code, const char *msg);    // sets the thread's last e
 // estimated bytes moved by one call (jac: D channels per coil; type1: adjoint type)
 double kbn_internal_cost(kbn_plan p, int B, int C, int jac, int type1);
 uint64_t kbn_internal_epoch(kbn_plan p);  // changes with every kbn_set_points
+// order `s` after the plan's last index pass (which runs on its own stream)
+int kbn_internal_points_wait(kbn_plan p, hipStream_t s);
+// note a finished index pass (before a capture, whose waits cannot name it)
+void kbn_internal_points_settle(kbn_plan p);
 // device memory through the plan's allocator, counted in its footprint
 int kbn_internal_alloc(kbn_plan p, void **ptr, int64_t bytes, hipStream_t s);
 void kbn_internal_free(kbn_plan p, void *ptr, hipStream_t s);

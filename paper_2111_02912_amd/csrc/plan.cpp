@@ -186,6 +186,13 @@ struct kbn_plan_s {
     std::vector<float2> h_tw[KBN_MAX_D];
     std::vector<float> h_coef;
     hipEvent_t upload_done = nullptr;
+    // The index pass runs on a stream of the plan's own, beside the caller's
+    // stream, so that a forward call's FFT passes (which do not read the
+    // points) overlap it; every read of the point buffers first makes its
+    // stream wait for points_ready.
+    hipStream_t istream = nullptr;
+    hipEvent_t points_in = nullptr, points_ready = nullptr, omega_read = nullptr;
+    bool points_pending = false;
     int D = 0;
     int N[KBN_MAX_D] = {1, 1, 1};
     int K[KBN_MAX_D] = {1, 1, 1};
@@ -348,7 +355,10 @@ void free_points(kbn_plan p, hipStream_t s) {
     p->counts_cap = 0;
 }
 
+int points_wait(kbn_plan p, hipStream_t stream);
+
 void free_plan(kbn_plan p, hipStream_t s) {
+    (void)points_wait(p, s);  // the frees below come after the last index pass
     for (auto &t : p->pending) {
         (void)hipEventDestroy(t.e0);
         (void)hipEventDestroy(t.e1);
@@ -370,11 +380,36 @@ void free_plan(kbn_plan p, hipStream_t s) {
     dev_free(p, p->ws, s);
     dev_free(p, p->fws, s);
     // the host constants may be freed only once their uploads have run
+    if (p->points_in) (void)hipEventDestroy(p->points_in);
+    if (p->omega_read) (void)hipEventDestroy(p->omega_read);
+    if (p->points_ready) (void)hipEventDestroy(p->points_ready);
+    if (p->istream) (void)hipStreamDestroy(p->istream);
     if (p->upload_done) {
         if (hipEventQuery(p->upload_done) != hipSuccess) (void)hipEventSynchronize(p->upload_done);
         (void)hipEventDestroy(p->upload_done);
     }
     delete p;
+}
+
+// Orders `stream` after the plan's last index pass.  Under graph capture
+// the wait would be on an event recorded outside the capture, so a capture
+// requires the index pass to be known finished (kbn_check_error, or the
+// batch capture's own eager pass); captured plans refuse new points.
+int points_wait(kbn_plan p, hipStream_t stream) {
+    if (!p->points_pending) return KBN_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return fail(KBN_ERR_HIP, "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone) {
+        if (hipEventQuery(p->points_ready) == hipSuccess) {
+            p->points_pending = false;
+            return KBN_OK;
+        }
+        return fail(KBN_ERR_UNSUPPORTED,
+                    "capture while the index pass of kbn_set_points may still run: call kbn_check_error first");
+    }
+    if (hipStreamWaitEvent(stream, p->points_ready, 0) != hipSuccess)
+        return fail(KBN_ERR_HIP, "hipStreamWaitEvent (points)");
+    return KBN_OK;
 }
 
 int ensure_ws(kbn_plan p, int64_t bytes, hipStream_t stream) {
@@ -588,6 +623,7 @@ int run_type2(kbn_plan p, int B, int C, int nw, int weighted, const float2 *x,
         const int64_t nch = nb * ncc * nw;
         float2 *grid = nullptr;
         int rc = t2_passes(p, nw, weighted, x, smaps, b0, c0, nb, ncc, bufA, bufB, &grid, stream);
+        if (rc == KBN_OK) rc = points_wait(p, stream);  // the FFT passes overlap the index pass
         if (rc != KBN_OK) return rc;
         const KbnGatherArgs ga = t2_gather_args(p, nch, ncc, nw, mode, grid, (b0 * C + c0) * p->M, y, v, dom, part,
                                                 (accumulate || b0 > 0 || c0 > 0) ? 1 : 0);
@@ -701,6 +737,7 @@ int run_type1(kbn_plan p, int B, int C, const float2 *y, const float2 *smaps, fl
     const Chunks ck = split_chunks(B, C, per_coil, p->max_ws);
     const int64_t units = ck.bc * ck.cc;
     int rc = ensure_ws(p, ws_type1(p, p->M, B, C), stream);
+    if (rc == KBN_OK) rc = points_wait(p, stream);
     if (rc != KBN_OK) return rc;
     float2 *bufA = p->ws;
     float2 *bufB = p->ws + units * gsz;
@@ -760,6 +797,10 @@ double kbn_internal_cost(kbn_plan p, int B, int C, int jac, int type1) {
 }
 
 uint64_t kbn_internal_epoch(kbn_plan p) { return p->epoch; }
+int kbn_internal_points_wait(kbn_plan p, hipStream_t s) { return points_wait(p, s); }
+void kbn_internal_points_settle(kbn_plan p) {
+    if (p->points_pending && hipEventQuery(p->points_ready) == hipSuccess) p->points_pending = false;
+}
 
 int kbn_internal_alloc(kbn_plan p, void **ptr, int64_t bytes, hipStream_t s) {
     return dev_alloc(p, (char **)ptr, bytes, s);
@@ -1037,6 +1078,25 @@ int64_t const_bytes(const kbn_plan p) {
     return b;
 }
 
+// The index pass's launches on the plan's stream (omega_read is recorded
+// after the kernel that reads omega, or at once if the pass stops before).
+int index_pass(kbn_plan p, int64_t M, const float *omega, const KbnPointsBufs &b) {
+    hipStream_t stream = p->istream;
+    const hipError_t e0 = hipEventRecord(p->omega_read, stream);  // replaced below once omega is read
+    if (e0 != hipSuccess) return fail(KBN_ERR_HIP, "index stream order");
+    KBN_LAUNCH(KBN_CLASS_INDEX,
+               kbn_launch_points(p->D, M, omega, p->scale, p->K, p->T, p->nt, p->ntiles, p->ntiles_own, p->sub, b,
+                                 stream, p->omega_read),
+               "index pass");
+    KBN_LAUNCH(KBN_CLASS_INDEX,
+               kbn_launch_owner_lists(p->geom(), M, p->cell, p->frac, p->toff, p->order,
+                                      p->counts + kbn_points_owner_base(M, p->ntiles), p->ooff, p->otile_order,
+                                      KBN_SPREAD_SEG, p->smax, p->swork, p->scomb, p->scounts, p->rec_p, p->rec_q,
+                                      p->rec_l, p->rec_f, stream),
+               "spread lists");
+    return KBN_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1101,6 +1161,11 @@ int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts
     if (rc == KBN_OK && (hipEventCreateWithFlags(&p->upload_done, hipEventDisableTiming) != hipSuccess ||
                          hipEventRecord(p->upload_done, stream) != hipSuccess))
         rc = fail(KBN_ERR_HIP, "upload event");
+    if (rc == KBN_OK && (hipStreamCreateWithFlags(&p->istream, hipStreamNonBlocking) != hipSuccess ||
+                         hipEventCreateWithFlags(&p->points_in, hipEventDisableTiming) != hipSuccess ||
+                         hipEventCreateWithFlags(&p->points_ready, hipEventDisableTiming) != hipSuccess ||
+                         hipEventCreateWithFlags(&p->omega_read, hipEventDisableTiming) != hipSuccess))
+        rc = fail(KBN_ERR_HIP, "index stream");
     if (rc != KBN_OK) {
         const std::string msg = g_err;
         free_plan(p, stream);
@@ -1120,6 +1185,12 @@ int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream_) {
     if (M < 0 || M > (2147483647LL >> p->D))
         return fail(KBN_ERR_INVALID_ARG, "M out of range (0 .. (2^31 - 1) / 2^D)");
     if (M > 0 && !omega) return fail(KBN_ERR_INVALID_ARG, "null omega");
+    {
+        // the previous index pass may still run: the frees, the new buffers
+        // and the new pass come after it
+        const int rc = points_wait(p, stream);
+        if (rc != KBN_OK) return rc;
+    }
     ++p->epoch;
     const PointSizes z = point_sizes(p, M);
     if (M > p->Mcap || z.counts > p->counts_cap) {
@@ -1162,16 +1233,22 @@ int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream_) {
     b.flag = p->flag;
     b.subs = p->subs;
     b.nsub = p->nsub;
-    KBN_LAUNCH(KBN_CLASS_INDEX,
-               kbn_launch_points(p->D, M, omega, p->scale, p->K, p->T, p->nt, p->ntiles, p->ntiles_own, p->sub,
-                                 b, stream),
-               "index pass");
-    KBN_LAUNCH(KBN_CLASS_INDEX,
-               kbn_launch_owner_lists(p->geom(), M, p->cell, p->frac, p->toff, p->order,
-                                      p->counts + kbn_points_owner_base(M, p->ntiles), p->ooff,
-                                      p->otile_order, KBN_SPREAD_SEG, p->smax, p->swork, p->scomb, p->scounts,
-                                      p->rec_p, p->rec_q, p->rec_l, p->rec_f, stream),
-               "spread lists");
+    // the index pass on the plan's stream, after everything queued on the
+    // caller's stream (omega, the buffers)
+    if (hipEventRecord(p->points_in, stream) != hipSuccess || hipStreamWaitEvent(p->istream, p->points_in, 0) != hipSuccess)
+        return fail(KBN_ERR_HIP, "index stream order");
+    p->points_pending = true;
+    const int rc = index_pass(p, M, omega, b);
+    // whatever was issued is waited for by later reads of the points, and the
+    // caller's later work may overwrite omega once the first index kernel has
+    // read it; the rest of the pass runs beside that work
+    if (hipEventRecord(p->points_ready, p->istream) != hipSuccess ||
+        hipStreamWaitEvent(stream, p->omega_read, 0) != hipSuccess)
+        return fail(KBN_ERR_HIP, "index stream order");
+    if (rc != KBN_OK) {
+        p->M = -1;
+        return rc;
+    }
     p->M = M;
     return KBN_OK;
 }
@@ -1526,6 +1603,8 @@ int kbn_get_points(kbn_plan p, int *order, int *cell, float *frac, int *offsets,
     if (!p) return fail(KBN_ERR_INVALID_ARG, "null plan");
     if (p->M < 0) return fail(KBN_ERR_NO_POINTS, "kbn_set_points has not been called");
     const int64_t M = p->M;
+    const int rcw = points_wait(p, stream);
+    if (rcw != KBN_OK) return rcw;
     if (M > 0) {
         if (order) KBN_HIP(hipMemcpyAsync(order, p->order, sizeof(int) * M, hipMemcpyDeviceToDevice, stream));
         if (cell)
@@ -1542,6 +1621,10 @@ int kbn_get_points(kbn_plan p, int *order, int *cell, float *frac, int *offsets,
 int kbn_check_error(kbn_plan p, void *stream) {
     if (!p) return fail(KBN_ERR_INVALID_ARG, "null plan");
     KBN_HIP(hipStreamSynchronize((hipStream_t)stream));
+    if (p->points_pending) {
+        KBN_HIP(hipEventSynchronize(p->points_ready));
+        p->points_pending = false;
+    }
     int h = 0;
     KBN_HIP(hipMemcpy(&h, p->flag, sizeof(int), hipMemcpyDeviceToHost));
     if (h) {

@@ -834,7 +834,7 @@ int64_t kbn_points_counts_size(int64_t M, int ntiles, int ntiles_own) {
 
 hipError_t kbn_launch_points(int D, int64_t M, const float *omega, const double *scale,
                              const int *K, const int *T, const int *nt, int ntiles, int ntiles_own,
-                             int sub, const KbnPointsBufs &b, hipStream_t s) {
+                             int sub, const KbnPointsBufs &b, hipStream_t s, hipEvent_t omega_read) {
     const int nbins = ntiles + 1;
     int *ocount = b.counts + kbn_points_owner_base(M, ntiles);
     {
@@ -848,6 +848,10 @@ hipError_t kbn_launch_points(int D, int64_t M, const float *omega, const double 
             D, M, chunk, nchunks, nbins, omega, scale[0], D > 1 ? scale[1] : 0.0, D > 2 ? scale[2] : 0.0,
             K[0], D > 1 ? K[1] : 1, D > 2 ? K[2] : 1, T[0], D > 1 ? T[1] : 1, D > 2 ? T[2] : 1,
             D > 1 ? nt[1] : 1, D > 2 ? nt[2] : 1, ntiles, b.cell_tmp, b.frac_tmp, b.tile, b.flag, b.counts);
+    if (omega_read) {  // omega is not read after this kernel
+        const hipError_t e = hipEventRecord(omega_read, s);
+        if (e != hipSuccess) return e;
+    }
     const int64_t S = (int64_t)nbins * nchunks;
     if (S <= KBN_SCAN_SMALL) {
         k_scan_small<<<dim3(1), dim3(1024), 0, s>>>((int)S, std::max(nchunks, 1), nbins, sub, b.counts, b.toff,
