@@ -152,8 +152,16 @@ int kbn_plan_footprint(int D, const int64_t *N, const kbn_opts *opts, int64_t M,
  * Computes, per point and axis, u = omega K_d / (2 pi) in FP64, the grid
  * cell floor(u) mod K_d and the in-cell fraction (float32), the tile id, and
  * a stable order of the points by tile (the appendix's offsets k_m and J
- * taps k_m + j are derived from these).  omega is read during the call's
- * stream work only; the caller may reuse it afterwards.  M = 0 is allowed.
+ * taps k_m + j are derived from these).  M = 0 is allowed.
+ *
+ * The pass runs on a stream of the plan's own, after the work already
+ * queued on `stream`; `stream` waits only until omega has been read (the
+ * caller may then overwrite it), so a following call's FFT passes run beside
+ * the rest of the pass.  Every later read of the points (interpolation,
+ * kbn_get_points, kbn_check_error, a batch) waits for the pass on its own
+ * stream.  A call made under HIP graph capture cannot wait for it: capture
+ * calls of the plan only after kbn_check_error (kbn_batch_capture does this
+ * itself), else they return UNSUPPORTED while the pass may still run.
  *
  * A non-finite omega (or |u| >= 2^40) sets a sticky device flag reported by
  * kbn_check_error; such points give NaN in forward outputs and omega
