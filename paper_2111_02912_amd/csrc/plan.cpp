@@ -399,14 +399,9 @@ int points_wait(kbn_plan p, hipStream_t stream) {
     if (!p->points_pending) return KBN_OK;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return fail(KBN_ERR_HIP, "hipStreamIsCapturing");
-    if (cs != hipStreamCaptureStatusNone) {
-        if (hipEventQuery(p->points_ready) == hipSuccess) {
-            p->points_pending = false;
-            return KBN_OK;
-        }
+    if (cs != hipStreamCaptureStatusNone)  // (no event query either: not allowed in every capture mode)
         return fail(KBN_ERR_UNSUPPORTED,
                     "capture while the index pass of kbn_set_points may still run: call kbn_check_error first");
-    }
     if (hipStreamWaitEvent(stream, p->points_ready, 0) != hipSuccess)
         return fail(KBN_ERR_HIP, "hipStreamWaitEvent (points)");
     return KBN_OK;

@@ -107,6 +107,42 @@ def test_nonfinite_points_are_flagged(dev):
     assert p.check_error() == 0  # the flag is cleared once reported
 
 
+def test_index_pass_stream_ordering(dev):
+    """The index pass runs on the plan's own stream: omega may be overwritten
+    on the caller's stream right after kbn_set_points (the pass has read it
+    by then), a forward call issued at once waits for the pass before its
+    gather, and a second set_points that grows the point buffers waits for
+    the first pass before freeing them."""
+    _say("index pass on its own stream")
+    N = (96, 80)
+    x = _c(W.complex_normal((2,) + N, 31), dev)
+    om1 = W.uniform_random(3000, 2, seed=32)
+    om2 = W.uniform_random(9000, 2, seed=33)
+    ref = _plan(N, dev)
+    ref.set_points(_f(om1, dev))
+    y1 = ref.forward(x)
+    ref.check_error()
+    p = _plan(N, dev)
+    for _ in range(3):
+        t = _f(om1, dev)
+        p.set_points(t)
+        t.fill_(float("nan"))  # same stream, right after the call
+        y = p.forward(x)
+        assert torch.equal(y, y1)
+        assert p.check_error() == 0
+    # grow: the second pass's new buffers replace the first's while it may run
+    p.set_points(_f(om1, dev))
+    p.set_points(_f(om2, dev))
+    y2 = p.forward(x)
+    ref.set_points(_f(om2, dev))
+    assert torch.equal(y2, ref.forward(x))
+    got = p.get_points()
+    cell, frac, bad = points_ref.cells(om2, p.K)
+    tid, nt = points_ref.tiles(cell, p.K, p.tile, bad)
+    perm, off = points_ref.tile_order(tid, nt)
+    assert np.array_equal(_np(got["order"]), perm)
+
+
 def _case(N, M_kind, seed):
     D = len(N)
     if M_kind == "radial":
