@@ -193,6 +193,9 @@ struct kbn_plan_s {
     hipStream_t istream = nullptr;
     hipEvent_t points_in = nullptr, points_ready = nullptr, omega_read = nullptr;
     bool points_pending = false;
+    uint64_t points_gen = 0;               // index passes issued
+    hipStream_t waited_stream = nullptr;   // the last stream ordered after pass waited_gen
+    uint64_t waited_gen = 0;
     int D = 0;
     int N[KBN_MAX_D] = {1, 1, 1};
     int K[KBN_MAX_D] = {1, 1, 1};
@@ -397,6 +400,9 @@ void free_plan(kbn_plan p, hipStream_t s) {
 // batch capture's own eager pass); captured plans refuse new points.
 int points_wait(kbn_plan p, hipStream_t stream) {
     if (!p->points_pending) return KBN_OK;
+    // a stream already ordered after this pass needs no second wait (the
+    // launch-bound small problems issue dozens of calls per pass)
+    if (p->waited_gen == p->points_gen && p->waited_stream == stream) return KBN_OK;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return fail(KBN_ERR_HIP, "hipStreamIsCapturing");
     if (cs != hipStreamCaptureStatusNone)  // (no event query either: not allowed in every capture mode)
@@ -404,6 +410,8 @@ int points_wait(kbn_plan p, hipStream_t stream) {
                     "capture while the index pass of kbn_set_points may still run: call kbn_check_error first");
     if (hipStreamWaitEvent(stream, p->points_ready, 0) != hipSuccess)
         return fail(KBN_ERR_HIP, "hipStreamWaitEvent (points)");
+    p->waited_stream = stream;
+    p->waited_gen = p->points_gen;
     return KBN_OK;
 }
 
@@ -1233,6 +1241,7 @@ int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream_) {
     if (hipEventRecord(p->points_in, stream) != hipSuccess || hipStreamWaitEvent(p->istream, p->points_in, 0) != hipSuccess)
         return fail(KBN_ERR_HIP, "index stream order");
     p->points_pending = true;
+    ++p->points_gen;
     const int rc = index_pass(p, M, omega, b);
     // whatever was issued is waited for by later reads of the points, and the
     // caller's later work may overwrite omega once the first index kernel has
