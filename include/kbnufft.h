@@ -154,8 +154,9 @@ int kbn_plan_footprint(int D, const int64_t *N, const kbn_opts *opts, int64_t M,
  * a stable order of the points by tile (the appendix's offsets k_m and J
  * taps k_m + j are derived from these).  M = 0 is allowed.
  *
- * The pass runs on a stream of the plan's own, after the work already
- * queued on `stream`; `stream` waits only until omega has been read (the
+ * From 8192 points the pass runs on a stream of the plan's own (smaller
+ * passes run on `stream`), after the work already queued on `stream`;
+ * `stream` waits only until omega has been read (the
  * caller may then overwrite it), so a following call's FFT passes run beside
  * the rest of the pass.  Every later read of the points (interpolation,
  * kbn_get_points, kbn_check_error, a batch) waits for the pass on its own

@@ -15,6 +15,7 @@
 #define KBN_MAX_K 1024      // largest oversampled grid edge handled by the LDS FFT
 #define KBN_MAX_TILES 40959 // tile histograms live in LDS (ntiles + 1 counters, at most 160 KiB)
 #define KBN_BLOCK 256
+#define KBN_INDEX_STREAM_MIN 8192  // points from which the index pass runs beside the caller's stream
 #define KBN_SUB 256        // sorted points per gather subproblem (one per thread)
 #define KBN_SPREAD_EB 64   // list entries staged per spread batch
 #define KBN_SPREAD_SEG 128  // list entries per spread work item (doubled if slots run out)

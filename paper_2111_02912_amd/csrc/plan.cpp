@@ -1083,13 +1083,14 @@ int64_t const_bytes(const kbn_plan p) {
 
 // The index pass's launches on the plan's stream (omega_read is recorded
 // after the kernel that reads omega, or at once if the pass stops before).
-int index_pass(kbn_plan p, int64_t M, const float *omega, const KbnPointsBufs &b) {
-    hipStream_t stream = p->istream;
-    const hipError_t e0 = hipEventRecord(p->omega_read, stream);  // replaced below once omega is read
-    if (e0 != hipSuccess) return fail(KBN_ERR_HIP, "index stream order");
+int index_pass(kbn_plan p, int64_t M, const float *omega, const KbnPointsBufs &b, hipStream_t stream) {
+    if (stream == p->istream) {
+        const hipError_t e0 = hipEventRecord(p->omega_read, stream);  // replaced below once omega is read
+        if (e0 != hipSuccess) return fail(KBN_ERR_HIP, "index stream order");
+    }
     KBN_LAUNCH(KBN_CLASS_INDEX,
                kbn_launch_points(p->D, M, omega, p->scale, p->K, p->T, p->nt, p->ntiles, p->ntiles_own, p->sub, b,
-                                 stream, p->omega_read),
+                                 stream, stream == p->istream ? p->omega_read : nullptr),
                "index pass");
     KBN_LAUNCH(KBN_CLASS_INDEX,
                kbn_launch_owner_lists(p->geom(), M, p->cell, p->frac, p->toff, p->order,
@@ -1236,19 +1237,29 @@ int kbn_set_points(kbn_plan p, int64_t M, const float *omega, void *stream_) {
     b.flag = p->flag;
     b.subs = p->subs;
     b.nsub = p->nsub;
-    // the index pass on the plan's stream, after everything queued on the
-    // caller's stream (omega, the buffers)
-    if (hipEventRecord(p->points_in, stream) != hipSuccess || hipStreamWaitEvent(p->istream, p->points_in, 0) != hipSuccess)
-        return fail(KBN_ERR_HIP, "index stream order");
-    p->points_pending = true;
-    ++p->points_gen;
-    const int rc = index_pass(p, M, omega, b);
-    // whatever was issued is waited for by later reads of the points, and the
-    // caller's later work may overwrite omega once the first index kernel has
-    // read it; the rest of the pass runs beside that work
-    if (hipEventRecord(p->points_ready, p->istream) != hipSuccess ||
-        hipStreamWaitEvent(stream, p->omega_read, 0) != hipSuccess)
-        return fail(KBN_ERR_HIP, "index stream order");
+    int rc;
+    if (M < KBN_INDEX_STREAM_MIN) {
+        // few points: the pass is a handful of short launches, cheaper on the
+        // caller's stream than behind a cross-stream wait (which the
+        // points_wait above already made any earlier pass's work precede)
+        rc = index_pass(p, M, omega, b, stream);
+        p->points_pending = false;
+    } else {
+        // the index pass on the plan's stream, after everything queued on the
+        // caller's stream (omega, the buffers)
+        if (hipEventRecord(p->points_in, stream) != hipSuccess ||
+            hipStreamWaitEvent(p->istream, p->points_in, 0) != hipSuccess)
+            return fail(KBN_ERR_HIP, "index stream order");
+        p->points_pending = true;
+        ++p->points_gen;
+        rc = index_pass(p, M, omega, b, p->istream);
+        // whatever was issued is waited for by later reads of the points, and
+        // the caller's later work may overwrite omega once the first index
+        // kernel has read it; the rest of the pass runs beside that work
+        if (hipEventRecord(p->points_ready, p->istream) != hipSuccess ||
+            hipStreamWaitEvent(stream, p->omega_read, 0) != hipSuccess)
+            return fail(KBN_ERR_HIP, "index stream order");
+    }
     if (rc != KBN_OK) {
         p->M = -1;
         return rc;

@@ -116,8 +116,9 @@ def test_index_pass_stream_ordering(dev):
     _say("index pass on its own stream")
     N = (96, 80)
     x = _c(W.complex_normal((2,) + N, 31), dev)
-    om1 = W.uniform_random(3000, 2, seed=32)
-    om2 = W.uniform_random(9000, 2, seed=33)
+    # above the size from which the pass runs on the plan's own stream
+    om1 = W.uniform_random(12000, 2, seed=32)
+    om2 = W.uniform_random(30000, 2, seed=33)
     ref = _plan(N, dev)
     ref.set_points(_f(om1, dev))
     y1 = ref.forward(x)
@@ -132,6 +133,11 @@ def test_index_pass_stream_ordering(dev):
         assert p.check_error() == 0
     # grow: the second pass's new buffers replace the first's while it may run
     p.set_points(_f(om1, dev))
+    p.set_points(_f(om2, dev))
+    # a small set on the caller's stream right after a large one on the plan's
+    p.set_points(_f(om2[:500], dev))
+    ref.set_points(_f(om2[:500], dev))
+    assert torch.equal(p.forward(x), ref.forward(x))
     p.set_points(_f(om2, dev))
     y2 = p.forward(x)
     ref.set_points(_f(om2, dev))
