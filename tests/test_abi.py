@@ -60,6 +60,9 @@ def test_error_strings_without_gpu():
     assert L.kbn_plan_create(ctypes.byref(h), 2, zero, None, None, None) == _lib.KBN_ERR_INVALID_ARG
     assert L.kbn_set_points(None, 1, None, None) == _lib.KBN_ERR_INVALID_ARG
     assert L.kbn_forward(None, 1, 1, None, None, None, None) == _lib.KBN_ERR_INVALID_ARG
+    assert L.kbn_batch_fuse(None, 1) == _lib.KBN_ERR_INVALID_ARG
+    assert L.kbn_batch_capture(None, None) == _lib.KBN_ERR_INVALID_ARG
+    assert L.kbn_check_error(None, None) == _lib.KBN_ERR_INVALID_ARG
 
 
 
