@@ -299,6 +299,15 @@ int kbn_check_error(kbn_plan p, void *stream);
  * Errors: INVALID_ARG (null plan, bad class), HIP.
  */
 int kbn_timing(kbn_plan p, int enable);
+
+/*
+ * Restrict the timing events to the kernel classes whose bit is set in
+ * `mask` (bit c for class c; all classes after kbn_plan_create), so that a
+ * measurement brackets only the kernels it reports and the events of the
+ * others do not add to the time being measured.  Takes effect for later
+ * launches.  Errors: INVALID_ARG (null plan).
+ */
+int kbn_timing_select(kbn_plan p, unsigned int mask);
 int kbn_timing_read(kbn_plan p, int cls, int64_t *launches, double *total_ms);
 const char *kbn_timing_name(int cls);
 

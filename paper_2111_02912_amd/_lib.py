@@ -35,7 +35,7 @@ EXPORTS = (
     "kbn_adjoint",
     "kbn_jac_omega_fwd", "kbn_jac_omega_adj", "kbn_jac_x", "kbn_plan_info",
     "kbn_get_points", "kbn_check_error", "kbn_plan_destroy", "kbn_strerror",
-    "kbn_last_error", "kbn_timing", "kbn_timing_read", "kbn_timing_name",
+    "kbn_last_error", "kbn_timing", "kbn_timing_select", "kbn_timing_read", "kbn_timing_name",
     "kbn_batch_create", "kbn_batch_run", "kbn_batch_capture", "kbn_batch_fuse", "kbn_batch_launch",
     "kbn_batch_destroy", "kbn_cg_work_bytes", "kbn_cg_begin", "kbn_cg_step",
     "kbn_cg_begin_image", "kbn_field_forward", "kbn_field_adjoint", "kbn_field_jac_omega_fwd",
@@ -123,6 +123,7 @@ def lib():
     L.kbn_last_error.argtypes = []
     L.kbn_last_error.restype = ctypes.c_char_p
     L.kbn_timing.argtypes = [vp, ci]
+    L.kbn_timing_select.argtypes = [vp, ctypes.c_uint]
     L.kbn_timing_read.argtypes = [vp, ci, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
     L.kbn_timing_name.argtypes = [ci]
     L.kbn_timing_name.restype = ctypes.c_char_p

@@ -56,7 +56,8 @@ const char *const kClassNames[KBN_NCLASS] = {"index",       "fft_first",    "fft
 #define KBN_LAUNCH(cls, expr, name)                                     \
     do {                                                                \
         hipEvent_t e0_ = nullptr;                                       \
-        if (p->timing) e0_ = timing_mark(p, stream);                    \
+        if (p->timing && ((p->timing_mask >> (cls)) & 1u))              \
+            e0_ = timing_mark(p, stream);                               \
         int rc_ = launched((expr), name, stream);                       \
         if (p->timing && e0_) {                                         \
             hipEvent_t e1_ = timing_mark(p, stream);                    \
@@ -248,6 +249,7 @@ struct kbn_plan_s {
         hipEvent_t e0, e1;
     };
     bool timing = false;
+    unsigned int timing_mask = ~0u;  // kernel classes that record events
     std::vector<Timed> pending;
     std::vector<hipEvent_t> pool;
     double t_ms[KBN_NCLASS] = {};
@@ -1654,6 +1656,12 @@ int kbn_plan_destroy(kbn_plan p, void *stream) {
     if (p->graph_refs > 0)
         return fail(KBN_ERR_INVALID_ARG, "plan is held by a captured batch; destroy the batch first");
     free_plan(p, (hipStream_t)stream);
+    return KBN_OK;
+}
+
+int kbn_timing_select(kbn_plan p, unsigned int mask) {
+    if (!p) return fail(KBN_ERR_INVALID_ARG, "null plan");
+    p->timing_mask = mask;
     return KBN_OK;
 }
 

@@ -388,9 +388,30 @@ class KbNufft:
                                         _stream(self.device)), "kbn_get_points")
         return {"order": order[:M], "cell": cell[:, :M], "frac": frac[:, :M], "offsets": off}
 
-    def timing(self, enable: bool):
-        """Start (clearing counters) or stop per-kernel event timing."""
+    def timing(self, enable: bool, classes=None):
+        """Start (clearing counters) or stop per-kernel event timing;
+        `classes` (names, default all) limits the events to those kernel
+        classes."""
+        if enable:
+            mask = 0xFFFFFFFF
+            if classes is not None:
+                names = self.timing_classes()
+                mask = 0
+                for c in classes:
+                    mask |= 1 << names.index(c)
+            check(_lib.lib().kbn_timing_select(self._h, mask), "kbn_timing_select")
         check(_lib.lib().kbn_timing(self._h, int(bool(enable))), "kbn_timing")
+
+    @staticmethod
+    def timing_classes():
+        """Kernel class names in class order."""
+        L = _lib.lib()
+        out = []
+        while True:
+            name = L.kbn_timing_name(len(out))
+            if name is None:
+                return out
+            out.append(name.decode())
 
     def timing_read(self) -> dict:
         """{class name: (launches, total ms)} of the timed launches so far."""

@@ -63,6 +63,7 @@ def test_error_strings_without_gpu():
     assert L.kbn_batch_fuse(None, 1) == _lib.KBN_ERR_INVALID_ARG
     assert L.kbn_batch_capture(None, None) == _lib.KBN_ERR_INVALID_ARG
     assert L.kbn_check_error(None, None) == _lib.KBN_ERR_INVALID_ARG
+    assert L.kbn_timing_select(None, 1) == _lib.KBN_ERR_INVALID_ARG
 
 
 

@@ -149,6 +149,27 @@ def test_index_pass_stream_ordering(dev):
     assert np.array_equal(_np(got["order"]), perm)
 
 
+def test_timing_selected_classes(dev):
+    """kbn_timing_select limits the timing events to the chosen classes."""
+    _say("timing of selected kernel classes")
+    N = (64, 48)
+    p = _plan(N, dev)
+    p.set_points(_f(W.uniform_random(3000, 2, seed=41), dev))
+    x = _c(W.complex_normal((2,) + N, 42), dev)
+    p.timing(True, classes=["fft_mid_fwd", "gather"])
+    y = p.forward(x)
+    p.adjoint(y)
+    p.timing(False)
+    got = {k: n for k, (n, ms) in p.timing_read().items() if n}
+    assert set(got) == {"fft_mid_fwd", "gather"}
+    p.timing(True)
+    p.forward(x)
+    p.adjoint(y)
+    p.timing(False)
+    got = {k for k, (n, ms) in p.timing_read().items() if n}
+    assert {"fft_first", "fft_mid_fwd", "gather", "spread", "fft_mid_inv", "fft_last_adj"} <= got
+
+
 def _case(N, M_kind, seed):
     D = len(N)
     if M_kind == "radial":
