@@ -400,7 +400,9 @@ __global__ void __launch_bounds__(NT) k_rows_first(KbnFirstPassArgs a, const flo
 }
 
 // ---- last inverse pass along the last axis (crop, scaling, coil sum) -------
-template <int L, int E, int NT>
+// ONE: a single coil (C = 1, with or without a map): each value is weighted
+// and stored as the last stage produces it, with no coil accumulators.
+template <int L, int E, int NT, bool ONE>
 __global__ void __launch_bounds__(NT) k_rows_last_adj(KbnLastAdjArgs a, const float2 *__restrict__ tw) {
     using F = Fft<L, E, true>;
     static_assert(NT % F::TL == 0, "a workgroup holds whole lines");
@@ -429,6 +431,36 @@ __global__ void __launch_bounds__(NT) k_rows_last_adj(KbnLastAdjArgs a, const fl
         lf = f;
     }
     const float *deap_l = a.deap[a.D - 1];
+    if constexpr (ONE) {
+        const float2 *in = a.in + line * (int64_t)L;
+        float2 v[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int p = F::template in_pos<0>(u, i);
+            v[i] = line_ok ? in[p] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();  // twiddles in LDS
+        const int cm = a.cmod > 0 ? (int)(bl % a.cmod) : 0;
+        const float2 *srow = a.smaps ? a.smaps + ((int64_t)cm * a.R0 + row) * Nl : nullptr;
+        float2 *x = a.x + line * Nl;
+        auto lds_idx = [](int pos) { return pos; };
+        float2 *ldsl = lds + li * L;
+        auto sink = [&](int, int pos, float2 val) {
+            const int j = pos_to_img<L>(pos, Nl);
+            if (line_ok && j >= 0) {
+                if (srow) val = cmulc(val, srow[j]);
+                const float f = lf * deap_l[j];
+                val = make_float2(val.x * f, val.y * f);
+                if (a.accumulate) {
+                    const float2 o = x[j];
+                    val = make_float2(o.x + val.x, o.y + val.y);
+                }
+                x[j] = val;
+            }
+        };
+        Stages<F, 0>::run(v, u, twl, ldsl, lds_idx, sink);
+        return;
+    }
     float2 acc[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) acc[i] = make_float2(0.f, 0.f);
@@ -601,7 +633,10 @@ hipError_t launch_rows_last(const KbnLastAdjArgs &a, const float2 *tw, hipStream
     constexpr int NT = row_nt(L);
     constexpr int LINES = NT / (L / E);
     const dim3 grid((unsigned)((a.nlines + LINES - 1) / LINES));
-    k_rows_last_adj<L, E, NT><<<grid, dim3(NT), 0, s>>>(a, tw);
+    if (a.C == 1)
+        k_rows_last_adj<L, E, NT, true><<<grid, dim3(NT), 0, s>>>(a, tw);
+    else
+        k_rows_last_adj<L, E, NT, false><<<grid, dim3(NT), 0, s>>>(a, tw);
     return hipGetLastError();
 }
 
