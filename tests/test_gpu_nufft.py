@@ -507,6 +507,59 @@ def test_wide_channel_spread_matches_narrow_groups(N, kind, nch, dev):
     assert e_a < TOL_NUFFT
 
 
+def _clusters(D, centres, each, seed, half=0.06):
+    """Small square clusters of samples around the given centres, wrapped
+    into [-pi, pi) (clusters at +-pi straddle the grid's wrap-around)."""
+    parts = []
+    for k, c in enumerate(centres):
+        pts = np.asarray(c, np.float64) + W.uniform_random(each, D, seed=seed + k, lo=-half, hi=half)
+        parts.append((pts + np.pi) % (2 * np.pi) - np.pi)
+    return np.concatenate(parts).astype(np.float32)
+
+
+@pytest.mark.parametrize("N,each", [((135, 150), 300), ((135, 150), 2600), ((300, 140), 300), ((20, 18, 14), 200)])
+def test_sparse_support(N, each, dev):
+    """Samples in a few small clusters (most of the oversampled grid outside
+    every sample's taps): at the centre, across the +-pi wrap on every axis
+    and off-centre; K = 270 x 300 (a partial last 8-row block), 600 x 280
+    and 40 x 36 x 28.  A second point set on the same plan (other clusters,
+    the grid workspace still holding the first set's values) must give the
+    NUDFT as well.  10400 samples take the index pass on the plan's own
+    stream, 1200 and 800 on the caller's."""
+    D = len(N)
+    _say(f"sparse support N={N} clusters of {each}")
+    z = [0.0] * D
+    sets = [
+        [z, [np.pi - 0.02] * D, [-np.pi + 0.01] + [0.7] * (D - 1), [1.3] + [-np.pi + 0.005] * (D - 1)],
+        [[-2.0] + [0.4] * (D - 1), [0.9] * D, [np.pi - 0.03] + [-1.1] * (D - 1)],
+    ]
+    p = _plan(N, dev)
+    B = 2
+    x = W.complex_normal((B,) + N, 9601)
+    pix = np.sort(W.rng(9602).choice(int(np.prod(N)), 400, replace=False))
+    for si, centres in enumerate(sets):
+        om = _clusters(D, centres, each, 9610 + 10 * si)
+        M = om.shape[0]
+        g = W.complex_normal((B, 1, M), 9603 + si)
+        p.set_points(_f(om, dev))
+        xs, gs = _c(x, dev), _c(g, dev)
+        yg = _np(p.forward(xs))
+        xa = _np(p.adjoint(gs))
+        sel = np.sort(W.rng(9604 + si).choice(M, min(M, 600), replace=False))
+        e_f = ndft.rel_l2(yg[:, 0, sel], ndft.forward(om[sel], x, N))
+        e_a = ndft.rel_l2(xa.reshape(B, -1)[:, pix], ndft.adjoint(om, g[:, 0], N, pix=pix))
+        _say(f"  set {si}: M={M} forward {e_f:.2e} adjoint {e_a:.2e}")
+        assert e_f < TOL_NUFFT and e_a < TOL_NUFFT
+        if M <= 1200:
+            gi = W.complex_normal((B,) + N, 9605 + si)
+            dom = _np(p.jac_omega_fwd(xs, gs))
+            doma = _np(p.jac_omega_adj(gs, _c(gi, dev)))
+            e_j = ndft.rel_l2(dom, ndft.jac_omega_fwd(om, x, g, N))
+            e_ja = ndft.rel_l2(doma, ndft.jac_omega_adj(om, g, gi, N))
+            _say(f"  set {si}: omega-Jacobians {e_j:.2e} {e_ja:.2e}")
+            assert e_j < TOL_JAC and e_ja < TOL_JAC
+
+
 @pytest.mark.parametrize("N,st", [((60, 52), 24), ((20, 22, 18), 10)])
 def test_scatter_spread_path(N, st, dev):
     """Owner tiles of more than 512 cells use the scatter spread kernel
