@@ -622,8 +622,12 @@ __device__ __forceinline__ void spread_os_wg(const KbnGeom &g, const KbnSpreadAr
     __shared__ float s_w[D == 2 ? EB : 1][D][J];
     __shared__ int s_l[D == 2 ? EB : 1][D];
     extern __shared__ float s_t[];  // 3D: [EB][D][To_max]
+    // 3D: the window polynomials' coefficients, read by every table entry
+    __shared__ float s_cf[D == 3 ? KBN_MAX_J * KBN_NCOEF : 1];
     const int nwork = a.scounts[0];
     const int nthr = blockDim.x;
+    if (D == 3)
+        for (int i = threadIdx.x; i < J * KBN_NCOEF; i += nthr) s_cf[i] = g.coef[i];  // seen after the first barrier
     int tmax = 1;
 #pragma unroll
     for (int d = 0; d < D; ++d) tmax = max(tmax, g.To[d]);
@@ -638,6 +642,8 @@ __device__ __forceinline__ void spread_os_wg(const KbnGeom &g, const KbnSpreadAr
     }
     const int ch0 = gx * CPT;
     const int nchg = min(CPT, a.nch - ch0);
+    // 3D tiles of 8 x 8 cells per x-slice: a wave holds exactly one slice
+    const bool slice_waves = D == 3 && EB <= 64 && CPT <= 16 && g.To[1] == 8 && g.To[D - 1] == 8;
     // work items in dispatch order (hottest tiles first); a grid smaller
     // than the work list strides over it
     for (int wk = wy; wk < nwork; wk += ny) {
@@ -689,7 +695,7 @@ __device__ __forceinline__ void spread_os_wg(const KbnGeom &g, const KbnSpreadAr
                 float wv = 0.f;
                 if (j < J) {
                     const float x = 2.f * a.rec_f[e * D + d] - 1.f;
-                    const float *cf = g.coef + j * KBN_NCOEF;
+                    const float *cf = s_cf + j * KBN_NCOEF;
                     float acc_w = cf[KBN_NCOEF - 1];
 #pragma unroll
                     for (int k = KBN_NCOEF - 2; k >= 0; --k) acc_w = fmaf(acc_w, x, cf[k]);
@@ -709,6 +715,50 @@ __device__ __forceinline__ void spread_os_wg(const KbnGeom &g, const KbnSpreadAr
                 s_y[t][k] = a.y[(int64_t)(ch0 + (ok ? k : 0)) * a.M + (ok ? s_p[t] : 0)];
             }
             __syncthreads();
+            if (D == 3 && slice_waves) {
+                // The wave's entries: a ballot over the batch of the slice
+                // weights (lane t: entry t), so that the walk below visits
+                // only entries that reach the slice, two at a time, with all
+                // their table and value reads issued before the sums.  The
+                // products and the order of the sums are those of the loop
+                // below.
+                const int t = threadIdx.x & 63;
+                const float wx_t = t < n ? s_t[t * D * tmax + c[0]] : 0.f;
+                unsigned long long todo = __ballot(wx_t != 0.f);
+                constexpr int U = KBN_SPREAD_OS_U;  // entries per step
+                while (todo) {
+                    int idx[U];
+                    bool has[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        has[u] = todo != 0;
+                        idx[u] = has[u] ? __builtin_ctzll(todo) : idx[0];
+                        if (has[u]) todo &= todo - 1;
+                    }
+                    float wv[U];
+                    float2 yv[U][CPT];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const float *ti = s_t + idx[u] * D * tmax;
+                        float w = ti[c[0]];
+#pragma unroll
+                        for (int d = 1; d < D; ++d) w *= ti[d * tmax + c[d]];
+                        wv[u] = w;
+#pragma unroll
+                        for (int k = 0; k < CPT; ++k) yv[u][k] = s_y[idx[u]][k];
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if (!has[u]) break;
+#pragma unroll
+                        for (int k = 0; k < CPT; ++k) {
+                            acc[k].x = fmaf(wv[u], yv[u][k].x, acc[k].x);
+                            acc[k].y = fmaf(wv[u], yv[u][k].y, acc[k].y);
+                        }
+                    }
+                }
+                continue;
+            }
             for (int i = 0; i < n; ++i) {
                 float w;
                 if (D == 3) {

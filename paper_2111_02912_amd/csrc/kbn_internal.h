@@ -28,6 +28,9 @@
 #define KBN_SPREAD_CL_EB 16 // list entries staged per batch of the channel-per-lane spread
 #endif
 #define KBN_SPREAD_LDS (64 * 1024)  // LDS budget of one spread workgroup
+#ifndef KBN_SPREAD_OS_U
+#define KBN_SPREAD_OS_U 3   // entries per step of the 3D cell-per-lane spread's walk
+#endif
 
 // kernel classes reported by kbn_timing_read (order of kClassNames)
 #define KBN_CLASS_INDEX 0
