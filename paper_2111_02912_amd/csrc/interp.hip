@@ -718,7 +718,7 @@ __device__ __forceinline__ void spread_os_wg(const KbnGeom &g, const KbnSpreadAr
             if (D == 3 && slice_waves) {
                 // The wave's entries: a ballot over the batch of the slice
                 // weights (lane t: entry t), so that the walk below visits
-                // only entries that reach the slice, two at a time, with all
+                // only entries that reach the slice, KBN_SPREAD_OS_U at a time, with all
                 // their table and value reads issued before the sums.  The
                 // products and the order of the sums are those of the loop
                 // below.
