@@ -17,6 +17,7 @@
 #define KBN_BLOCK 256
 #define KBN_INDEX_STREAM_MIN 8192  // points from which the index pass runs beside the caller's stream
 #define KBN_SUB 256        // sorted points per gather subproblem (one per thread)
+#define KBN_GATHER_WG_TARGET 2048  // workgroups a gather aims for (point blocks x channel groups)
 #define KBN_SPREAD_EB 64   // list entries staged per spread batch
 #define KBN_SPREAD_SEG 128  // list entries per spread work item (doubled if slots run out)
 #define KBN_SPREAD_SMAX 256 // partial-tile slots for tiles split into several work items
@@ -198,6 +199,10 @@ struct KbnGatherShape {
     int64_t blocks;
     int cg, groups;
 };
+// Nominal channel groups of a gather over nbc channel sets in `blocks`
+// point blocks: never more than nbc, and never fewer for a larger nbc, so
+// that it bounds the groups of every smaller chunk as well.
+int64_t kbn_gather_groups(int64_t blocks, int64_t nbc);
 KbnGatherShape kbn_gather_shape(const KbnGeom &g, int64_t M, int nch, int nw);
 
 struct KbnSpreadArgs {

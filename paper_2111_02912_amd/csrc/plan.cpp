@@ -463,7 +463,8 @@ static Chunks split_chunks(int64_t B, int C, int64_t per_coil, int64_t max_ws) {
 // workspace cap.  Type 2 (forward, nw weight channels per coil; mode 1 adds
 // the per-group partial omega-gradients: the gather's point blocks do not
 // depend on the channel count, and a chunk's channel groups are at most
-// min(its image-coil pairs, ceil(2048 / blocks))).
+// kbn_gather_groups of its image-coil pairs, a bound that also holds for
+// every smaller chunk).
 int64_t ws_type2(const kbn_plan p, int64_t M, int B, int C, int nw, int mode) {
     const int64_t per_coil = (int64_t)nw * p->gsize() * (int64_t)sizeof(float2) * 2;
     const Chunks ck = split_chunks(B, C, per_coil, p->max_ws);
@@ -471,7 +472,7 @@ int64_t ws_type2(const kbn_plan p, int64_t M, int B, int C, int nw, int mode) {
     int64_t part_bytes = 0;
     if (mode == 1) {
         const int64_t blocks0 = kbn_gather_shape(p->geom(), M, (int)(units * nw), nw).blocks;
-        const int64_t groups_max = std::max<int64_t>(1, std::min<int64_t>(units, (2048 + blocks0 - 1) / blocks0));
+        const int64_t groups_max = kbn_gather_groups(blocks0, units);
         part_bytes = groups_max * M * p->D * (int64_t)sizeof(float);
     }
     return units * per_coil + part_bytes;
