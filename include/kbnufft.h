@@ -139,7 +139,8 @@ int kbn_plan_create(kbn_plan *out, int D, const int64_t *N, const kbn_opts *opts
  * forward and adjoint calls with B images of C coils (and of the
  * omega-Jacobian with jac != 0) under opts->max_workspace.  Equal to
  * kbn_plan_info's device_bytes after kbn_set_points(M) and those calls.
- * The off-resonance workspace is not included.  For admission control.
+ * The off-resonance workspace and that of kbn_forward_jac_omega (D + 1
+ * grids per image-coil pair) are not included.  For admission control.
  * Errors: INVALID_ARG (null bytes, M < 0 or too large, B < 1, C < 1, and the
  * option errors of kbn_plan_create), UNSUPPORTED.
  */
@@ -228,6 +229,28 @@ int kbn_adjoint(kbn_plan p, int B, int C, const void *y, const void *smaps, void
  */
 int kbn_jac_omega_fwd(kbn_plan p, int B, int C, const void *x, const void *smaps,
                       const void *g, float *domega, int accumulate, void *stream);
+
+/*
+ * kbn_forward and kbn_jac_omega_fwd of the same images in one call, for an
+ * upstream gradient g that is known before y (Sec. II-C and eq. (e,Ax)):
+ *
+ *   y[b][c] = A(omega) (s_c (.) x_b)          (overwritten)
+ *   domega[m][d] (+)= sum_{b,c} Im{ [A(s_c x_b (.) r^[d])]_m conj(g[b][c][m]) }
+ *
+ * In 2D the weight r^[0] is constant along the lines of the first FFT pass,
+ * so that channel is not transformed on its own there: the axis-0 pass
+ * derives it from the unweighted channel, one grid-row write and read less
+ * per image-coil pair than the two separate calls.  y equals kbn_forward's
+ * bit for bit; domega agrees with kbn_jac_omega_fwd to float32 rounding
+ * (the r^[0] scaling is applied after the first pass instead of before).
+ * Other dimensions and FFT lengths run the two calls.  x: c64 [B][N...];
+ * y, g: c64 [B][C][M] (y and g must not overlap); domega: device float32
+ * [M][D]; accumulate = 0 overwrites domega, 1 adds.  The workspace holds
+ * D + 1 grids per image-coil pair (kbn_plan_footprint does not count it).
+ * Errors as kbn_forward, plus INVALID_ARG for a null domega.
+ */
+int kbn_forward_jac_omega(kbn_plan p, int B, int C, const void *x, const void *smaps, void *y,
+                          const void *g, float *domega, int accumulate, void *stream);
 
 /*
  * Gradient of a real loss w.r.t. omega through x = E(omega)^H y, given the

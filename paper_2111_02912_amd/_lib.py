@@ -33,7 +33,7 @@ KBN_STATIC_WORKSPACE = 67108864
 EXPORTS = (
     "kbn_plan_create", "kbn_plan_footprint", "kbn_set_points", "kbn_forward", "kbn_forward_static",
     "kbn_adjoint",
-    "kbn_jac_omega_fwd", "kbn_jac_omega_adj", "kbn_jac_x", "kbn_plan_info",
+    "kbn_jac_omega_fwd", "kbn_forward_jac_omega", "kbn_jac_omega_adj", "kbn_jac_x", "kbn_plan_info",
     "kbn_get_points", "kbn_check_error", "kbn_plan_destroy", "kbn_strerror",
     "kbn_last_error", "kbn_timing", "kbn_timing_select", "kbn_timing_read", "kbn_timing_name",
     "kbn_batch_create", "kbn_batch_run", "kbn_batch_capture", "kbn_batch_fuse", "kbn_batch_launch",
@@ -110,6 +110,7 @@ def lib():
     L.kbn_forward_static.argtypes = [vp, ci, ci, vp, vp, vp, vp]
     L.kbn_adjoint.argtypes = [vp, ci, ci, vp, vp, vp, vp]
     L.kbn_jac_omega_fwd.argtypes = [vp, ci, ci, vp, vp, vp, vp, ci, vp]
+    L.kbn_forward_jac_omega.argtypes = [vp, ci, ci, vp, vp, vp, vp, vp, ci, vp]
     L.kbn_jac_omega_adj.argtypes = [vp, ci, ci, vp, vp, vp, vp, ci, vp]
     L.kbn_jac_x.argtypes = [vp, ci, ci, ci, vp, vp, vp, vp]
     L.kbn_plan_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ci), ctypes.POINTER(ci),

@@ -16,6 +16,7 @@
 // b < E/R (TL = L/E threads per line); butterfly j reads elements
 // j + q*L/R and writes element (j - j%Ns)*R + j%Ns + q*Ns, q < R.
 #include <algorithm>
+#include <climits>
 
 #include "kbn_internal.h"
 
@@ -258,7 +259,30 @@ __device__ __forceinline__ int pos_to_img(int p, int n) {
 // overlap the LDS stages of the previous (the grid holds only as many
 // workgroups as fit on the device at once); it needs about twice the
 // registers, so it is used only where it measured faster.
-template <int L, int E, bool INV, int NT>
+// Channel of the o-th line group in processing order: input channel (the
+// return value), output channel `oo` and whether it is derived (scaled by
+// r^[0]).  With DER the groups run pair by pair, [unweighted, r^[0],
+// r^[1], ...], so that the derived channel re-reads its source while that
+// is still in cache; see KbnMidPassArgs::dsplit.
+template <bool DER>
+__device__ __forceinline__ int64_t col_map(const KbnMidPassArgs &a, int64_t o, int64_t &oo, bool &der) {
+    der = false;
+    oo = o;
+    if constexpr (DER) {
+        const int64_t cc = o / (a.dnw + 1);
+        const int k = (int)(o - cc * (a.dnw + 1));
+        if (k == 0) {
+            oo = cc;
+            return cc;
+        }
+        oo = a.dsplit + cc * a.dnw + (k - 1);
+        der = k == 1;
+        return der ? cc : oo;
+    }
+    return o;
+}
+
+template <int L, int E, bool INV, int NT, bool DER = false>
 __global__ void __launch_bounds__(NT) k_cols(KbnMidPassArgs a, const float2 *__restrict__ tw) {
     using F = Fft<L, E, INV>;
     static_assert(NT % F::TL == 0, "a workgroup holds whole lines");
@@ -270,14 +294,21 @@ __global__ void __launch_bounds__(NT) k_cols(KbnMidPassArgs a, const float2 *__r
     const int64_t o = blockIdx.x / ntile;
     const int c0 = (int)(blockIdx.x - o * ntile) * LINES;
     const bool col_ok = c0 + l < a.inner;
-    const float2 *in = a.in + (o * a.nin) * (int64_t)a.inner + c0 + l;
-    float2 *out = a.out + (o * a.nout) * (int64_t)a.inner + c0 + l;
+    bool der;
+    int64_t oo;
+    const int64_t oi = col_map<DER>(a, o, oo, der);
+    const float2 *in = a.in + (oi * a.nin) * (int64_t)a.inner + c0 + l;
+    float2 *out = a.out + (oo * a.nout) * (int64_t)a.inner + c0 + l;
     float2 v[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int p = F::template in_pos<0>(u, i);
         const int r = a.pad_in ? pos_to_img<L>(p, a.nin) : p;
         v[i] = (col_ok && r >= 0) ? in[(int64_t)r * a.inner] : make_float2(0.f, 0.f);
+        if (DER && der) {
+            const float f = (float)(r - a.nin / 2);
+            v[i] = make_float2(v[i].x * f, v[i].y * f);
+        }
     }
     auto lds_idx = [](int pos) { return pos * LINES; };
     float2 *ldsl = lds + l;
@@ -288,7 +319,42 @@ __global__ void __launch_bounds__(NT) k_cols(KbnMidPassArgs a, const float2 *__r
     Stages<F, 0>::run(v, u, tw, ldsl, lds_idx, sink);
 }
 
-template <int L, int E, bool INV, int NT>
+// Tile t of the persistent column pass with a derived channel: input and
+// output channel, first column and, for unweighted and derived tiles, the
+// index q of the (pair, column tile) they share (-1 for the others).  The
+// first 2P tiles (P = pairs x column tiles) come in blocks of 2G (G = grid
+// size): G unweighted tiles, then the derived tiles of the same q, so that
+// a workgroup striding by G meets each derived tile right after its source
+// (in the last, shorter block the twin is loaded again); the weighted
+// channels w = 1 .. dnw-1 follow in channel order.
+// (32-bit: the launcher takes this form only below 2^31 tiles)
+__device__ __forceinline__ void der_tile(const KbnMidPassArgs &a, int t, int G, int ntile, int lines, int64_t &oi,
+                                         int64_t &oo, int &c0, bool &der, int &q) {
+    const int P = (int)a.dsplit * ntile;
+    int ct;
+    if (t < 2 * P) {
+        const int base = (t / (2 * G)) * G;
+        const int w = t - 2 * base;
+        const int rem = min(G, P - base);
+        der = w >= rem;
+        q = base + (der ? w - rem : w);
+        const int cc = q / ntile;
+        ct = q - cc * ntile;
+        oi = cc;
+        oo = der ? a.dsplit + (int64_t)cc * a.dnw : cc;
+    } else {
+        const int r = t - 2 * P;
+        const int wq = r / ntile;
+        ct = r - wq * ntile;
+        const int cc = wq / (a.dnw - 1);
+        oi = oo = a.dsplit + (int64_t)cc * a.dnw + 1 + (wq - cc * (a.dnw - 1));
+        der = false;
+        q = -1;
+    }
+    c0 = ct * lines;
+}
+
+template <int L, int E, bool INV, int NT, bool DER = false>
 __global__ void __launch_bounds__(NT) k_cols_pf(KbnMidPassArgs a, const float2 *__restrict__ tw) {
     using F = Fft<L, E, INV>;
     static_assert(NT % F::TL == 0, "a workgroup holds whole lines");
@@ -298,34 +364,75 @@ __global__ void __launch_bounds__(NT) k_cols_pf(KbnMidPassArgs a, const float2 *
     const int u = threadIdx.x / LINES;
     const int ntile = (a.inner + LINES - 1) / LINES;
     const int64_t total = a.outer * ntile;
-    auto load = [&](int64_t t, float2 (&w)[E]) {
-        const int64_t o = t / ntile;
-        const int c0 = (int)(t - o * ntile) * LINES;
+    // tile t -> input channel oi, output channel oo, first column c0
+    auto tile = [&](int64_t t, int64_t &oi, int64_t &oo, int &c0, bool &der, int &q) {
+        if constexpr (DER) {
+            der_tile(a, (int)t, (int)gridDim.x, ntile, LINES, oi, oo, c0, der, q);
+        } else {
+            oi = oo = t / ntile;
+            c0 = (int)(t - oi * ntile) * LINES;
+            der = false;
+            q = -1;
+        }
+    };
+    // r^[0] of the image row of register element i
+    auto rweight = [&](int i) {
+        const int r = pos_to_img<L>(F::template in_pos<0>(u, i), a.nin);
+        return (float)(r - a.nin / 2);
+    };
+    auto load = [&](int64_t oi, int c0, bool der, float2 (&w)[E]) {
         const bool col_ok = c0 + l < a.inner;
-        const float2 *in = a.in + (o * a.nin) * (int64_t)a.inner + c0 + l;
+        const float2 *in = a.in + (oi * a.nin) * (int64_t)a.inner + c0 + l;
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int p = F::template in_pos<0>(u, i);
             const int r = a.pad_in ? pos_to_img<L>(p, a.nin) : p;
             w[i] = (col_ok && r >= 0) ? in[(int64_t)r * a.inner] : make_float2(0.f, 0.f);
+            if (DER && der) {
+                const float f = rweight(i);
+                w[i] = make_float2(w[i].x * f, w[i].y * f);
+            }
         }
     };
     float2 nv[E];
     int64_t t = blockIdx.x;
-    if (t < total) load(t, nv);
+    // tile t's channels and column, then the next tile's
+    int64_t oi = 0, oo = 0;
+    int c0 = 0, q = -1;
+    bool der = false;
+    if (t < total) {
+        tile(t, oi, oo, c0, der, q);
+        load(oi, c0, der, nv);
+    }
     auto lds_idx = [](int pos) { return pos * LINES; };
     float2 *ldsl = lds + l;
     for (; t < total; t += gridDim.x) {
         float2 v[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) v[i] = nv[i];
+        const int64_t co = oo;
+        const int cc0 = c0;
         const int64_t tn = t + gridDim.x;
-        if (tn < total) load(tn, nv);
+        if (tn < total) {
+            const int pq = q;
+            const bool pder = der;
+            tile(tn, oi, oo, c0, der, q);
+            // the next tile derived from this one: scale the values in
+            // registers instead of reading them again
+            const bool twin = DER && !pder && pq >= 0 && der && q == pq;
+            if (twin) {
+#pragma unroll
+                for (int i = 0; i < E; ++i) {
+                    const float f = rweight(i);
+                    nv[i] = make_float2(v[i].x * f, v[i].y * f);
+                }
+            } else {
+                load(oi, c0, der, nv);
+            }
+        }
         if (t != (int64_t)blockIdx.x) __syncthreads();  // the previous tile's LDS reads are done
-        const int64_t o = t / ntile;
-        const int c0 = (int)(t - o * ntile) * LINES;
-        const bool col_ok = c0 + l < a.inner;
-        float2 *out = a.out + (o * a.nout) * (int64_t)a.inner + c0 + l;
+        const bool col_ok = cc0 + l < a.inner;
+        float2 *out = a.out + (co * a.nout) * (int64_t)a.inner + cc0 + l;
         auto sink = [&](int, int pos, float2 val) {
             const int r = a.crop_out ? pos_to_img<L>(pos, a.nout) : pos;
             if (col_ok && r >= 0) out[(int64_t)r * a.inner] = val;
@@ -354,14 +461,26 @@ __global__ void __launch_bounds__(NT) k_rows_first(KbnFirstPassArgs a, const flo
     int64_t xrow = 0, srow = 0;
     float lf = 0.f;
     int wsel = -1;
+    int64_t oline = line;  // output line
     if (line_ok) {
         const int64_t ch = line / a.R0;
         const int row = (int)(line - ch * a.R0);
-        const int w = (int)(ch % a.nw);
-        const int64_t cc = ch / a.nw;
+        int64_t cc;
+        if (a.nplain > 0) {  // forward plus omega-Jacobian layout (D >= 2)
+            if (ch < a.nplain) {
+                cc = ch;
+            } else {
+                const int64_t q = ch - a.nplain;
+                cc = q / (a.D - 1);
+                wsel = 1 + (int)(q - cc * (a.D - 1));
+                oline = (a.nplain + cc * a.D + wsel) * a.R0 + row;
+            }
+        } else {
+            cc = ch / a.nw;
+            wsel = a.weighted ? (int)(ch - cc * a.nw) : -1;
+        }
         const int c = (int)(cc % a.C);
         const int64_t bl = cc / a.C;
-        wsel = a.weighted ? w : -1;
         xrow = (bl * a.R0 + row) * (int64_t)Nl;
         srow = ((int64_t)c * a.R0 + row) * Nl;
         float f = 1.f;
@@ -390,7 +509,7 @@ __global__ void __launch_bounds__(NT) k_rows_first(KbnFirstPassArgs a, const flo
         v[i] = x;
     }
     __syncthreads();  // twiddles in LDS
-    float2 *out = a.out + line * L;
+    float2 *out = a.out + oline * L;
     auto lds_idx = [](int pos) { return pos; };
     float2 *ldsl = lds + li * L;
     auto sink = [&](int, int pos, float2 val) {
@@ -589,6 +708,9 @@ hipError_t launch_cols(const KbnMidPassArgs &a, const float2 *tw, int inverse, h
     const int64_t ntile = (a.inner + LINES - 1) / LINES;
     const int64_t total = a.outer * ntile;
     if (total <= 0) return hipSuccess;
+    const bool der = a.dsplit > 0;
+    if (der && (inverse || !a.pad_in || a.dnw < 2 || a.outer != a.dsplit * (a.dnw + 1) || total > INT_MAX / 2))
+        return hipErrorInvalidValue;
     if constexpr (col_pf(L)) {
         static const hipError_t ok = [] {
             const hipError_t e = allow_lds(k_cols_pf<L, E, false, NT>, LDS);
@@ -597,6 +719,14 @@ hipError_t launch_cols(const KbnMidPassArgs &a, const float2 *tw, int inverse, h
         if (ok != hipSuccess) return ok;
         static const int64_t cap_fwd = resident_blocks(k_cols_pf<L, E, false, NT>, NT, LDS);
         static const int64_t cap_inv = resident_blocks(k_cols_pf<L, E, true, NT>, NT, LDS);
+        if (der) {
+            static const hipError_t ok_der = allow_lds(k_cols_pf<L, E, false, NT, true>, LDS);
+            if (ok_der != hipSuccess) return ok_der;
+            static const int64_t cap_der = resident_blocks(k_cols_pf<L, E, false, NT, true>, NT, LDS);
+            const dim3 grid((unsigned)std::min<int64_t>(total, cap_der));
+            k_cols_pf<L, E, false, NT, true><<<grid, dim3(NT), LDS, s>>>(a, tw);
+            return hipGetLastError();
+        }
         const dim3 grid((unsigned)std::min<int64_t>(total, inverse ? cap_inv : cap_fwd));
         if (inverse)
             k_cols_pf<L, E, true, NT><<<grid, dim3(NT), LDS, s>>>(a, tw);
@@ -609,7 +739,11 @@ hipError_t launch_cols(const KbnMidPassArgs &a, const float2 *tw, int inverse, h
         }();
         if (ok != hipSuccess) return ok;
         const dim3 grid((unsigned)total);
-        if (inverse)
+        if (der) {
+            static const hipError_t ok_der = allow_lds(k_cols<L, E, false, NT, true>, LDS);
+            if (ok_der != hipSuccess) return ok_der;
+            k_cols<L, E, false, NT, true><<<grid, dim3(NT), LDS, s>>>(a, tw);
+        } else if (inverse)
             k_cols<L, E, true, NT><<<grid, dim3(NT), LDS, s>>>(a, tw);
         else
             k_cols<L, E, false, NT><<<grid, dim3(NT), LDS, s>>>(a, tw);

@@ -122,6 +122,13 @@ struct KbnFirstPassArgs {      // forward: prologue + FFT along the last axis
     int D;
     int N[KBN_MAX_D];
     const float *deap[KBN_MAX_D];
+    // > 0: forward plus omega-Jacobian layout of nplain image-coil pairs.
+    // Logical channels are the nplain unweighted ones, then for each pair
+    // its weights w = 1..D-1 (nlines = nplain * D * R0); they are written
+    // at output channels [nplain unweighted][nplain][D weights], leaving
+    // every w = 0 slot for the axis-0 pass to derive (r^[0] is constant
+    // along the lines of this pass).
+    int64_t nplain = 0;
 };
 
 struct KbnMidPassArgs {        // FFT along a non-last axis, strided
@@ -132,6 +139,12 @@ struct KbnMidPassArgs {        // FFT along a non-last axis, strided
     int inner;                 // product of the later axes' (grid) sizes
     int pad_in;                // 1: input rows sit at r mod L (zero-padded)
     int crop_out;              // 1: output rows are taken from r mod L
+    // > 0 (forward axis-0 pass with pad_in, outer = channels only): output
+    // channel dsplit + q with q % dnw == 0 is r^[0] times the unweighted
+    // channel q / dnw, read from that channel's input with each image row
+    // r scaled by r - nin / 2 (the other channels read their own input)
+    int64_t dsplit = 0;
+    int dnw = 1;
 };
 
 struct KbnLastAdjArgs {        // adjoint: IFFT along the last axis + crop + scale + coil sum

@@ -245,6 +245,21 @@ class KbNufft:
                                            int(accumulate), _stream(self.device)), "kbn_jac_omega_fwd")
         return dom
 
+    def forward_jac_omega(self, x: torch.Tensor, g: torch.Tensor, smaps=None, out=None,
+                          accumulate: bool = False):
+        """forward(x) and jac_omega_fwd(x, g) in one library call (g known
+        before y); returns (y [B, C, M], dL/domega [M, D] float32)."""
+        self._need_points()
+        xx = self._img(x, "x")
+        s, C = self._maps(smaps)
+        B = xx.shape[0]
+        gg = self._ksp(g, B, C, "g")
+        y = torch.empty((B, C, self.M), dtype=torch.complex64, device=self.device)
+        dom = out if out is not None else torch.empty((self.M, self.D), dtype=torch.float32, device=self.device)
+        check(_lib.lib().kbn_forward_jac_omega(self._h, B, C, _ptr(xx), _ptr(s), _ptr(y), _ptr(gg), _ptr(dom),
+                                               int(accumulate), _stream(self.device)), "kbn_forward_jac_omega")
+        return y, dom
+
     def jac_omega_adj(self, y: torch.Tensor, g: torch.Tensor, smaps=None, out=None,
                       accumulate: bool = False) -> torch.Tensor:
         """dL/domega for x = E^H y given g = dL/dx; returns [M, D] float32."""

@@ -57,7 +57,7 @@ def kernel_class(name: str):
     if base in ("k_last_adj", "k_rows_last_adj"):
         return "fft_last_adj"
     if base in ("k_cols", "k_cols_pf", "k_mid_pass"):
-        # k_cols[_pf]<L, E, INV, NT>, k_mid_pass<MAXE, INV>
+        # k_cols[_pf]<L, E, INV, NT[, DER]>, k_mid_pass<MAXE, INV>
         inv = ta[2] if base.startswith("k_cols") and len(ta) > 2 else (ta[1] if len(ta) > 1 else "false")
         return "fft_mid_inv" if inv == "true" else "fft_mid_fwd"
     if base in ("k_gather_staged", "k_gather"):

@@ -287,6 +287,86 @@ def test_chunked_batches_match_single_pass(dev):
     assert ndft.rel_l2(c[1], c[0]) < 1e-6
 
 
+FWD_JAC_CASES = [
+    ((64, 64), "radial", True),      # K = 128 x 128: r^[0] channel derived in the axis-0 pass
+    ((99, 80), 1700, True),          # odd N_0, K = 200 x 160, ragged tiles
+    ((45, 37), 1500, False),         # K = 90 x 75: generic FFT lengths, two separate calls
+    ((96,), 700, False),             # 1D
+    ((20, 18, 14), 900, False),      # 3D
+]
+
+
+@pytest.mark.parametrize("N,kind,fused", FWD_JAC_CASES)
+def test_forward_jac_omega(N, kind, fused, dev):
+    """kbn_forward_jac_omega: y bit-equal to kbn_forward, domega equal to
+    kbn_jac_omega_fwd up to float32 rounding where the r^[0] channel is
+    derived (bit-equal where the call runs the two operations), both
+    against the exact forms; accumulate adds; a workspace cap that splits
+    the batch into chunks changes nothing."""
+    _say(f"forward + omega-Jacobian N={N} points={kind} fused={fused}")
+    om = _case(N, kind, 51)
+    M = om.shape[0]
+    B, C = 2, 3
+    x = W.complex_normal((B,) + N, 52)
+    smaps = W.sense_maps(C, N)
+    g = W.complex_normal((B, C, M), 53)
+    p = _plan(N, dev)
+    p.set_points(_f(om, dev))
+    xs, ss, gs = _c(x, dev), _c(smaps, dev), _c(g, dev)
+    y_ref = _np(p.forward(xs, ss))
+    d_ref = _np(p.jac_omega_fwd(xs, gs, ss))
+    yt, dt = p.forward_jac_omega(xs, gs, ss)
+    y, d = _np(yt), _np(dt)
+    assert np.array_equal(y, y_ref)
+    err = ndft.rel_l2(d, d_ref)
+    _say(f"  domega vs kbn_jac_omega_fwd: {err:.2e}")
+    if fused:
+        assert err < TOL_STEPS
+    else:
+        assert np.array_equal(d, d_ref)
+    assert ndft.rel_l2(y, ndft.sense_forward(om, x, N, smaps)) < TOL_NUFFT
+    assert ndft.rel_l2(d, ndft.jac_omega_fwd(om, x, g, N, smaps)) < TOL_JAC
+    _, acc = p.forward_jac_omega(xs, gs, ss, out=dt.clone(), accumulate=True)
+    assert ndft.rel_l2(_np(acc), 2 * d) < 1e-6
+    gsz = int(np.prod(p.K)) * 8
+    pc = _plan(N, dev, max_workspace=2 * gsz * (len(N) + 1) * 2)  # two image-coil pairs per chunk
+    pc.set_points(_f(om, dev))
+    yc, dc = pc.forward_jac_omega(xs, gs, ss)
+    assert np.array_equal(_np(yc), y)
+    assert ndft.rel_l2(_np(dc), d) < 1e-6
+
+
+def test_forward_jac_omega_persistent_twins(dev):
+    """256 x 256 images (K = 512), 4 images x 3 coils: the persistent axis-0
+    pass then meets each derived r^[0] tile right after its unweighted source
+    in one full block of workgroup strides (values scaled in registers) and
+    loads it again in the shorter last block.  y bit-equal to kbn_forward;
+    domega against kbn_jac_omega_fwd and, on sampled rows, the exact
+    gradient."""
+    N = (256, 256)
+    M = 3000
+    B, C = 4, 3
+    _say(f"forward + omega-Jacobian, persistent column pass N={N} M={M} B={B} C={C}")
+    om = W.uniform_random(M, 2, seed=61)
+    x = W.complex_normal((B,) + N, 62)
+    smaps = W.sense_maps(C, N)
+    g = W.complex_normal((B, C, M), 63)
+    p = _plan(N, dev)
+    p.set_points(_f(om, dev))
+    xs, ss, gs = _c(x, dev), _c(smaps, dev), _c(g, dev)
+    y_ref = _np(p.forward(xs, ss))
+    d_ref = _np(p.jac_omega_fwd(xs, gs, ss))
+    yt, dt = p.forward_jac_omega(xs, gs, ss)
+    assert np.array_equal(_np(yt), y_ref)
+    d = _np(dt)
+    err = ndft.rel_l2(d, d_ref)
+    _say(f"  domega vs kbn_jac_omega_fwd: {err:.2e}")
+    assert err < TOL_STEPS
+    rows = np.random.default_rng(64).choice(M, 48, replace=False)
+    ex = ndft.jac_omega_fwd(om, x, g, N, smaps, rows=rows)
+    assert ndft.rel_l2(d[rows], ex) < TOL_JAC
+
+
 def test_chunked_jacobian_last_chunk_with_more_groups(dev):
     """omega-Jacobian in image chunks of 7 and 6 where the smaller last chunk
     splits into more channel groups than the first (about 2048 / blocks = 6
