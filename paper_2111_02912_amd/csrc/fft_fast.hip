@@ -251,19 +251,12 @@ __device__ __forceinline__ int pos_to_img(int p, int n) {
     return -1;
 }
 
-// ---- strided pass along a non-last axis -------------------------------------
-// lines = LINES adjacent columns; LDS layout [position][column] (column fastest).
-// k_cols transforms one column tile per workgroup.  k_cols_pf walks over
-// column tiles with a grid stride and loads the next tile's inputs into
-// registers before transforming the current one, so the loads of one tile
-// overlap the LDS stages of the previous (the grid holds only as many
-// workgroups as fit on the device at once); it needs about twice the
-// registers, so it is used only where it measured faster.
-// Channel of the o-th line group in processing order: input channel (the
-// return value), output channel `oo` and whether it is derived (scaled by
-// r^[0]).  With DER the groups run pair by pair, [unweighted, r^[0],
+// k_cols: channel of the o-th line group in processing order: input channel
+// (the return value), output channel `oo` and whether it is derived (scaled
+// by r^[0]).  With DER the groups run pair by pair, [unweighted, r^[0],
 // r^[1], ...], so that the derived channel re-reads its source while that
-// is still in cache; see KbnMidPassArgs::dsplit.
+// is still in cache; see KbnMidPassArgs::dsplit (k_cols_pf orders its tiles
+// with der_tile instead).
 template <bool DER>
 __device__ __forceinline__ int64_t col_map(const KbnMidPassArgs &a, int64_t o, int64_t &oo, bool &der) {
     der = false;
@@ -282,6 +275,14 @@ __device__ __forceinline__ int64_t col_map(const KbnMidPassArgs &a, int64_t o, i
     return o;
 }
 
+// ---- strided pass along a non-last axis -------------------------------------
+// lines = LINES adjacent columns; LDS layout [position][column] (column fastest).
+// k_cols transforms one column tile per workgroup.  k_cols_pf walks over
+// column tiles with a grid stride and loads the next tile's inputs into
+// registers before transforming the current one, so the loads of one tile
+// overlap the LDS stages of the previous (the grid holds only as many
+// workgroups as fit on the device at once); it needs about twice the
+// registers, so it is used only where it measured faster.
 template <int L, int E, bool INV, int NT, bool DER = false>
 __global__ void __launch_bounds__(NT) k_cols(KbnMidPassArgs a, const float2 *__restrict__ tw) {
     using F = Fft<L, E, INV>;

@@ -787,8 +787,8 @@ int run_jac(kbn_plan p, int B, int C, const float2 *img, const float2 *smaps, co
 // specialised FFT lengths, the first pass (along axis 1) transforms the
 // unweighted and the r^[1]-weighted images only: r^[0] is constant along
 // axis-1 lines, so the axis-0 pass derives the r^[0] channel by scaling the
-// unweighted channel's rows, reading it right after that channel's own
-// transform.  This saves one grid-row write and one read per image-coil pair
+// unweighted channel's rows (the persistent pass scales the values it holds
+// for the source tile).  This saves one grid-row write and one read per image-coil pair
 // against kbn_forward followed by kbn_jac_omega_fwd.  The unweighted channel
 // goes through the same steps as in kbn_forward (same y bits); the derived
 // channel rounds the product r^[0] * window scale in another order than
@@ -846,8 +846,10 @@ int run_fwd_jac(kbn_plan p, int B, int C, const float2 *x, const float2 *smaps, 
         ma.dsplit = npair;
         ma.dnw = D;
         KBN_LAUNCH(KBN_CLASS_FFT_MID_FWD, kbn_launch_fast_mid(ma, p->K[0], p->tw[0], 0, stream), "mid pass");
-        rc = points_wait(p, stream);  // the FFT passes overlap the index pass (waiting before
-        if (rc != KBN_OK) return rc;  // the axis-0 pass measured 1.79 vs 1.76 ms on the 256-image step)
+        // the FFT passes overlap the index pass (waiting before the axis-0
+        // pass measured 1.79 against 1.76 ms on the 256-image step)
+        rc = points_wait(p, stream);
+        if (rc != KBN_OK) return rc;
         const int64_t k0 = (b0 * C + c0) * p->M;
         const KbnGatherArgs gy = t2_gather_args(p, npair, ncc, 1, 0, bufB, k0, y, nullptr, nullptr, nullptr, 0);
         KBN_LAUNCH(KBN_CLASS_GATHER, kbn_launch_gather(geom, gy, 0, stream), "gather");
