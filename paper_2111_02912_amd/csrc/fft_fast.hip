@@ -275,6 +275,57 @@ __device__ __forceinline__ int64_t col_map(const KbnMidPassArgs &a, int64_t o, i
     return o;
 }
 
+// Inputs of the E register elements of one column line at the stage-0
+// positions.  HALF (forward passes whose input is an image axis zero-padded
+// to twice its length, K = 2N as on the sigma = 2 grids, with a stage-0
+// radix divisible by 4): the element index alone says which positions hold
+// image rows, so the others are zero without an address, a test or a load
+// (half the elements) and the row offset is a constant.  DER && der: each
+// row r is scaled by r - nin / 2 (the derived r^[0] channel).
+template <class F, bool HALF, bool DER>
+__device__ __forceinline__ void col_load(const KbnMidPassArgs &a, const float2 *in, int u, bool col_ok, bool der,
+                                         float2 (&w)[F::E]) {
+    constexpr int L = F::L, E = F::E;
+    if constexpr (HALF) {
+        constexpr int R0 = F::template R<0>();
+        static_assert(R0 % 4 == 0, "HALF needs a stage-0 radix divisible by 4");
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int q = i % R0;
+            if (q < R0 / 4 || q >= 3 * R0 / 4) {
+                const int p = F::template in_pos<0>(u, i);
+                const int r = q < R0 / 4 ? p + L / 4 : p - 3 * L / 4;
+                w[i] = col_ok ? in[(int64_t)r * a.inner] : make_float2(0.f, 0.f);
+                if (DER && der) {
+                    const float f = (float)(r - L / 4);
+                    w[i] = make_float2(w[i].x * f, w[i].y * f);
+                }
+            } else {
+                w[i] = make_float2(0.f, 0.f);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int p = F::template in_pos<0>(u, i);
+            const int r = a.pad_in ? pos_to_img<L>(p, a.nin) : p;
+            w[i] = (col_ok && r >= 0) ? in[(int64_t)r * a.inner] : make_float2(0.f, 0.f);
+            if (DER && der) {
+                const float f = (float)(r - a.nin / 2);
+                w[i] = make_float2(w[i].x * f, w[i].y * f);
+            }
+        }
+    }
+}
+
+// the HALF load applies to a forward pass of length L (stage-0 radix
+// divisible by 4; an inverse pass cropping its output the same way measured
+// slower, 0.190 -> 0.205 ms on the 256-image step)
+template <int L, int E>
+constexpr bool half_ok() {
+    return Fft<L, E, false>::template R<0>() % 4 == 0;
+}
+
 // ---- strided pass along a non-last axis -------------------------------------
 // lines = LINES adjacent columns; LDS layout [position][column] (column fastest).
 // k_cols transforms one column tile per workgroup.  k_cols_pf walks over
@@ -283,9 +334,10 @@ __device__ __forceinline__ int64_t col_map(const KbnMidPassArgs &a, int64_t o, i
 // overlap the LDS stages of the previous (the grid holds only as many
 // workgroups as fit on the device at once); it needs about twice the
 // registers, so it is used only where it measured faster.
-template <int L, int E, bool INV, int NT, bool DER = false>
+template <int L, int E, bool INV, int NT, bool DER = false, bool HALF = false>
 __global__ void __launch_bounds__(NT) k_cols(KbnMidPassArgs a, const float2 *__restrict__ tw) {
     using F = Fft<L, E, INV>;
+    static_assert(!(INV && (DER || HALF)), "derived channels and the HALF load are forward forms");
     static_assert(NT % F::TL == 0, "a workgroup holds whole lines");
     constexpr int LINES = NT / F::TL;
     extern __shared__ float2 lds[];  // [L][LINES], dynamic (may exceed 64 KiB)
@@ -301,16 +353,7 @@ __global__ void __launch_bounds__(NT) k_cols(KbnMidPassArgs a, const float2 *__r
     const float2 *in = a.in + (oi * a.nin) * (int64_t)a.inner + c0 + l;
     float2 *out = a.out + (oo * a.nout) * (int64_t)a.inner + c0 + l;
     float2 v[E];
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-        const int p = F::template in_pos<0>(u, i);
-        const int r = a.pad_in ? pos_to_img<L>(p, a.nin) : p;
-        v[i] = (col_ok && r >= 0) ? in[(int64_t)r * a.inner] : make_float2(0.f, 0.f);
-        if (DER && der) {
-            const float f = (float)(r - a.nin / 2);
-            v[i] = make_float2(v[i].x * f, v[i].y * f);
-        }
-    }
+    col_load<F, HALF, DER>(a, in, u, col_ok, der, v);
     auto lds_idx = [](int pos) { return pos * LINES; };
     float2 *ldsl = lds + l;
     auto sink = [&](int, int pos, float2 val) {
@@ -355,9 +398,10 @@ __device__ __forceinline__ void der_tile(const KbnMidPassArgs &a, int t, int G, 
     c0 = ct * lines;
 }
 
-template <int L, int E, bool INV, int NT, bool DER = false>
+template <int L, int E, bool INV, int NT, bool DER = false, bool HALF = false>
 __global__ void __launch_bounds__(NT) k_cols_pf(KbnMidPassArgs a, const float2 *__restrict__ tw) {
     using F = Fft<L, E, INV>;
+    static_assert(!(INV && (DER || HALF)), "derived channels and the HALF load are forward forms");
     static_assert(NT % F::TL == 0, "a workgroup holds whole lines");
     constexpr int LINES = NT / F::TL;
     extern __shared__ float2 lds[];  // [L][LINES], dynamic
@@ -384,16 +428,7 @@ __global__ void __launch_bounds__(NT) k_cols_pf(KbnMidPassArgs a, const float2 *
     auto load = [&](int64_t oi, int c0, bool der, float2 (&w)[E]) {
         const bool col_ok = c0 + l < a.inner;
         const float2 *in = a.in + (oi * a.nin) * (int64_t)a.inner + c0 + l;
-#pragma unroll
-        for (int i = 0; i < E; ++i) {
-            const int p = F::template in_pos<0>(u, i);
-            const int r = a.pad_in ? pos_to_img<L>(p, a.nin) : p;
-            w[i] = (col_ok && r >= 0) ? in[(int64_t)r * a.inner] : make_float2(0.f, 0.f);
-            if (DER && der) {
-                const float f = rweight(i);
-                w[i] = make_float2(w[i].x * f, w[i].y * f);
-            }
-        }
+        col_load<F, HALF, DER>(a, in, u, col_ok, der, w);
     };
     float2 nv[E];
     int64_t t = blockIdx.x;
@@ -700,56 +735,64 @@ hipError_t allow_lds(K kernel, size_t bytes) {
     return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// one forward column-pass launch (the persistent form where col_pf(L))
+template <int L, bool DER, bool HALF>
+hipError_t launch_cols_fwd(const KbnMidPassArgs &a, const float2 *tw, int64_t total, hipStream_t s) {
+    constexpr int E = col_e(L);
+    constexpr int NT = col_nt(L);
+    constexpr size_t LDS = sizeof(float2) * L * (NT / (L / E));
+    if constexpr (col_pf(L)) {
+        static const hipError_t ok = allow_lds(k_cols_pf<L, E, false, NT, DER, HALF>, LDS);
+        if (ok != hipSuccess) return ok;
+        static const int64_t cap = resident_blocks(k_cols_pf<L, E, false, NT, DER, HALF>, NT, LDS);
+        k_cols_pf<L, E, false, NT, DER, HALF><<<dim3((unsigned)std::min<int64_t>(total, cap)), dim3(NT), LDS, s>>>(a, tw);
+    } else {
+        static const hipError_t ok = allow_lds(k_cols<L, E, false, NT, DER, HALF>, LDS);
+        if (ok != hipSuccess) return ok;
+        k_cols<L, E, false, NT, DER, HALF><<<dim3((unsigned)total), dim3(NT), LDS, s>>>(a, tw);
+    }
+    return hipGetLastError();
+}
+
+// one inverse column-pass launch
+template <int L>
+hipError_t launch_cols_inv(const KbnMidPassArgs &a, const float2 *tw, int64_t total, hipStream_t s) {
+    constexpr int E = col_e(L);
+    constexpr int NT = col_nt(L);
+    constexpr size_t LDS = sizeof(float2) * L * (NT / (L / E));
+    if constexpr (col_pf(L)) {
+        static const hipError_t ok = allow_lds(k_cols_pf<L, E, true, NT>, LDS);
+        if (ok != hipSuccess) return ok;
+        static const int64_t cap = resident_blocks(k_cols_pf<L, E, true, NT>, NT, LDS);
+        k_cols_pf<L, E, true, NT><<<dim3((unsigned)std::min<int64_t>(total, cap)), dim3(NT), LDS, s>>>(a, tw);
+    } else {
+        static const hipError_t ok = allow_lds(k_cols<L, E, true, NT>, LDS);
+        if (ok != hipSuccess) return ok;
+        k_cols<L, E, true, NT><<<dim3((unsigned)total), dim3(NT), LDS, s>>>(a, tw);
+    }
+    return hipGetLastError();
+}
+
 template <int L>
 hipError_t launch_cols(const KbnMidPassArgs &a, const float2 *tw, int inverse, hipStream_t s) {
     constexpr int E = col_e(L);
     constexpr int NT = col_nt(L);
     constexpr int LINES = NT / (L / E);
-    constexpr size_t LDS = sizeof(float2) * L * LINES;
     const int64_t ntile = (a.inner + LINES - 1) / LINES;
     const int64_t total = a.outer * ntile;
     if (total <= 0) return hipSuccess;
     const bool der = a.dsplit > 0;
     if (der && (inverse || !a.pad_in || a.dnw < 2 || a.outer != a.dsplit * (a.dnw + 1) || total > INT_MAX / 2))
         return hipErrorInvalidValue;
-    if constexpr (col_pf(L)) {
-        static const hipError_t ok = [] {
-            const hipError_t e = allow_lds(k_cols_pf<L, E, false, NT>, LDS);
-            return e != hipSuccess ? e : allow_lds(k_cols_pf<L, E, true, NT>, LDS);
-        }();
-        if (ok != hipSuccess) return ok;
-        static const int64_t cap_fwd = resident_blocks(k_cols_pf<L, E, false, NT>, NT, LDS);
-        static const int64_t cap_inv = resident_blocks(k_cols_pf<L, E, true, NT>, NT, LDS);
-        if (der) {
-            static const hipError_t ok_der = allow_lds(k_cols_pf<L, E, false, NT, true>, LDS);
-            if (ok_der != hipSuccess) return ok_der;
-            static const int64_t cap_der = resident_blocks(k_cols_pf<L, E, false, NT, true>, NT, LDS);
-            const dim3 grid((unsigned)std::min<int64_t>(total, cap_der));
-            k_cols_pf<L, E, false, NT, true><<<grid, dim3(NT), LDS, s>>>(a, tw);
-            return hipGetLastError();
+    if (!inverse) {
+        if constexpr (half_ok<L, E>()) {
+            if (a.pad_in && 2 * a.nin == L)
+                return der ? launch_cols_fwd<L, true, true>(a, tw, total, s)
+                           : launch_cols_fwd<L, false, true>(a, tw, total, s);
         }
-        const dim3 grid((unsigned)std::min<int64_t>(total, inverse ? cap_inv : cap_fwd));
-        if (inverse)
-            k_cols_pf<L, E, true, NT><<<grid, dim3(NT), LDS, s>>>(a, tw);
-        else
-            k_cols_pf<L, E, false, NT><<<grid, dim3(NT), LDS, s>>>(a, tw);
-    } else {
-        static const hipError_t ok = [] {
-            const hipError_t e = allow_lds(k_cols<L, E, false, NT>, LDS);
-            return e != hipSuccess ? e : allow_lds(k_cols<L, E, true, NT>, LDS);
-        }();
-        if (ok != hipSuccess) return ok;
-        const dim3 grid((unsigned)total);
-        if (der) {
-            static const hipError_t ok_der = allow_lds(k_cols<L, E, false, NT, true>, LDS);
-            if (ok_der != hipSuccess) return ok_der;
-            k_cols<L, E, false, NT, true><<<grid, dim3(NT), LDS, s>>>(a, tw);
-        } else if (inverse)
-            k_cols<L, E, true, NT><<<grid, dim3(NT), LDS, s>>>(a, tw);
-        else
-            k_cols<L, E, false, NT><<<grid, dim3(NT), LDS, s>>>(a, tw);
+        return der ? launch_cols_fwd<L, true, false>(a, tw, total, s) : launch_cols_fwd<L, false, false>(a, tw, total, s);
     }
-    return hipGetLastError();
+    return launch_cols_inv<L>(a, tw, total, s);
 }
 
 template <int L>
